@@ -1,0 +1,162 @@
+"""FP64 CPU oracle for the all-pairs Lipschitz bound evaluation.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg are the only callers.  The product library never imports,
+links or runs anything here, and nothing here imports the product.
+
+The arithmetic lives in ``lipfit_oracle.c`` (plain C, double precision,
+OpenMP over queries/rows), written from the paper's definitions:
+  * bounds / interpolant:   Eq. (2), Eq. (3), directional distance Eq. (4)
+  * consistency check:      the Lipschitz condition of Sec. 1 in the pairwise
+                            form of Eqs. (5)-(6) with zero corrections
+  * global constant:        Sec. 5 (``lipschitz_constant``), max pairwise slope
+  * per-point constants:    Sec. 4.3, scalar form over the 16 nearest data
+  * subgradients:           chain rule through the selected data points
+This module only marshals numpy arrays into that library.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lipfit_oracle.c")
+_LIB = os.path.join(_HERE, "liblipfit_oracle.so")
+
+L1, L2, LINF = 1, 2, 3
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (no fast-math, no FP contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
+               "-shared", "-std=c99", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i32, i64, f64 = ctypes.c_int, ctypes.c_long, ctypes.c_double
+        lib.orc_num_threads.restype = i32
+        lib.orc_bounds.argtypes = [i32, i32, P, P, P, P, i64, f64, P, P, i64, P, P, P, P, P]
+        lib.orc_bounds.restype = None
+        lib.orc_consistency.argtypes = [i32, i32, P, P, P, P, i64, f64, P, f64, P, i64,
+                                        P, P, P, P, P, P]
+        lib.orc_consistency.restype = None
+        lib.orc_estimate_M_global.argtypes = [i32, i32, P, P, P, i64, P, P]
+        lib.orc_estimate_M_global.restype = i32
+        lib.orc_estimate_M_knn.argtypes = [i32, i32, P, P, P, i64, i32, P, i64, P, P]
+        lib.orc_estimate_M_knn.restype = i32
+        lib.orc_grad.argtypes = [i32, i32, P, P, P, P, i64, f64, P, P, i64, P, P, P, P, P,
+                                 P, P, P]
+        lib.orc_grad.restype = None
+        _lib = lib
+    return _lib
+
+
+def num_threads() -> int:
+    return int(_load().orc_num_threads())
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f32(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _common(x, y, w, mon, d):
+    x = _f32(x)
+    y = _f32(y)
+    assert x.ndim == 2 and x.shape[1] == d and y.shape == (x.shape[0],)
+    w = np.ones(d, np.float64) if w is None else np.ascontiguousarray(w, np.float64)
+    mon = None if mon is None else np.ascontiguousarray(mon, np.int8)
+    return x, y, w, mon
+
+
+def bounds(x, y, xq, norm: int, M: float = 0.0, Mk=None, mon=None, w=None):
+    """H_up, H_lo, g (float64) and arg_up, arg_lo (int64) for every query."""
+    d = int(np.shape(x)[1])
+    x, y, w, mon = _common(x, y, w, mon, d)
+    xq = _f32(xq).reshape(-1, d)
+    Mk = None if Mk is None else _f32(Mk)
+    q = xq.shape[0]
+    hu, hl, g = (np.empty(q, np.float64) for _ in range(3))
+    au, al = np.empty(q, np.int64), np.empty(q, np.int64)
+    _load().orc_bounds(d, norm, _p(w), _p(mon), _p(x), _p(y), x.shape[0], float(M), _p(Mk),
+                       _p(xq), q, _p(hu), _p(hl), _p(g), _p(au), _p(al))
+    return hu, hl, g, au, al
+
+
+def consistency(x, y, norm: int, M: float = 0.0, Mk=None, mon=None, w=None, tol: float = 0.0,
+                rows: Optional[Sequence[int]] = None):
+    """Per-row slacks, partners and violation counts (see lipfit_oracle.c)."""
+    d = int(np.shape(x)[1])
+    x, y, w, mon = _common(x, y, w, mon, d)
+    Mk = None if Mk is None else _f32(Mk)
+    rows_a = None if rows is None else np.ascontiguousarray(rows, np.int64)
+    nr = x.shape[0] if rows_a is None else rows_a.shape[0]
+    su, sl = np.empty(nr, np.float64), np.empty(nr, np.float64)
+    pu, pl, vu, vl = (np.empty(nr, np.int64) for _ in range(4))
+    _load().orc_consistency(d, norm, _p(w), _p(mon), _p(x), _p(y), x.shape[0], float(M), _p(Mk),
+                            float(tol), _p(rows_a), nr, _p(su), _p(sl), _p(pu), _p(pl),
+                            _p(vu), _p(vl))
+    return dict(slack_up=su, slack_lo=sl, partner_up=pu, partner_lo=pl, viol_up=vu, viol_lo=vl)
+
+
+def estimate_M_global(x, y, norm: int, w=None):
+    """(status, M, (i, k)): max pairwise slope with the symmetric distance."""
+    d = int(np.shape(x)[1])
+    x, y, w, _ = _common(x, y, w, None, d)
+    M = np.zeros(1, np.float64)
+    pair = np.full(2, -1, np.int64)
+    st = _load().orc_estimate_M_global(d, norm, _p(w), _p(x), _p(y), x.shape[0], _p(M), _p(pair))
+    return int(st), float(M[0]), (int(pair[0]), int(pair[1]))
+
+
+def estimate_M_knn(x, y, norm: int, K: int = 16, w=None, rows: Optional[Sequence[int]] = None):
+    """(status, M_i[float64], neighbours[rows, K]) for the requested rows."""
+    d = int(np.shape(x)[1])
+    x, y, w, _ = _common(x, y, w, None, d)
+    rows_a = None if rows is None else np.ascontiguousarray(rows, np.int64)
+    nr = x.shape[0] if rows_a is None else rows_a.shape[0]
+    M = np.empty(nr, np.float64)
+    nbr = np.empty((nr, K), np.int64)
+    st = _load().orc_estimate_M_knn(d, norm, _p(w), _p(x), _p(y), x.shape[0], int(K),
+                                    _p(rows_a), nr, _p(M), _p(nbr))
+    return int(st), M, nbr
+
+
+def grad(x, y, xq, norm: int, arg_up, arg_lo, dg=None, dh_up=None, dh_lo=None,
+         M: float = 0.0, Mk=None, mon=None, w=None):
+    """(dxq[q, d], dy[n], dM[1] or [n]) in float64 at the given indices."""
+    d = int(np.shape(x)[1])
+    x, y, w, mon = _common(x, y, w, mon, d)
+    xq = _f32(xq).reshape(-1, d)
+    Mk = None if Mk is None else _f32(Mk)
+    n, q = x.shape[0], xq.shape[0]
+    au = np.ascontiguousarray(arg_up, np.int64)
+    al = np.ascontiguousarray(arg_lo, np.int64)
+    f64 = lambda a: None if a is None else np.ascontiguousarray(a, np.float64)
+    dg, dh_up, dh_lo = f64(dg), f64(dh_up), f64(dh_lo)
+    dxq = np.zeros((q, d), np.float64)
+    dy = np.zeros(n, np.float64)
+    dM = np.zeros(n if Mk is not None else 1, np.float64)
+    _load().orc_grad(d, norm, _p(w), _p(mon), _p(x), _p(y), n, float(M), _p(Mk), _p(xq), q,
+                     _p(au), _p(al), _p(dg), _p(dh_up), _p(dh_lo), _p(dxq), _p(dy), _p(dM))
+    return dxq, dy, dM

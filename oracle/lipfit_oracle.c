@@ -1,0 +1,390 @@
+/*
+ * Plain FP64 CPU oracle for the all-pairs Lipschitz bound evaluation.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg load this library.  It shares no code, header
+ * or constant with the GPU library: it is written straight from the paper's
+ * definitions, in double precision, with no blocking, tiling or pruning.
+ * Inputs are the same float32 arrays the GPU reads, widened to double.
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC (see build.py).
+ *
+ * Notation (paper, Sec. 1 and 3): data x^k in R^d, values y^k, k = 0..n-1
+ * (0-based here), query point x, Lipschitz constant M (global) or M_k
+ * (per datum, Sec. 4.3 applied with a scalar per datum), distance dist.
+ *
+ * Readings of points the paper leaves open (each also listed in the design
+ * notes):
+ *  - Eq. (4) gives one directional distance ||(x - x^k)_+||.  It is used for
+ *    the upper bound; the lower bound uses ||(x^k - x)_+||, the mirror image
+ *    (f(x) <= f(max(x, x^k)) <= y^k + M||(x - x^k)_+|| and
+ *    f(x) >= f(min(x, x^k)) >= y^k - M||(x^k - x)_+|| for increasing f).
+ *  - Monotone-decreasing coordinates swap the two.  Unconstrained
+ *    coordinates contribute |x_i - x^k_i| to both.  The norm is taken of the
+ *    whole per-coordinate component vector, weighted: ||w (.) c||_p,
+ *    p in {1, 2, inf}.
+ *  - Ties in min/max go to the lowest index k (strict < and > scans from 0).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+enum { ORC_L1 = 1, ORC_L2 = 2, ORC_LINF = 3 };
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* Per-coordinate components of the directional distances between the point a
+ * (the one being evaluated) and the datum b: delta = a_i - b_i.
+ *   mon_i =  0: c_up = c_lo = |delta|
+ *   mon_i = +1: c_up = (delta)_+,  c_lo = (-delta)_+      (Eq. 4 and mirror)
+ *   mon_i = -1: c_up = (-delta)_+, c_lo = (delta)_+
+ * mon == NULL means all coordinates unconstrained. */
+static void components(int i, double delta, const signed char *mon, double *cu, double *cl)
+{
+    int m = mon ? mon[i] : 0;
+    if (m == 0) {
+        *cu = fabs(delta);
+        *cl = *cu;
+    } else if (m > 0) {
+        *cu = delta > 0.0 ? delta : 0.0;
+        *cl = delta < 0.0 ? -delta : 0.0;
+    } else {
+        *cu = delta < 0.0 ? -delta : 0.0;
+        *cl = delta > 0.0 ? delta : 0.0;
+    }
+}
+
+/* dist(a, b) for the upper and the lower bound (Eq. 2 with Eq. 4).  For l2,
+ * *su_sq / *sl_sq (if not NULL) receive the sums of squares before the root.
+ * Coordinates are accumulated in index order starting from 0.0. */
+static void dist_pair(int d, int norm, const double *w, const signed char *mon,
+                      const float *a, const float *b, double *dup, double *dlo,
+                      double *su_sq, double *sl_sq)
+{
+    double su = 0.0, sl = 0.0;
+    for (int i = 0; i < d; ++i) {
+        double delta = (double)a[i] - (double)b[i];
+        double cu, cl;
+        components(i, delta, mon, &cu, &cl);
+        cu = w[i] * cu;
+        cl = w[i] * cl;
+        if (norm == ORC_L1) {
+            su = su + cu;
+            sl = sl + cl;
+        } else if (norm == ORC_L2) {
+            su = su + cu * cu;
+            sl = sl + cl * cl;
+        } else {
+            if (cu > su) su = cu;
+            if (cl > sl) sl = cl;
+        }
+    }
+    if (su_sq) *su_sq = su;
+    if (sl_sq) *sl_sq = sl;
+    if (norm == ORC_L2) {
+        su = sqrt(su);
+        sl = sqrt(sl);
+    }
+    *dup = su;
+    *dlo = sl;
+}
+
+static double m_of(const float *Mk, double M, long k) { return Mk ? (double)Mk[k] : M; }
+
+/* Eq. (2) and Eq. (3): for every query x,
+ *   H_up(x) = min_k (y^k + M_k dist_up(x, x^k)),  H_lo(x) = max_k (y^k - M_k dist_lo(x, x^k)),
+ *   g(x) = (H_up(x) + H_lo(x)) / 2,
+ * with the lowest index among exact ties.  Any output pointer may be NULL. */
+void orc_bounds(int d, int norm, const double *w, const signed char *mon,
+                const float *x, const float *y, long n, double M, const float *Mk,
+                const float *xq, long q,
+                double *h_up, double *h_lo, double *g, long *arg_up, long *arg_lo)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long j = 0; j < q; ++j) {
+        const float *xj = xq + j * (long)d;
+        double best_u = INFINITY, best_l = -INFINITY;
+        long au = -1, al = -1;
+        for (long k = 0; k < n; ++k) {
+            double du, dl;
+            dist_pair(d, norm, w, mon, xj, x + k * (long)d, &du, &dl, NULL, NULL);
+            double mk = m_of(Mk, M, k);
+            double u = (double)y[k] + mk * du;
+            double l = (double)y[k] - mk * dl;
+            if (u < best_u) { best_u = u; au = k; }
+            if (l > best_l) { best_l = l; al = k; }
+        }
+        if (h_up) h_up[j] = best_u;
+        if (h_lo) h_lo[j] = best_l;
+        if (g) g[j] = 0.5 * (best_u + best_l);
+        if (arg_up) arg_up[j] = au;
+        if (arg_lo) arg_lo[j] = al;
+    }
+}
+
+/* Data-side consistency check: whether the data can be interpolated by a
+ * function with Lipschitz constant M (Sec. 1, the Lipschitz condition
+ * |f(x) - f(z)| <= M d(x, z)) that also respects the monotonicity constraints
+ * (Sec. 4.1), in the pairwise form of Eqs. (5)-(6) with eps = 0.
+ * For each requested row i (all rows when rows == NULL), over k != i:
+ *   t_up(i,k) = (y_k + M_k dist_up(x^i, x^k)) - y_i    (>= 0 when consistent)
+ *   t_lo(i,k) = y_i - (y_k - M_k dist_lo(x^i, x^k))    (>= 0 when consistent)
+ * slack_up[r] = min_k t_up, slack_lo[r] = min_k t_lo (lowest k on ties),
+ * viol_up[r] / viol_lo[r] = number of k with t < -tol.
+ * Equality |y_i - y_k| = M d is consistent (the condition is "<=").
+ * With n == 1 the slacks are +inf and the partners -1. */
+void orc_consistency(int d, int norm, const double *w, const signed char *mon,
+                     const float *x, const float *y, long n, double M, const float *Mk,
+                     double tol, const long *rows, long n_rows,
+                     double *slack_up, double *slack_lo, long *partner_up, long *partner_lo,
+                     long *viol_up, long *viol_lo)
+{
+    if (!rows) n_rows = n;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (long r = 0; r < n_rows; ++r) {
+        long i = rows ? rows[r] : r;
+        const float *xi = x + i * (long)d;
+        double yi = (double)y[i];
+        double su = INFINITY, sl = INFINITY;
+        long pu = -1, pl = -1, cu = 0, cl = 0;
+        for (long k = 0; k < n; ++k) {
+            if (k == i) continue;
+            double du, dl;
+            dist_pair(d, norm, w, mon, xi, x + k * (long)d, &du, &dl, NULL, NULL);
+            double mk = m_of(Mk, M, k);
+            double tu = ((double)y[k] + mk * du) - yi;
+            double tl = yi - ((double)y[k] - mk * dl);
+            if (tu < su) { su = tu; pu = k; }
+            if (tl < sl) { sl = tl; pl = k; }
+            if (tu < -tol) ++cu;
+            if (tl < -tol) ++cl;
+        }
+        if (slack_up) slack_up[r] = su;
+        if (slack_lo) slack_lo[r] = sl;
+        if (partner_up) partner_up[r] = pu;
+        if (partner_lo) partner_lo[r] = pl;
+        if (viol_up) viol_up[r] = cu;
+        if (viol_lo) viol_lo[r] = cl;
+    }
+}
+
+/* Global Lipschitz constant from the data (Sec. 5, lipschitz_constant):
+ *   M = max over pairs i < k of |y_i - y_k| / dist(x^i, x^k),
+ * with the symmetric distance (monotonicity ignored).  Pairs at distance 0
+ * with equal y are skipped.  Returns 0, or 3 when two coincident points carry
+ * different values (infinite slope; that pair is reported).  The maximising
+ * pair is the lexicographically lowest (i, k) among exact ties; with no
+ * usable pair M = 0 and pair = (-1, -1). */
+int orc_estimate_M_global(int d, int norm, const double *w, const float *x, const float *y,
+                          long n, double *M_out, long *pair)
+{
+    double *row_best = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    long *row_arg = (long *)malloc(sizeof(long) * (size_t)(n > 0 ? n : 1));
+    long *row_dup = (long *)malloc(sizeof(long) * (size_t)(n > 0 ? n : 1));
+#pragma omp parallel for schedule(dynamic, 8)
+    for (long i = 0; i < n; ++i) {
+        double best = -1.0;
+        long arg = -1, dup = -1;
+        for (long k = i + 1; k < n; ++k) {
+            double du, dl;
+            dist_pair(d, norm, w, NULL, x + i * (long)d, x + k * (long)d, &du, &dl, NULL, NULL);
+            double dy = fabs((double)y[i] - (double)y[k]);
+            if (du == 0.0) {
+                if (dy != 0.0 && dup < 0) dup = k;
+                continue;
+            }
+            double r = dy / du;
+            if (r > best) { best = r; arg = k; }
+        }
+        row_best[i] = best;
+        row_arg[i] = arg;
+        row_dup[i] = dup;
+    }
+    int status = 0;
+    double best = -1.0;
+    pair[0] = -1;
+    pair[1] = -1;
+    for (long i = 0; i < n; ++i) {
+        if (row_dup[i] >= 0) {
+            status = 3;
+            pair[0] = i;
+            pair[1] = row_dup[i];
+            break;
+        }
+        if (row_arg[i] >= 0 && row_best[i] > best) {
+            best = row_best[i];
+            pair[0] = i;
+            pair[1] = row_arg[i];
+        }
+    }
+    *M_out = status ? INFINITY : (best < 0.0 ? 0.0 : best);
+    free(row_best);
+    free(row_arg);
+    free(row_dup);
+    return status;
+}
+
+typedef struct { double key; long j; } keyed;
+
+static int keyed_cmp(const void *pa, const void *pb)
+{
+    const keyed *a = (const keyed *)pa, *b = (const keyed *)pb;
+    if (a->key < b->key) return -1;
+    if (a->key > b->key) return 1;
+    return (a->j > b->j) - (a->j < b->j);
+}
+
+/* Per-point Lipschitz constant from the K nearest data (the scalar form of
+ * Sec. 4.3: M_i = max over the K nearest j != i of |y_i - y_j| / dist(x^i, x^j)).
+ * Nearness uses the symmetric distance (monotonicity ignored); for l2 the
+ * points are ranked by the sum of squares, which orders them like the
+ * distance.  Ties rank the lower j first.  The ranking is a full sort of all
+ * j != i.  Coincident neighbours with equal y are skipped; with different y
+ * the function returns 3 and M_out[r] = +inf for that row.  nbr (if not
+ * NULL) receives the K neighbour indices of each row in rank order (-1 when
+ * n - 1 < K). */
+int orc_estimate_M_knn(int d, int norm, const double *w, const float *x, const float *y,
+                       long n, int K, const long *rows, long n_rows, double *M_out, long *nbr)
+{
+    if (!rows) n_rows = n;
+    int status = 0;
+#pragma omp parallel
+    {
+        keyed *buf = (keyed *)malloc(sizeof(keyed) * (size_t)(n > 1 ? n : 1));
+#pragma omp for schedule(dynamic, 4) reduction(max : status)
+        for (long r = 0; r < n_rows; ++r) {
+            long i = rows ? rows[r] : r;
+            long m = 0;
+            for (long j = 0; j < n; ++j) {
+                if (j == i) continue;
+                double du, dl, sq, sq2;
+                dist_pair(d, norm, w, NULL, x + i * (long)d, x + j * (long)d, &du, &dl, &sq, &sq2);
+                buf[m].key = (norm == ORC_L2) ? sq : du;
+                buf[m].j = j;
+                ++m;
+            }
+            qsort(buf, (size_t)m, sizeof(keyed), keyed_cmp);
+            long kk = m < K ? m : K;
+            double best = 0.0;
+            for (long t = 0; t < kk; ++t) {
+                long j = buf[t].j;
+                double du, dl;
+                dist_pair(d, norm, w, NULL, x + i * (long)d, x + j * (long)d, &du, &dl, NULL, NULL);
+                double dy = fabs((double)y[i] - (double)y[j]);
+                if (du == 0.0) {
+                    if (dy != 0.0) { best = INFINITY; status = 3; }
+                    continue;
+                }
+                double s = dy / du;
+                if (s > best) best = s;
+            }
+            M_out[r] = best;
+            if (nbr) {
+                for (long t = 0; t < K; ++t) nbr[r * (long)K + t] = t < kk ? buf[t].j : -1;
+            }
+        }
+        free(buf);
+    }
+    return status;
+}
+
+/* Derivative of the component c_i with respect to delta_i = a_i - b_i, for the
+ * upper (up = 1) or the lower (up = 0) distance.  Kinks take 0:
+ * |.|'(0) = 0 and (.)_+'(0) = 0. */
+static double dcomp(int i, double delta, const signed char *mon, int up)
+{
+    int m = mon ? mon[i] : 0;
+    if (m == 0) return delta > 0.0 ? 1.0 : (delta < 0.0 ? -1.0 : 0.0);
+    int pos = (m > 0) == (up != 0); /* component is (delta)_+ when pos, else (-delta)_+ */
+    if (pos) return delta > 0.0 ? 1.0 : 0.0;
+    return delta < 0.0 ? -1.0 : 0.0;
+}
+
+/* Gradient of dist_up (up = 1) or dist_lo (up = 0) with respect to the first
+ * argument a.  l2 at distance 0 gives 0; linf takes the lowest coordinate
+ * among the maximal weighted components. */
+static void dist_grad(int d, int norm, const double *w, const signed char *mon,
+                      const float *a, const float *b, int up, double dist, double *out)
+{
+    double cmax = -1.0;
+    int jmax = -1;
+    for (int i = 0; i < d; ++i) {
+        double delta = (double)a[i] - (double)b[i];
+        double cu, cl;
+        components(i, delta, mon, &cu, &cl);
+        double c = w[i] * (up ? cu : cl);
+        double dc = w[i] * dcomp(i, delta, mon, up);
+        if (norm == ORC_L1) {
+            out[i] = dc;
+        } else if (norm == ORC_L2) {
+            out[i] = dist > 0.0 ? c * dc / dist : 0.0;
+        } else {
+            out[i] = 0.0;
+            if (c > cmax) { cmax = c; jmax = i; }
+        }
+    }
+    if (norm == ORC_LINF && jmax >= 0) {
+        double delta = (double)a[jmax] - (double)b[jmax];
+        out[jmax] = w[jmax] * dcomp(jmax, delta, mon, up);
+    }
+}
+
+/* Subgradients of g (and optionally of H_up, H_lo) through the selected data
+ * points a = arg_up[j], b = arg_lo[j]:
+ *   H_up = y_a + M_a dist_up(x, x^a),  H_lo = y_b - M_b dist_lo(x, x^b),  g = (H_up + H_lo)/2.
+ * With G_up = dg/2 + dh_up and G_lo = dg/2 + dh_lo (missing arrays count 0):
+ *   dxq[j]  = G_up M_a grad dist_up - G_lo M_b grad dist_lo
+ *   dy[a]  += G_up,  dy[b] += G_lo
+ *   dM     += G_up dist_up - G_lo dist_lo            (global M, dM[0])
+ *   dM[a]  += G_up dist_up,  dM[b] -= G_lo dist_lo   (per-point M_k)
+ * dy and dM are accumulated in query order; dxq is overwritten. */
+void orc_grad(int d, int norm, const double *w, const signed char *mon,
+              const float *x, const float *y, long n, double M, const float *Mk,
+              const float *xq, long q, const long *arg_up, const long *arg_lo,
+              const double *dg, const double *dh_up, const double *dh_lo,
+              double *dxq, double *dy, double *dM)
+{
+    (void)y;
+    (void)n;
+    double *gu = (double *)malloc(sizeof(double) * (size_t)(d > 0 ? d : 1));
+    double *gl = (double *)malloc(sizeof(double) * (size_t)(d > 0 ? d : 1));
+    for (long j = 0; j < q; ++j) {
+        const float *xj = xq + j * (long)d;
+        long a = arg_up[j], b = arg_lo[j];
+        double Gu = (dg ? 0.5 * dg[j] : 0.0) + (dh_up ? dh_up[j] : 0.0);
+        double Gl = (dg ? 0.5 * dg[j] : 0.0) + (dh_lo ? dh_lo[j] : 0.0);
+        double du, dl_unused, du_unused, dl;
+        dist_pair(d, norm, w, mon, xj, x + a * (long)d, &du, &dl_unused, NULL, NULL);
+        dist_pair(d, norm, w, mon, xj, x + b * (long)d, &du_unused, &dl, NULL, NULL);
+        dist_grad(d, norm, w, mon, xj, x + a * (long)d, 1, du, gu);
+        dist_grad(d, norm, w, mon, xj, x + b * (long)d, 0, dl, gl);
+        double Ma = m_of(Mk, M, a), Mb = m_of(Mk, M, b);
+        if (dxq) {
+            for (int i = 0; i < d; ++i) dxq[j * (long)d + i] = Gu * Ma * gu[i] - Gl * Mb * gl[i];
+        }
+        if (dy) {
+            dy[a] += Gu;
+            dy[b] += Gl;
+        }
+        if (dM) {
+            if (Mk) {
+                dM[a] += Gu * du;
+                dM[b] -= Gl * dl;
+            } else {
+                dM[0] += Gu * du - Gl * dl;
+            }
+        }
+    }
+    free(gu);
+    free(gl);
+}
