@@ -1,0 +1,237 @@
+/*
+ * lipfit.h - C ABI of the MI355X (gfx950) library for Lipschitz-optimal
+ * scattered-data fitting: the all-pairs bound evaluation and its data-side
+ * passes.
+ *
+ * Problem (paper, Sec. 1 and 3): data x^k in R^d with values y^k,
+ * k = 0..n-1, a Lipschitz constant M (or one constant M_k per datum,
+ * Sec. 4.3), a distance dist, optional monotonicity per coordinate
+ * (Sec. 4.1), and query points x.  For every query
+ *     H_up(x) = min_k ( y^k + M_k dist_up(x, x^k) )          Eq. (2)
+ *     H_lo(x) = max_k ( y^k - M_k dist_lo(x, x^k) )          Eq. (2)
+ *     g(x)    = ( H_up(x) + H_lo(x) ) / 2                    Eq. (3)
+ * The distance is the weighted l1, l2 or linf norm of the per-coordinate
+ * component vector c: for an unconstrained coordinate c_i = |x_i - x^k_i|
+ * in both bounds; for an increasing coordinate the upper bound uses
+ * (x_i - x^k_i)_+ (Eq. 4) and the lower bound its mirror (x^k_i - x_i)_+;
+ * a decreasing coordinate swaps the two.  dist = || w (.) c ||_p.
+ *
+ * Conventions shared by every entry point
+ *  - Every array argument is a DEVICE pointer owned by the caller, except
+ *    the lip_metric fields w and mon, which are HOST arrays of length d.
+ *  - Matrices are row-major: x is [n][d], xq is [q][d], dxq is [q][d].
+ *  - Calls are asynchronous on `stream` (a hipStream_t; NULL = the null
+ *    stream).  Argument validation is synchronous and happens before any
+ *    device work: on an error status nothing has been enqueued and no HIP
+ *    call has been made.  LIP_E_DEVICE reports a failed launch.
+ *  - Output pointers documented as optional may be NULL to skip them.
+ *  - Indices are int32 (n < 2^31).  Ties in a min / max go to the lowest
+ *    index.  n == 0 is LIP_E_SHAPE; q == 0 is a successful no-op.
+ *  - Scratch memory comes from the caller's workspace `ws` of `ws_bytes`
+ *    bytes (at least lip_workspace_size(...)); no entry point allocates
+ *    device memory, except lip_plan_create and lip_autotune.
+ *  - NaN inputs give unspecified results unless LIP_FLAG_CHECK_FINITE is set,
+ *    which scans the inputs first (synchronously) and returns
+ *    LIP_E_NONFINITE.
+ */
+#ifndef LIPFIT_H
+#define LIPFIT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LIP_OK = 0,
+    LIP_E_ARG = 1,          /* NULL where required, bad enum, bad flag combination */
+    LIP_E_SHAPE = 2,        /* n == 0, d outside 1..LIP_MAX_DIM, sizes too large */
+    LIP_E_VALUE = 3,        /* M < 0, weight <= 0, mon outside {-1,0,1}, tol < 0 */
+    LIP_E_NONFINITE = 4,    /* NaN/Inf found by LIP_FLAG_CHECK_FINITE */
+    LIP_E_UNSUPPORTED = 5,  /* e.g. LIP_FLAG_BF16 with l1/linf or monotone coordinates */
+    LIP_E_WORKSPACE = 6,    /* ws is NULL or smaller than lip_workspace_size() */
+    LIP_E_DEVICE = 7        /* a HIP call or kernel launch failed */
+} lip_status;
+
+typedef enum { LIP_L1 = 1, LIP_L2 = 2, LIP_LINF = 3 } lip_norm;
+
+#define LIP_MAX_DIM 16
+#define LIP_MAX_KNN 32
+
+/* Flags (bitwise or). */
+#define LIP_FLAG_CHECK_FINITE  (1u << 0)
+/* l2 without monotone coordinates only: the cross term x . x^k in BF16 MFMA
+ * with FP32 accumulation, then every candidate within the proven error bound
+ * re-evaluated with the FP32 path's arithmetic, so the results (values and
+ * indices) are identical to the FP32 path. */
+#define LIP_FLAG_BF16          (1u << 1)
+/* Backward: accumulate dy / dM without floating-point atomics, so repeated
+ * calls give bitwise identical results. */
+#define LIP_FLAG_DETERMINISTIC (1u << 2)
+
+/* Distance definition (Sec. 3 "other distances", Sec. 4.1 monotonicity). */
+typedef struct {
+    int32_t d;            /* dimension, 1..LIP_MAX_DIM */
+    int32_t norm;         /* lip_norm */
+    const float *w;       /* HOST [d] weights > 0, or NULL for all ones */
+    const int8_t *mon;    /* HOST [d] in {-1, 0, +1}, or NULL for no constraints */
+} lip_metric;
+
+typedef void *lip_stream; /* hipStream_t */
+
+/* Bytes of workspace that lip_bounds / lip_fit_eval / lip_consistency /
+ * lip_estimate_M need for these sizes and flags (an upper bound; 0 is never
+ * returned). */
+size_t lip_workspace_size(int64_t n, int64_t q, int32_t d, uint32_t flags);
+
+/* Eq. (2): the upper and lower Lipschitz bounds at q query points and the
+ * data points that attain them.
+ *   x [n][d], y [n]       data set D (Sec. 1)
+ *   M                     global Lipschitz constant (>= 0, finite); ignored
+ *                         when Mk != NULL
+ *   Mk [n] or NULL        per-datum constants (Sec. 4.3, scalar per datum);
+ *                         each pair uses the datum's own M_k
+ *   xq [q][d]             query points
+ *   h_up, h_lo [q]        optional outputs (FP32)
+ *   arg_up, arg_lo [q]    optional outputs: attaining data index, lowest on ties
+ * Arithmetic is FP32 (FP32 with a BF16 cross term under LIP_FLAG_BF16, with
+ * identical results).  The forward is bitwise deterministic. */
+lip_status lip_bounds(const lip_metric *metric, const float *x, const float *y, int64_t n,
+                      float M, const float *Mk, const float *xq, int64_t q,
+                      float *h_up, float *h_lo, int32_t *arg_up, int32_t *arg_lo,
+                      void *ws, size_t ws_bytes, uint32_t flags, lip_stream stream);
+
+/* Eq. (3): the optimal interpolant g = (H_up + H_lo)/2 at the queries, plus
+ * the optional bound outputs of lip_bounds (all of g, h_up, h_lo, arg_up,
+ * arg_lo are optional).  Same arguments and rules as lip_bounds. */
+lip_status lip_fit_eval(const lip_metric *metric, const float *x, const float *y, int64_t n,
+                        float M, const float *Mk, const float *xq, int64_t q,
+                        float *g, float *h_up, float *h_lo, int32_t *arg_up, int32_t *arg_lo,
+                        void *ws, size_t ws_bytes, uint32_t flags, lip_stream stream);
+
+/* Subgradients of g (and of H_up, H_lo) through the indices a = arg_up[j],
+ * b = arg_lo[j] saved by the forward (the chain rule applied to Eq. 2-3):
+ *   G_up = dg/2 + dh_up,  G_lo = dg/2 + dh_lo    (missing arrays count 0)
+ *   dxq[j]  = G_up M_a grad_x dist_up(x, x^a) - G_lo M_b grad_x dist_lo(x, x^b)
+ *   dy[a]  += G_up,  dy[b] += G_lo
+ *   dM[0]  += G_up dist_up - G_lo dist_lo              (global M, Mk == NULL)
+ *   dM[a]  += G_up dist_up,  dM[b] -= G_lo dist_lo     (per-datum M_k)
+ * Kinks take the zero subgradient: |.|'(0) = 0, (.)_+'(0) = 0, grad l2 at
+ * distance 0 = 0; linf picks the lowest coordinate among the largest.
+ *   dg, dh_up, dh_lo [q]  upstream gradients, any may be NULL
+ *   dxq [q][d]            optional, overwritten
+ *   dy [n]                optional, ACCUMULATED (the caller zeroes it)
+ *   dM [1] or [n]         optional, ACCUMULATED
+ * Uses FP32 atomics for dy / dM unless LIP_FLAG_DETERMINISTIC, which takes
+ * ws (>= lip_workspace_size) and gives bitwise reproducible sums. */
+lip_status lip_fit_backward(const lip_metric *metric, const float *x, const float *y, int64_t n,
+                            float M, const float *Mk, const float *xq, int64_t q,
+                            const int32_t *arg_up, const int32_t *arg_lo,
+                            const float *dg, const float *dh_up, const float *dh_lo,
+                            float *dxq, float *dy, float *dM,
+                            void *ws, size_t ws_bytes, uint32_t flags, lip_stream stream);
+
+/* Data-side consistency check in FP64: can the data be interpolated by a
+ * function that satisfies the Lipschitz condition (Sec. 1) and the
+ * monotonicity constraints (Sec. 4.1)?  Pairwise form of Eqs. (5)-(6) with
+ * zero corrections; for each row i and every k != i:
+ *   t_up(i,k) = (y_k + M_k dist_up(x^i, x^k)) - y_i
+ *   t_lo(i,k) = y_i - (y_k - M_k dist_lo(x^i, x^k))
+ * all evaluated in double precision from the FP32 inputs, in this order,
+ * coordinates accumulated in index order, correctly rounded operations.
+ *   counts [2] (int64, required)  number of ordered pairs with t_up < -tol
+ *                                 and with t_lo < -tol (overwritten)
+ *   slack_up, slack_lo [n]        optional: min_k t_up, min_k t_lo (+inf if n == 1)
+ *   partner_up, partner_lo [n]    optional: the k attaining them (lowest on ties)
+ * Equality (|y_i - y_k| = M dist) is consistent.  Needs ws. */
+lip_status lip_consistency(const lip_metric *metric, const float *x, const float *y, int64_t n,
+                           float M, const float *Mk, double tol, int64_t *counts,
+                           double *slack_up, double *slack_lo,
+                           int32_t *partner_up, int32_t *partner_lo,
+                           void *ws, size_t ws_bytes, uint32_t flags, lip_stream stream);
+
+#define LIP_M_GLOBAL 0
+#define LIP_M_LOCAL_KNN 1
+
+/* Lipschitz constants estimated from the data, with the symmetric distance
+ * (monotonicity in metric->mon is ignored), in FP64 from the FP32 inputs.
+ * LIP_M_GLOBAL (Sec. 5, the max of |y_i - y_k| / dist(x^i, x^k) over all
+ * pairs; no distance matrix is stored):
+ *   M64 [1] optional, M32 [1] optional (M64 rounded up to FP32, so that the
+ *   data stay consistent with it), pair [2] optional (int64, lowest (i, k)
+ *   with i < k among ties).
+ * LIP_M_LOCAL_KNN (Sec. 4.3, scalar per datum): for each i, the knn nearest
+ *   j != i (ranked by dist, l2 by the sum of squares; ties rank the lower j
+ *   first), M_i = max over them of |y_i - y_j| / dist:
+ *   M64 [n] optional, M32 [n] optional (rounded up), pair unused.
+ * Coincident points with equal y are skipped; coincident points with
+ * different y make the slope infinite: the result is +inf (and, for
+ * LIP_M_GLOBAL, pair names the lowest such pair).  knn in 1..LIP_MAX_KNN.
+ * Needs ws. */
+lip_status lip_estimate_M(const lip_metric *metric, const float *x, const float *y, int64_t n,
+                          int32_t mode, int32_t knn, double *M64, float *M32, int64_t *pair,
+                          void *ws, size_t ws_bytes, uint32_t flags, lip_stream stream);
+
+/* ---- many independent fits in one launch ------------------------------------
+ * One entry per data set: its own metric, data, constants, queries and
+ * outputs (all device pointers except metric.w / metric.mon).  Outputs as in
+ * lip_fit_eval; the results are identical to calling lip_fit_eval on each
+ * set. */
+typedef struct {
+    lip_metric metric;
+    const float *x;
+    const float *y;
+    int64_t n;
+    float M;
+    const float *Mk;
+    const float *xq;
+    int64_t q;
+    float *g;
+    float *h_up;
+    float *h_lo;
+    int32_t *arg_up;
+    int32_t *arg_lo;
+} lip_batch_desc;
+
+typedef struct lip_plan lip_plan;
+
+/* Builds a plan: copies the descriptors, allocates the plan's own device
+ * memory (staged data, work list, counters), picks tile parameters from the
+ * tuning table, orders the work longest-first and records one HIP graph that
+ * runs every set.  The metric host arrays are copied; the device arrays
+ * must stay valid while the plan is executed. */
+lip_status lip_plan_create(lip_plan **plan, const lip_batch_desc *sets, int32_t n_sets,
+                           uint32_t flags, lip_stream stream);
+/* Launches the plan's graph on `stream` (asynchronous). */
+lip_status lip_plan_execute(lip_plan *plan, lip_stream stream);
+/* Releases the plan (synchronises with its last execution first). */
+lip_status lip_plan_destroy(lip_plan *plan);
+
+/* ---- tile parameters --------------------------------------------------------
+ * Runtime tiling choices of the bound kernels for one shape class
+ * (d, number of monotone coordinates, norm). */
+typedef struct {
+    int32_t tile;         /* data points per argmin tile (multiple of 8) */
+    int32_t split;        /* number of data chunks (1 = no split) */
+    int32_t waves;        /* waves per workgroup (1..4) */
+    int32_t reserved;
+} lip_tile_cfg;
+
+lip_status lip_tune_get(int32_t d, int32_t n_mon, int32_t norm, int64_t n, int64_t q,
+                        lip_tile_cfg *cfg);
+lip_status lip_tune_set(int32_t d, int32_t n_mon, int32_t norm, const lip_tile_cfg *cfg);
+/* Times candidate tile parameters for this shape class on synthetic data
+ * of the given sizes (allocates and frees its own device memory, blocks),
+ * stores the fastest with lip_tune_set and returns it. */
+lip_status lip_autotune(int32_t d, int32_t n_mon, int32_t norm, int64_t n, int64_t q,
+                        lip_stream stream, lip_tile_cfg *best);
+
+const char *lip_status_string(lip_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LIPFIT_H */

@@ -54,6 +54,8 @@ def _load():
         lib.orc_num_threads.restype = i32
         lib.orc_bounds.argtypes = [i32, i32, P, P, P, P, i64, f64, P, P, i64, P, P, P, P, P]
         lib.orc_bounds.restype = None
+        lib.orc_candidates.argtypes = [i32, i32, P, P, P, P, i64, f64, P, P, P, P]
+        lib.orc_candidates.restype = None
         lib.orc_consistency.argtypes = [i32, i32, P, P, P, P, i64, f64, P, f64, P, i64,
                                         P, P, P, P, P, P]
         lib.orc_consistency.restype = None
@@ -101,6 +103,18 @@ def bounds(x, y, xq, norm: int, M: float = 0.0, Mk=None, mon=None, w=None):
     _load().orc_bounds(d, norm, _p(w), _p(mon), _p(x), _p(y), x.shape[0], float(M), _p(Mk),
                        _p(xq), q, _p(hu), _p(hl), _p(g), _p(au), _p(al))
     return hu, hl, g, au, al
+
+
+def candidates(x, y, xq1, norm: int, M: float = 0.0, Mk=None, mon=None, w=None):
+    """(u[n], l[n]) float64: every bound candidate of Eq. (2) for one query."""
+    d = int(np.shape(x)[1])
+    x, y, w, mon = _common(x, y, w, mon, d)
+    q1 = _f32(xq1).reshape(d)
+    Mk = None if Mk is None else _f32(Mk)
+    u, l = np.empty(x.shape[0], np.float64), np.empty(x.shape[0], np.float64)
+    _load().orc_candidates(d, norm, _p(w), _p(mon), _p(x), _p(y), x.shape[0], float(M), _p(Mk),
+                           _p(q1), _p(u), _p(l))
+    return u, l
 
 
 def consistency(x, y, norm: int, M: float = 0.0, Mk=None, mon=None, w=None, tol: float = 0.0,

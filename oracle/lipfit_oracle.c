@@ -132,6 +132,21 @@ void orc_bounds(int d, int norm, const double *w, const signed char *mon,
     }
 }
 
+/* All candidates of Eq. (2) for one query: u[k] = y^k + M_k dist_up(x, x^k),
+ * l[k] = y^k - M_k dist_lo(x, x^k), k = 0..n-1 (used to list near-ties). */
+void orc_candidates(int d, int norm, const double *w, const signed char *mon,
+                    const float *x, const float *y, long n, double M, const float *Mk,
+                    const float *xq1, double *u, double *l)
+{
+    for (long k = 0; k < n; ++k) {
+        double du, dl;
+        dist_pair(d, norm, w, mon, xq1, x + k * (long)d, &du, &dl, NULL, NULL);
+        double mk = m_of(Mk, M, k);
+        u[k] = (double)y[k] + mk * du;
+        l[k] = (double)y[k] - mk * dl;
+    }
+}
+
 /* Data-side consistency check: whether the data can be interpolated by a
  * function with Lipschitz constant M (Sec. 1, the Lipschitz condition
  * |f(x) - f(z)| <= M d(x, z)) that also respects the monotonicity constraints

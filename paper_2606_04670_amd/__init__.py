@@ -1,0 +1,11 @@
+"""MI355X (gfx950) implementation of the all-pairs Lipschitz bound evaluation
+of optimal Lipschitz interpolation with monotonicity constraints: the
+envelopes H_up / H_lo (Eq. 2), the interpolant g (Eq. 3) with directional
+distances on monotone coordinates (Eq. 4), the data-side consistency check
+and Lipschitz-constant estimates, subgradients, batched fits and a
+BF16-MFMA l2 variant.  The work runs in hand-written HIP kernels behind the
+C ABI of include/lipfit.h; this package only binds it.
+"""
+from ._lib import LipError, load  # noqa: F401
+from .api import (LipFitFn, Metric, Plan, autotune, backward, bounds, consistency,  # noqa: F401
+                  estimate_M, fit_eval, lipfit, tune_get, tune_set)

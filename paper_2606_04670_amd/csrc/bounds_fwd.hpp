@@ -1,0 +1,247 @@
+// Fused all-pairs bound kernel: distance -> bound candidates -> min / max ->
+// first attaining index, for Eq. (2)-(3), without materialising the
+// query x data matrix.
+//
+// Work decomposition.  A wave owns 64*R queries (R per lane, held in VGPRs)
+// and one chunk of the data (a run of whole tiles).  The data are streamed
+// in groups of 4 records through scalar loads (the next group is requested
+// before the current one is used); every record is used by all R queries of
+// all 64 lanes before it is dropped.  Workgroups are numbered chunk-fastest,
+// so with a chunk count that divides 8 or is a multiple of 8, each XCD
+// (blockIdx % 8) always reads the same chunks and keeps them in its own L2.
+//
+// Argmin without per-pair index tracking.  The inner loop keeps only the
+// running min/max.  At the end of each tile a lane records the tile id if
+// its running value strictly improved during that tile.  The attaining index
+// is then the first index in the last improving tile whose candidate equals
+// the final value; a re-scan of that one tile per query with the identical
+// arithmetic (pair_bounds) finds it.  Ties therefore resolve to the lowest
+// index, as in the definition.
+//
+// Split chunks write per-chunk partial results; a combine kernel reduces
+// them in chunk order (strict comparisons keep the lower index on ties).
+#pragma once
+
+#include <array>
+#include <climits>
+#include <utility>
+
+#include "lip_device.hpp"
+#include "lip_internal.hpp"
+
+namespace lip {
+
+// Records per scalar-load group: two groups (current and next) must fit in
+// the SGPR file next to the loop state.  Tiles are multiples of 8 records, so
+// a tile always holds an even number of groups.
+constexpr int group_for_dim(int D) { return D <= 5 ? 4 : 2; }
+
+template <int D, int DM, int NORM>
+struct FwdTraits {
+    static constexpr int R = rows_for_dim(D);
+    static constexpr bool kQm = (NORM == kNormL1 && DM > 0);
+};
+
+template <int D>
+__device__ __forceinline__ void load_group(cfloat_ptr p, float (&v)[group_for_dim(D) * Rec<D>::S])
+{
+#pragma unroll
+    for (int i = 0; i < group_for_dim(D) * Rec<D>::S; ++i) v[i] = p[i];
+}
+
+template <int D, int DM, int NORM>
+__device__ __forceinline__ void eval_group(const float (&v)[group_for_dim(D) * Rec<D>::S],
+                                           const float (&q)[D], float qm, float big, float &hu,
+                                           float &hl)
+{
+    constexpr int S = Rec<D>::S;
+    constexpr int kGroup = group_for_dim(D);
+    float uu[kGroup], ll[kGroup];
+#pragma unroll
+    for (int g = 0; g < kGroup; ++g) {
+        float xk[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) xk[j] = v[g * S + j];
+        pair_bounds<D, DM, NORM>(q, qm, xk, v[g * S + Rec<D>::Y], v[g * S + Rec<D>::M],
+                                 v[g * S + Rec<D>::YU], big, uu[g], ll[g]);
+    }
+#pragma unroll
+    for (int g = 0; g < kGroup; g += 2) {
+        hu = fminf(fminf(hu, uu[g]), uu[g + 1]);
+        hl = fmaxf(fmaxf(hl, ll[g]), ll[g + 1]);
+    }
+}
+
+template <int D, int DM, int NORM>
+__global__ void __launch_bounds__(256) bounds_fwd_kernel(FwdArgs a)
+{
+    constexpr int S = Rec<D>::S;
+    constexpr int R = FwdTraits<D, DM, NORM>::R;
+    constexpr int kGroup = group_for_dim(D);
+    constexpr int GS = kGroup * S;
+    const int lane = threadIdx.x & 63;
+    // wave index is wave-uniform; readfirstlane lets the compiler keep every
+    // loop counter and address derived from it in SGPRs
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nw = blockDim.x >> 6;
+    const int chunk = blockIdx.x % a.n_chunks;
+    const int64_t qblock = (int64_t)(blockIdx.x / a.n_chunks) * nw + wave;
+    const int64_t q0 = qblock * (64 * R);
+    if (q0 >= a.q) return;  // wave-uniform: no query of this wave exists
+
+    const float big = opaque_inf();
+    float qv[R][D];
+    float qm[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        int64_t qi = q0 + r * 64 + lane;
+        qi = qi < a.q ? qi : a.q - 1;
+        const float *src = a.xq + qi * D;
+#pragma unroll
+        for (int j = 0; j < D; ++j) qv[r][j] = src[a.xf.perm[j]] * a.xf.scale[j];
+        qm[r] = query_mon_sum<D, DM>(qv[r]);
+    }
+
+    const int64_t t0 = (int64_t)chunk * a.tiles_per_chunk;
+    int64_t t1 = t0 + a.tiles_per_chunk;
+    t1 = t1 < a.n_tiles ? t1 : a.n_tiles;
+    const int tile = a.tile;
+    const int gpt = tile / kGroup;  // groups per tile
+
+    float hu[R], hl[R], pu[R], pl[R];
+    int tu[R], tl[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        hu[r] = __builtin_inff();
+        hl[r] = -__builtin_inff();
+        pu[r] = hu[r];
+        pl[r] = hl[r];
+        tu[r] = (int)t0;
+        tl[r] = (int)t0;
+    }
+
+    // Double-buffered scalar loads: group gi+1 is requested before group gi
+    // is evaluated.  A tile holds an even number of groups, so the loop body
+    // handles two groups and the tile-end bookkeeping follows the second.
+    const cfloat_ptr base = as_const(a.data);
+    const int64_t g0 = t0 * gpt, g1 = t1 * gpt;
+    float ga[GS], gb[GS];
+    if (g0 < g1) load_group<D>(base + g0 * GS, ga);
+    int left = gpt / 2;
+    int64_t t = t0;
+    for (int64_t gi = g0; gi < g1; gi += 2) {
+        load_group<D>(base + (gi + 1) * GS, gb);
+#pragma unroll
+        for (int r = 0; r < R; ++r) eval_group<D, DM, NORM>(ga, qv[r], qm[r], big, hu[r], hl[r]);
+        const int64_t gn = gi + 2 < g1 ? gi + 2 : gi + 1;
+        load_group<D>(base + gn * GS, ga);
+#pragma unroll
+        for (int r = 0; r < R; ++r) eval_group<D, DM, NORM>(gb, qv[r], qm[r], big, hu[r], hl[r]);
+        if (--left == 0) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                tu[r] = hu[r] < pu[r] ? (int)t : tu[r];
+                tl[r] = hl[r] > pl[r] ? (int)t : tl[r];
+                pu[r] = hu[r];
+                pl[r] = hl[r];
+            }
+            left = gpt / 2;
+            ++t;
+        }
+    }
+
+    // Re-scan the last improving tile of each query for the first index that
+    // attains the final value (descending scan: the last hit is the lowest).
+    int au[R], al[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t bu = (int64_t)tu[r] * tile, bl = (int64_t)tl[r] * tile;
+        int iu = INT_MAX, il = INT_MAX;
+#pragma unroll 2
+        for (int k = tile - 1; k >= 0; --k) {
+            const float *ru = a.data + (bu + k) * S;
+            const float *rl = a.data + (bl + k) * S;
+            float xu[D], xl[D];
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                xu[j] = ru[j];
+                xl[j] = rl[j];
+            }
+            float u, l, unused;
+            pair_bounds<D, DM, NORM>(qv[r], qm[r], xu, ru[Rec<D>::Y], ru[Rec<D>::M], ru[Rec<D>::YU],
+                                     big, u, unused);
+            pair_bounds<D, DM, NORM>(qv[r], qm[r], xl, rl[Rec<D>::Y], rl[Rec<D>::M], rl[Rec<D>::YU],
+                                     big, unused, l);
+            iu = (u == hu[r]) ? (int)(bu + k) : iu;
+            il = (l == hl[r]) ? (int)(bl + k) : il;
+        }
+        au[r] = iu;
+        al[r] = il;
+    }
+
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t qi = q0 + r * 64 + lane;
+        if (qi >= a.q) continue;
+        if (a.n_chunks == 1) {
+            if (a.g) a.g[qi] = 0.5f * (hu[r] + hl[r]);
+            if (a.h_up) a.h_up[qi] = hu[r];
+            if (a.h_lo) a.h_lo[qi] = hl[r];
+            if (a.arg_up) a.arg_up[qi] = au[r];
+            if (a.arg_lo) a.arg_lo[qi] = al[r];
+        } else {
+            const int64_t o = (int64_t)chunk * a.q + qi;
+            const int64_t o2 = ((int64_t)a.n_chunks + chunk) * a.q + qi;
+            a.part_v[o] = hu[r];
+            a.part_i[o] = au[r];
+            a.part_v[o2] = hl[r];
+            a.part_i[o2] = al[r];
+        }
+    }
+}
+
+template <int NORM, int D, int DM>
+void launch_fwd(const FwdArgs &a, dim3 grid, dim3 block, hipStream_t s)
+{
+    hipLaunchKernelGGL((bounds_fwd_kernel<D, DM, NORM>), grid, block, 0, s, a);
+}
+
+template <int NORM, int D, int... DMs>
+constexpr std::array<FwdLauncher, D + 1> fwd_row(std::integer_sequence<int, DMs...>)
+{
+    return {{&launch_fwd<NORM, D, DMs>...}};
+}
+
+template <int NORM, int D>
+FwdLauncher fwd_pick(int dm)
+{
+    constexpr auto row = fwd_row<NORM, D>(std::make_integer_sequence<int, D + 1>{});
+    return row[dm];
+}
+
+template <int NORM>
+FwdLauncher fwd_table(int d, int dm)
+{
+    if (dm < 0 || dm > d) return nullptr;
+    switch (d) {
+    case 1: return fwd_pick<NORM, 1>(dm);
+    case 2: return fwd_pick<NORM, 2>(dm);
+    case 3: return fwd_pick<NORM, 3>(dm);
+    case 4: return fwd_pick<NORM, 4>(dm);
+    case 5: return fwd_pick<NORM, 5>(dm);
+    case 6: return fwd_pick<NORM, 6>(dm);
+    case 7: return fwd_pick<NORM, 7>(dm);
+    case 8: return fwd_pick<NORM, 8>(dm);
+    case 9: return fwd_pick<NORM, 9>(dm);
+    case 10: return fwd_pick<NORM, 10>(dm);
+    case 11: return fwd_pick<NORM, 11>(dm);
+    case 12: return fwd_pick<NORM, 12>(dm);
+    case 13: return fwd_pick<NORM, 13>(dm);
+    case 14: return fwd_pick<NORM, 14>(dm);
+    case 15: return fwd_pick<NORM, 15>(dm);
+    case 16: return fwd_pick<NORM, 16>(dm);
+    default: return nullptr;
+    }
+}
+
+}  // namespace lip

@@ -1,0 +1,76 @@
+// Host-side helpers shared by the entry points: argument validation (no HIP
+// call is made before it passes), metric -> coordinate transform, tiling
+// choices and workspace layout.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/lipfit.h"
+#include "lip_internal.hpp"
+
+namespace lip {
+
+constexpr int kMaxTile = 256;                 // largest argmin tile (records)
+constexpr int kMaxChunks = 64;                // largest data split
+constexpr int64_t kMaxPartials = 1ll << 23;   // n_chunks * q cap (per bound)
+constexpr int64_t kMaxIndex = 2147483647ll;   // indices are int32
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Validated metric: transform of the coordinates and monotone count.
+struct MetricInfo {
+    int d = 0;
+    int norm = 0;
+    int dm = 0;          // number of monotone coordinates
+    Xform xf{};          // free coordinates first, then monotone ones
+    double w[kMaxDim];   // weights (for the FP64 passes)
+    int8_t mon[kMaxDim]; // original monotonicity (for the FP64 passes)
+};
+
+lip_status parse_metric(const lip_metric *m, MetricInfo *out);
+
+// Resolved tiling for one bound-kernel launch.
+struct FwdPlan {
+    int R = 0;
+    int tile = 64;
+    int waves = 4;
+    int64_t n_pad = 0, n_tiles = 0;
+    int tiles_per_chunk = 0, n_chunks = 1;
+    int64_t grid = 0;
+};
+
+lip_tile_cfg tune_lookup(int d, int dm, int norm, int64_t n, int64_t q);
+FwdPlan make_fwd_plan(const MetricInfo &mi, int64_t n, int64_t q, const lip_tile_cfg &cfg);
+
+// Workspace layout of the bound path.
+size_t staged_bytes(int64_t n, int d);
+size_t partial_bytes(int64_t q);
+
+FwdLauncher fwd_launcher(int norm, int d, int dm);
+
+// Runs the bound path (stage -> fused kernel -> optional combine) on a
+// validated problem.  ws must hold staged_bytes + partial_bytes.
+lip_status run_bounds(const MetricInfo &mi, const float *x, const float *y, int64_t n, float M,
+                      const float *Mk, const float *xq, int64_t q, float *g, float *h_up,
+                      float *h_lo, int32_t *arg_up, int32_t *arg_lo, void *ws, size_t ws_bytes,
+                      const lip_tile_cfg &cfg, hipStream_t stream);
+
+// BF16-MFMA l2 variant of run_bounds (bf16_l2.hip).
+lip_status run_bounds_bf16(const MetricInfo &mi, const float *x, const float *y, int64_t n, float M,
+                           const float *Mk, const float *xq, int64_t q, float *g, float *h_up,
+                           float *h_lo, int32_t *arg_up, int32_t *arg_lo, void *ws,
+                           size_t ws_bytes, hipStream_t stream);
+size_t bf16_extra_bytes(int64_t n, int64_t q, int d);
+
+// Workspace needs of the other passes.
+size_t data_side_ws_bytes(int64_t n, int d);
+size_t backward_ws_bytes(int64_t n);
+
+lip_status check_finite(const float *const *arrays, const int64_t *counts, int n_arrays,
+                        void *ws, hipStream_t stream);
+
+inline lip_status dev_status(hipError_t e) { return e == hipSuccess ? LIP_OK : LIP_E_DEVICE; }
+
+}  // namespace lip

@@ -1,0 +1,68 @@
+// Internal declarations shared by the host library and the kernel
+// translation units.  Not part of the public ABI (include/lipfit.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lip_device.hpp"
+
+namespace lip {
+
+// Queries per lane for a dimension: keeps R (D + 7) around 80-100 VGPRs.
+constexpr int rows_for_dim(int D) { return D <= 2 ? 12 : (D <= 4 ? 8 : (D <= 6 ? 6 : 4)); }
+
+// Arguments of the fused bound kernel (see bounds_fwd.hpp).
+struct FwdArgs {
+    const float *data;       // staged records [n_pad][D + 3]
+    int64_t n;               // real data count (n <= n_pad)
+    int64_t n_tiles;         // n_pad / tile
+    int32_t tile;            // records per argmin tile (multiple of 8)
+    int32_t tiles_per_chunk;
+    int32_t n_chunks;
+    int32_t pad0;
+    const float *xq;         // [q][D] row-major, untransformed
+    int64_t q;
+    Xform xf;                // query transform (same as the staging one)
+    float *g, *h_up, *h_lo;  // outputs (n_chunks == 1), any may be NULL
+    int32_t *arg_up, *arg_lo;
+    float *part_v;           // [2][n_chunks][q] partial values (n_chunks > 1)
+    int32_t *part_i;         // [2][n_chunks][q] partial indices
+};
+
+typedef void (*FwdLauncher)(const FwdArgs &, dim3, dim3, hipStream_t);
+
+// Staging of the data set into bound-kernel records (stage.hip).
+struct StageArgs {
+    const float *x;   // [n][D] row-major
+    const float *y;   // [n]
+    const float *Mk;  // [n] or NULL
+    float M;          // global constant when Mk == NULL
+    int32_t l1_mon;   // number of monotone coordinates when the norm is l1, else 0
+    int64_t n, n_pad;
+    Xform xf;
+    float *out;       // [n_pad][D + 3]
+};
+
+// Chunk-partial reduction (stage.hip).
+struct CombineArgs {
+    const float *part_v;
+    const int32_t *part_i;
+    int64_t q;
+    int32_t n_chunks;
+    int32_t pad0;
+    float *g, *h_up, *h_lo;
+    int32_t *arg_up, *arg_lo;
+};
+
+hipError_t launch_stage(int d, const StageArgs &a, hipStream_t s);
+hipError_t launch_combine(const CombineArgs &a, hipStream_t s);
+hipError_t launch_nonfinite(const float *v, int64_t n, int *flag, hipStream_t s);
+hipError_t launch_fill_i32(int *p, int64_t n, int v, hipStream_t s);
+
+FwdLauncher fwd_launcher_l1(int d, int dm);
+FwdLauncher fwd_launcher_l2(int d, int dm);
+FwdLauncher fwd_launcher_linf(int d, int dm);
+
+
+}  // namespace lip

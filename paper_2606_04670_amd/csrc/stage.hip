@@ -1,0 +1,148 @@
+// Small helper kernels of the bound path: data staging, partial combine,
+// fills and the optional finite-value scan.
+#include <climits>
+
+#include "lip_device.hpp"
+#include "lip_internal.hpp"
+
+namespace lip {
+
+// Stage the data set into records [x'_0..x'_{D-1} | y | M | yU] (see
+// lip_device.hpp), padding up to n_pad by repeating the last datum.  A
+// repeated record has the same candidates as the datum it copies and a
+// higher index, so it never wins a tie.
+template <int D>
+__global__ void stage_kernel(StageArgs a)
+{
+    constexpr int S = Rec<D>::S;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.n_pad; k += stride) {
+        const int64_t src = k < a.n ? k : a.n - 1;
+        const float *xs = a.x + src * D;
+        float *o = a.out + k * S;
+        float xv[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) xv[j] = xs[a.xf.perm[j]] * a.xf.scale[j];
+        const float y = a.y[src];
+        const float m = a.Mk ? a.Mk[src] : a.M;
+        // l1 with monotone coordinates: yU = y - M * sum_mon x'_i (summed in
+        // index order, like the per-query sum Qm).
+        float yu = y;
+        if (a.l1_mon > 0) {
+            float s = 0.0f;
+            bool first = true;
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                if (j >= D - a.l1_mon) {
+                    s = first ? xv[j] : s + xv[j];
+                    first = false;
+                }
+            }
+            yu = fmaf(-m, s, y);
+        }
+#pragma unroll
+        for (int j = 0; j < D; ++j) o[j] = xv[j];
+        o[Rec<D>::Y] = y;
+        o[Rec<D>::M] = m;
+        o[Rec<D>::YU] = yu;
+    }
+}
+
+// Reduce per-chunk partials in chunk order: strict comparisons keep the
+// earlier chunk (lower indices) on ties.  Writes the final outputs.
+__global__ void combine_kernel(CombineArgs a)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < a.q; j += stride) {
+        float bu = a.part_v[j];
+        int iu = a.part_i[j];
+        float bl = a.part_v[(int64_t)a.n_chunks * a.q + j];
+        int il = a.part_i[(int64_t)a.n_chunks * a.q + j];
+        for (int c = 1; c < a.n_chunks; ++c) {
+            const float vu = a.part_v[(int64_t)c * a.q + j];
+            const float vl = a.part_v[((int64_t)a.n_chunks + c) * a.q + j];
+            if (vu < bu) {
+                bu = vu;
+                iu = a.part_i[(int64_t)c * a.q + j];
+            }
+            if (vl > bl) {
+                bl = vl;
+                il = a.part_i[((int64_t)a.n_chunks + c) * a.q + j];
+            }
+        }
+        if (a.g) a.g[j] = 0.5f * (bu + bl);
+        if (a.h_up) a.h_up[j] = bu;
+        if (a.h_lo) a.h_lo[j] = bl;
+        if (a.arg_up) a.arg_up[j] = iu;
+        if (a.arg_lo) a.arg_lo[j] = il;
+    }
+}
+
+// Sets flag[0] to 1 if any of the n floats is NaN or +-Inf (exponent bits
+// all ones; tested on the bit pattern).
+__global__ void nonfinite_kernel(const float *v, int64_t n, int *flag)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int bad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint32_t b = __float_as_uint(v[i]);
+        bad |= ((b & 0x7f800000u) == 0x7f800000u);
+    }
+    if (bad) atomicOr(flag, 1);
+}
+
+__global__ void fill_i32_kernel(int *p, int64_t n, int v)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+static int grid_for(int64_t n, int block)
+{
+    int64_t g = (n + block - 1) / block;
+    if (g > 65536) g = 65536;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+hipError_t launch_stage(int d, const StageArgs &a, hipStream_t s)
+{
+    const int block = 256;
+    const int grid = grid_for(a.n_pad, block);
+    switch (d) {
+#define LIP_STAGE_CASE(DD) \
+    case DD: hipLaunchKernelGGL(stage_kernel<DD>, dim3(grid), dim3(block), 0, s, a); break;
+        LIP_STAGE_CASE(1) LIP_STAGE_CASE(2) LIP_STAGE_CASE(3) LIP_STAGE_CASE(4)
+        LIP_STAGE_CASE(5) LIP_STAGE_CASE(6) LIP_STAGE_CASE(7) LIP_STAGE_CASE(8)
+        LIP_STAGE_CASE(9) LIP_STAGE_CASE(10) LIP_STAGE_CASE(11) LIP_STAGE_CASE(12)
+        LIP_STAGE_CASE(13) LIP_STAGE_CASE(14) LIP_STAGE_CASE(15) LIP_STAGE_CASE(16)
+#undef LIP_STAGE_CASE
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(const CombineArgs &a, hipStream_t s)
+{
+    const int block = 256;
+    hipLaunchKernelGGL(combine_kernel, dim3(grid_for(a.q, block)), dim3(block), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_nonfinite(const float *v, int64_t n, int *flag, hipStream_t s)
+{
+    if (n <= 0 || !v) return hipSuccess;
+    const int block = 256;
+    hipLaunchKernelGGL(nonfinite_kernel, dim3(grid_for(n, block)), dim3(block), 0, s, v, n, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int *p, int64_t n, int v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int block = 256;
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(grid_for(n, block)), dim3(block), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+}  // namespace lip

@@ -1,0 +1,161 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/lipfit.h declares, and its host-side validation rejects bad arguments
+before any device work (status codes of include/lipfit.h)."""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2606_04670_amd", "liblipfit.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB),
+                                reason="liblipfit.so not built (run __graft_entry__.build())")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2606_04670_amd import _lib
+    _lib.load()
+    return _lib
+
+
+def test_exports_every_declared_symbol(L):
+    names = L.header_symbols()
+    assert len(names) >= 13
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True,
+                         check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    lib = L.load()
+    for n in names:
+        assert getattr(lib, n) is not None
+
+
+def test_status_strings(L):
+    lib = L.load()
+    for st in range(8):
+        assert lib.lip_status_string(st)
+    assert lib.lip_status_string(0) == b"ok"
+
+
+def test_workspace_size_monotone(L):
+    lib = L.load()
+    a = lib.lip_workspace_size(1000, 1000, 4, 0)
+    b = lib.lip_workspace_size(100000, 1000000, 4, 0)
+    assert 0 < a < b
+    assert lib.lip_workspace_size(0, 0, 0, 0) > 0
+
+
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+
+
+def _metric(L, d=3, norm=2, w=None, mon=None):
+    keep = []
+    wp = monp = None
+    if w is not None:
+        wa = np.asarray(w, np.float32)
+        keep.append(wa)
+        wp = wa.ctypes.data_as(ctypes.c_void_p)
+    if mon is not None:
+        ma = np.asarray(mon, np.int8)
+        keep.append(ma)
+        monp = ma.ctypes.data_as(ctypes.c_void_p)
+    m = L.LipMetric(d, norm, wp, monp)
+    return m, keep
+
+
+def _eval(L, m, n=10, q=5, M=1.0, Mk=None, ws=FAKE, ws_bytes=1 << 30, flags=0, x=FAKE):
+    lib = L.load()
+    return lib.lip_fit_eval(ctypes.byref(m), x, FAKE, n, M, Mk, FAKE, q, FAKE, None, None, None,
+                            None, ws, ws_bytes, flags, None)
+
+
+def test_fit_eval_validation(L):
+    m, keep = _metric(L)
+    assert _eval(L, m, n=0) == L.LIP_E_SHAPE
+    assert _eval(L, m, q=-1) == L.LIP_E_SHAPE
+    assert _eval(L, m, M=-1.0) == L.LIP_E_VALUE
+    assert _eval(L, m, M=float("nan")) == L.LIP_E_VALUE
+    assert _eval(L, m, M=float("inf")) == L.LIP_E_VALUE
+    assert _eval(L, m, x=None) == L.LIP_E_ARG
+    assert _eval(L, m, ws=None) == L.LIP_E_WORKSPACE
+    assert _eval(L, m, flags=1 << 7) == L.LIP_E_ARG
+    assert _eval(L, m, q=0) == L.LIP_OK  # no-op, no device work
+    bad_d, k1 = _metric(L, d=0)
+    assert _eval(L, bad_d) == L.LIP_E_SHAPE
+    big_d, k2 = _metric(L, d=17)
+    assert _eval(L, big_d) == L.LIP_E_SHAPE
+    bad_norm, k3 = _metric(L, norm=4)
+    assert _eval(L, bad_norm) == L.LIP_E_ARG
+    bad_w, k4 = _metric(L, w=[1.0, 0.0, 1.0])
+    assert _eval(L, bad_w) == L.LIP_E_VALUE
+    bad_mon, k5 = _metric(L, mon=[0, 2, 0])
+    assert _eval(L, bad_mon) == L.LIP_E_VALUE
+    # BF16 path: l2 without monotone coordinates only
+    l1, k6 = _metric(L, norm=1)
+    assert _eval(L, l1, flags=L.LIP_FLAG_BF16) == L.LIP_E_UNSUPPORTED
+    monm, k7 = _metric(L, mon=[1, 0, 0])
+    assert _eval(L, monm, flags=L.LIP_FLAG_BF16) == L.LIP_E_UNSUPPORTED
+    assert L.load().lip_fit_eval(None, FAKE, FAKE, 10, 1.0, None, FAKE, 5, FAKE, None, None,
+                                 None, None, FAKE, 1 << 30, 0, None) == L.LIP_E_ARG
+
+
+def test_other_entry_points_validation(L):
+    lib = L.load()
+    m, keep = _metric(L)
+    # backward
+    assert lib.lip_fit_backward(ctypes.byref(m), FAKE, FAKE, 0, 1.0, None, FAKE, 5, FAKE, FAKE,
+                                FAKE, None, None, FAKE, FAKE, FAKE, None, 0, 0, None) \
+        == L.LIP_E_SHAPE
+    assert lib.lip_fit_backward(ctypes.byref(m), FAKE, FAKE, 10, 1.0, None, FAKE, 5, None, FAKE,
+                                FAKE, None, None, FAKE, FAKE, FAKE, None, 0, 0, None) \
+        == L.LIP_E_ARG
+    assert lib.lip_fit_backward(ctypes.byref(m), FAKE, FAKE, 10, 1.0, None, FAKE, 5, FAKE, FAKE,
+                                FAKE, None, None, FAKE, FAKE, FAKE, None, 0,
+                                L.LIP_FLAG_DETERMINISTIC, None) == L.LIP_E_WORKSPACE
+    assert lib.lip_fit_backward(ctypes.byref(m), FAKE, FAKE, 10, 1.0, None, FAKE, 0, FAKE, FAKE,
+                                FAKE, None, None, FAKE, FAKE, FAKE, None, 0, 0, None) == L.LIP_OK
+    # consistency
+    assert lib.lip_consistency(ctypes.byref(m), FAKE, FAKE, 10, 1.0, None, -1.0, FAKE, None, None,
+                               None, None, FAKE, 1 << 30, 0, None) == L.LIP_E_VALUE
+    assert lib.lip_consistency(ctypes.byref(m), FAKE, FAKE, 10, 1.0, None, 0.0, None, None, None,
+                               None, None, FAKE, 1 << 30, 0, None) == L.LIP_E_ARG
+    assert lib.lip_consistency(ctypes.byref(m), FAKE, FAKE, 10, 1.0, None, 0.0, FAKE, None, None,
+                               None, None, FAKE, 16, 0, None) == L.LIP_E_WORKSPACE
+    # estimate_M
+    assert lib.lip_estimate_M(ctypes.byref(m), FAKE, FAKE, 10, 7, 16, None, None, None, FAKE,
+                              1 << 30, 0, None) == L.LIP_E_ARG
+    assert lib.lip_estimate_M(ctypes.byref(m), FAKE, FAKE, 10, L.LIP_M_LOCAL_KNN, 0, None, None,
+                              None, FAKE, 1 << 30, 0, None) == L.LIP_E_VALUE
+    assert lib.lip_estimate_M(ctypes.byref(m), FAKE, FAKE, 10, L.LIP_M_LOCAL_KNN, 33, None, None,
+                              None, FAKE, 1 << 30, 0, None) == L.LIP_E_VALUE
+    assert lib.lip_estimate_M(ctypes.byref(m), FAKE, FAKE, 0, L.LIP_M_GLOBAL, 16, None, None,
+                              None, FAKE, 1 << 30, 0, None) == L.LIP_E_SHAPE
+
+
+def test_tuning_table(L):
+    lib = L.load()
+    cfg = L.LipTileCfg()
+    assert lib.lip_tune_get(4, 2, 1, 100000, 1000000, ctypes.byref(cfg)) == L.LIP_OK
+    assert cfg.tile % 8 == 0 and cfg.split >= 1 and cfg.waves >= 1
+    bad = L.LipTileCfg(12, 1, 4, 0)
+    assert lib.lip_tune_set(4, 2, 1, ctypes.byref(bad)) == L.LIP_E_VALUE
+    good = L.LipTileCfg(128, 2, 2, 0)
+    assert lib.lip_tune_set(4, 2, 1, ctypes.byref(good)) == L.LIP_OK
+    got = L.LipTileCfg()
+    lib.lip_tune_get(4, 2, 1, 10, 10, ctypes.byref(got))
+    assert (got.tile, got.split, got.waves) == (128, 2, 2)
+    assert lib.lip_tune_set(4, 2, 1, None) == L.LIP_OK
+    assert lib.lip_tune_get(4, 5, 1, 10, 10, ctypes.byref(got)) == L.LIP_E_SHAPE
+
+
+def test_python_binding_refuses_cpu_tensors():
+    import torch
+    import paper_2606_04670_amd as lf
+    x = torch.zeros(4, 2)
+    with pytest.raises(ValueError):
+        lf.fit_eval(x, torch.zeros(4), torch.zeros(3, 2), lf.Metric(2, "l2"), M=1.0)

@@ -1,0 +1,161 @@
+"""GPU parity of the fused bound kernel (lip_fit_eval) against the FP64 oracle.
+
+Sizes span several argmin tiles with ragged tails; full-size workloads are
+checked on sampled queries.  Comparison rules are in tests/_parity.py.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from _parity import check_bounds
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lf():
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    import paper_2606_04670_amd as lf
+    lf.load()
+    return lf
+
+
+DEV = torch.device("cuda:0")
+
+
+def run(lf, p, want=("g", "h_up", "h_lo", "arg_up", "arg_lo"), Mk=None, **kw):
+    Mk = p.Mk if Mk is None else Mk
+    x = torch.from_numpy(p.x).to(DEV)
+    y = torch.from_numpy(p.y).to(DEV)
+    xq = torch.from_numpy(p.xq).to(DEV)
+    mk = None if Mk is None else torch.from_numpy(np.asarray(Mk, np.float32)).to(DEV)
+    met = lf.Metric(p.d, p.norm, mon=p.mon, w=p.w)
+    out = lf.fit_eval(x, y, xq, met, M=None if mk is not None else p.M, Mk=mk, want=want, **kw)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def test_plain_l2_workload_full(lf):
+    """d=2, N=1,000, Q=10,000, l2, M=4: every query against the oracle."""
+    p = W.plain_l2()
+    rep = check_bounds(p, run(lf, p), label="plain_l2")
+    print(rep)
+
+
+MON_PATTERNS = {
+    1: [[0], [1], [-1]],
+    2: [[0, 0], [1, 0], [-1, 1]],
+    3: [[0, 0, 0], [1, 0, -1], [1, 1, 1]],
+    4: [[0, 0, 0, 0], [1, 0, 1, 0], [0, -1, 0, 1]],
+    5: [[0] * 5, [1, 0, 0, -1, 0]],
+    7: [[0] * 7, [1, -1, 0, 0, 1, 0, 0]],
+    8: [[0] * 8, [1, 0, 1, 0, 1, 0, 1, 0]],
+    12: [[0] * 12, [1] * 6 + [0] * 6],
+    16: [[0] * 16, [0, 1] * 8],
+}
+
+
+@pytest.mark.parametrize("norm", [1, 2, 3])
+@pytest.mark.parametrize("d", sorted(MON_PATTERNS))
+def test_random_problems(lf, norm, d):
+    """Every norm x dimension x monotone pattern, global and per-point M,
+    weighted distances; n = 1,337 (ragged tail), q = 777."""
+    for k, mon in enumerate(MON_PATTERNS[d]):
+        for local in (False, True):
+            p = W.random_problem(1000 * d + 10 * k + local, n=1337, q=777, d=d, norm=norm,
+                                 mon=np.array(mon, np.int8), local=local, weighted=(k % 2 == 1))
+            check_bounds(p, run(lf, p), label=f"d={d} norm={norm} mon={mon} local={local}")
+
+
+@pytest.mark.parametrize("n,q", [(1, 5), (2, 1), (7, 64), (9, 65), (300, 129), (4097, 3)])
+def test_small_and_ragged_sizes(lf, n, q):
+    for norm in (1, 2, 3):
+        p = W.random_problem(7 + n + q, n=n, q=q, d=3, norm=norm, mon=np.array([1, 0, 0], np.int8),
+                             local=True)
+        check_bounds(p, run(lf, p), label=f"n={n} q={q} norm={norm}")
+
+
+def test_zero_queries_is_noop(lf):
+    p = W.random_problem(3, n=10, q=0, d=2, norm=2)
+    out = run(lf, p)
+    assert all(v.size == 0 for v in out.values())
+
+
+def test_ties_resolve_to_lowest_index(lf):
+    """M = 0: every candidate is y_k, so the argmin / argmax are the first
+    occurrences of min y / max y; duplicated data points tie exactly."""
+    g = np.random.default_rng(5)
+    n = 2000
+    x = g.random((n, 3)).astype(np.float32)
+    y = np.round(g.random(n) * 4).astype(np.float32)  # values in {0..4}: many ties
+    xq = g.random((500, 3)).astype(np.float32)
+    p = W.Problem("ties", x, y, 0.0, None, xq, 2, np.zeros(3, np.int8), np.ones(3, np.float32))
+    out = run(lf, p)
+    assert np.all(out["arg_up"] == np.argmin(y)) and np.all(out["arg_lo"] == np.argmax(y))
+    assert np.all(out["h_up"] == y.min()) and np.all(out["h_lo"] == y.max())
+    # duplicated points: copies 0..n-1 then again; the first copy must win
+    x2 = np.concatenate([x, x]).astype(np.float32)
+    y2 = np.concatenate([y, y]).astype(np.float32)
+    p2 = W.Problem("dups", x2, y2, 1.5, None, xq, 2, np.zeros(3, np.int8), np.ones(3, np.float32))
+    o2 = run(lf, p2)
+    assert np.all(o2["arg_up"] < n) and np.all(o2["arg_lo"] < n)
+    o1 = run(lf, W.Problem("single", x, y, 1.5, None, xq, 2, np.zeros(3, np.int8),
+                           np.ones(3, np.float32)))
+    for k in o1:
+        np.testing.assert_array_equal(o1[k], o2[k])
+
+
+@pytest.mark.parametrize("norm", [1, 2, 3])
+def test_tiling_and_split_do_not_change_results(lf, norm):
+    """Tile size, data split and waves per workgroup are performance knobs:
+    outputs must be bitwise identical across them (deterministic forward)."""
+    p = W.random_problem(11, n=5000, q=3000, d=4, norm=norm, mon=np.array([1, 0, 1, 0], np.int8),
+                         local=True)
+    ref = None
+    try:
+        for tile, split, waves in [(64, 1, 4), (8, 1, 1), (256, 3, 2), (32, 16, 4), (128, 64, 3)]:
+            lf.tune_set(4, 2, norm, tile=tile, split=split, waves=waves)
+            out = run(lf, p)
+            if ref is None:
+                ref = out
+                check_bounds(p, out, label=f"norm={norm}")
+            else:
+                for k in ref:
+                    np.testing.assert_array_equal(out[k], ref[k], err_msg=f"{k} {tile} {split}")
+    finally:
+        lf.tune_set(4, 2, norm, clear=True)
+    out2 = run(lf, p)
+    for k in ref:
+        np.testing.assert_array_equal(out2[k], ref[k])
+
+
+@pytest.mark.parametrize("norm", [1, 2, 3])
+def test_monotone_local_workload_full_size_sampled(lf, norm):
+    """d=4, N=100,000, Q=1,000,000, coordinates 1 and 3 increasing, per-point
+    M_k: the GPU evaluates every query, the oracle a seeded sample of 512."""
+    p = W.monotone_local(norm=norm)
+    out = run(lf, p)
+    qidx = np.sort(np.random.default_rng(norm).choice(p.q, 512, replace=False))
+    qidx = np.concatenate([[0, p.q - 1], qidx])
+    rep = check_bounds(p, out, qidx=qidx, label=f"monotone_local norm={norm}")
+    print(rep)
+    # determinism at full size
+    out2 = run(lf, p)
+    for k in out:
+        np.testing.assert_array_equal(out[k], out2[k])
+
+
+def test_diff_l2_workload_full_size_sampled(lf):
+    p = W.diff_l2()
+    out = run(lf, p)
+    qidx = np.sort(np.random.default_rng(3).choice(p.q, 256, replace=False))
+    print(check_bounds(p, out, qidx=qidx, label="diff_l2"))
+
+
+def test_mixed_l2_workload_full_size_sampled(lf):
+    """d=16, N=1,000,000, Q=1,000,000 (FP32 VALU path)."""
+    p = W.mixed_l2()
+    out = run(lf, p)
+    qidx = np.sort(np.random.default_rng(5).choice(p.q, 64, replace=False))
+    print(check_bounds(p, out, qidx=qidx, label="mixed_l2"))

@@ -1,0 +1,168 @@
+"""GPU data-side passes against the FP64 oracle.
+
+Both sides evaluate every pair in double precision with the same operation
+order, so slacks, partners, violation counts, slopes and neighbour sets are
+compared exactly (bit for bit).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def lf():
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    import paper_2606_04670_amd as lf
+    lf.load()
+    return lf
+
+
+def _t(a):
+    return None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _consistency(lf, p, M, Mk, tol=0.0):
+    met = lf.Metric(p.d, p.norm, mon=p.mon, w=p.w)
+    r = lf.consistency(_t(p.x), _t(p.y), met, M=None if Mk is not None else M, Mk=_t(Mk), tol=tol)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in r.items()}
+
+
+CASES = [
+    (1, [0, 0, 0], False, False),
+    (2, [1, 0, -1], True, True),
+    (3, [1, 1, 0], False, True),
+    (2, [0, 0, 0], False, False),
+]
+
+
+@pytest.mark.parametrize("norm,mon,local,weighted", CASES)
+def test_consistency_exact(lf, norm, mon, local, weighted):
+    for n, M in [(1, 1.0), (2, 0.5), (777, 1.5), (1031, 4.0)]:
+        p = W.random_problem(400 + n, n=n, q=1, d=3, norm=norm, mon=np.array(mon, np.int8),
+                             local=local, weighted=weighted)
+        M32 = float(np.float32(M))
+        g = _consistency(lf, p, M32, p.Mk)
+        o = oracle.consistency(p.x, p.y, norm, M=M32, Mk=p.Mk, mon=p.mon, w=p.w)
+        np.testing.assert_array_equal(g["slack_up"], o["slack_up"])
+        np.testing.assert_array_equal(g["slack_lo"], o["slack_lo"])
+        np.testing.assert_array_equal(g["partner_up"], o["partner_up"])
+        np.testing.assert_array_equal(g["partner_lo"], o["partner_lo"])
+        assert g["counts"][0] == o["viol_up"].sum() and g["counts"][1] == o["viol_lo"].sum()
+
+
+def test_consistency_boundary_ties_and_tolerance(lf):
+    """Dyadic 1-D data with slopes exactly M: consistent at M, violated just
+    below it; a tolerance absorbs the violations."""
+    x = (np.arange(64, dtype=np.float32) / 8.0)[:, None]
+    y = (np.arange(64, dtype=np.float32) * 0.25).astype(np.float32)  # slope 2
+    p = W.Problem("ties", x, y, 2.0, None, x, 1, np.zeros(1, np.int8), np.ones(1, np.float32))
+    for norm in (1, 2, 3):
+        p.norm = norm
+        g = _consistency(lf, p, 2.0, None)
+        assert g["counts"].tolist() == [0, 0]
+        g = _consistency(lf, p, float(np.float32(1.999)), None)
+        o = oracle.consistency(x, y, norm, M=float(np.float32(1.999)))
+        assert g["counts"].tolist() == [o["viol_up"].sum(), o["viol_lo"].sum()] != [0, 0]
+        g = _consistency(lf, p, float(np.float32(1.999)), None, tol=1.0)
+        assert g["counts"].tolist() == [0, 0]
+
+
+def test_consistency_monotone_local_workload_sampled_rows(lf):
+    """d=4, N=100,000 with per-point M_k and monotone coordinates: every row
+    on the GPU, a seeded sample of rows on the oracle, compared exactly; the
+    totals against the oracle over all rows of a 6,000-point prefix."""
+    p = W.monotone_local(q=1)
+    g = _consistency(lf, p, 0.0, p.Mk)
+    rows = np.sort(np.random.default_rng(9).choice(p.n, 300, replace=False))
+    o = oracle.consistency(p.x, p.y, p.norm, Mk=p.Mk, mon=p.mon, rows=rows)
+    for k in ("slack_up", "slack_lo", "partner_up", "partner_lo"):
+        np.testing.assert_array_equal(g[k][rows], o[k])
+    n2 = 6000
+    p2 = W.Problem("prefix", p.x[:n2], p.y[:n2], 0.0, p.Mk[:n2], p.xq, p.norm, p.mon, p.w)
+    g2 = _consistency(lf, p2, 0.0, p2.Mk)
+    o2 = oracle.consistency(p2.x, p2.y, p.norm, Mk=p2.Mk, mon=p.mon)
+    assert g2["counts"].tolist() == [o2["viol_up"].sum(), o2["viol_lo"].sum()]
+
+
+@pytest.mark.parametrize("norm", [1, 2, 3])
+def test_estimate_global_exact(lf, norm):
+    for n in (2, 3, 500, 1337):
+        p = W.random_problem(500 + n, n=n, q=1, d=4, norm=norm, weighted=(n % 2 == 1))
+        met = lf.Metric(p.d, norm, w=p.w)
+        M64, M32, pair = lf.estimate_M(_t(p.x), _t(p.y), met, mode="global")
+        st, Mo, po = oracle.estimate_M_global(p.x, p.y, norm, w=p.w)
+        assert st == 0
+        assert M64.item() == Mo and tuple(pair.cpu().tolist()) == po
+        f = np.float32(Mo)
+        expect = f if float(f) >= Mo else np.nextafter(f, np.float32(np.inf))
+        assert np.float32(M32.item()) == expect
+
+
+def test_estimate_global_duplicates(lf):
+    x = np.array([[0, 0], [1, 0], [0, 0], [1, 0], [3, 3]], np.float32)
+    y = np.array([0, 1, 0, 1, 2], np.float32)
+    met = lf.Metric(2, "l2")
+    M64, M32, pair = lf.estimate_M(_t(x), _t(y), met)
+    assert pair.cpu().tolist() == [0, 1] and M64.item() == 1.0
+    y2 = np.array([0, 1, 0, 1.5, 2], np.float32)
+    M64, M32, pair = lf.estimate_M(_t(x), _t(y2), met)
+    assert np.isinf(M64.item()) and pair.cpu().tolist() == [1, 3]
+
+
+@pytest.mark.parametrize("norm", [1, 2, 3])
+@pytest.mark.parametrize("K", [1, 5, 16, 32])
+def test_estimate_knn_exact(lf, norm, K):
+    p = W.random_problem(600 + K, n=1111, q=1, d=3, norm=norm, weighted=True)
+    met = lf.Metric(p.d, norm, w=p.w)
+    M64, M32, _ = lf.estimate_M(_t(p.x), _t(p.y), met, mode="knn", knn=K)
+    st, Mo, nb = oracle.estimate_M_knn(p.x, p.y, norm, K=K, w=p.w)
+    np.testing.assert_array_equal(M64.cpu().numpy(), Mo)
+    m32 = M32.cpu().numpy().astype(np.float64)
+    assert np.all(m32 >= Mo)
+
+
+def test_estimate_knn_small_n_and_ties(lf):
+    x = np.array([[0.0], [1.0], [-1.0], [2.0]], np.float32)
+    y = np.array([0.0, 1.0, 3.0, 0.0], np.float32)
+    met = lf.Metric(1, "l1")
+    for K in (1, 2, 3, 16):
+        M64, _, _ = lf.estimate_M(_t(x), _t(y), met, mode="knn", knn=K)
+        st, Mo, _ = oracle.estimate_M_knn(x, y, 1, K=K)
+        np.testing.assert_array_equal(M64.cpu().numpy(), Mo)
+
+
+@pytest.mark.parametrize("norm", [1, 2, 3])
+def test_estimates_monotone_local_workload_sampled(lf, norm):
+    """d=4, N=100,000: kNN-16 constants of sampled rows equal the oracle's;
+    the global slope equals the oracle's slope at the GPU's pair and bounds
+    every sampled row's slopes."""
+    p = W.monotone_local(q=1, norm=norm)
+    met = lf.Metric(4, norm)
+    M64, M32, _ = lf.estimate_M(_t(p.x), _t(p.y), met, mode="knn", knn=16)
+    rows = np.sort(np.random.default_rng(norm).choice(p.n, 48, replace=False))
+    st, Mo, _ = oracle.estimate_M_knn(p.x, p.y, norm, K=16, rows=rows)
+    np.testing.assert_array_equal(M64.cpu().numpy()[rows], Mo)
+    G64, G32, pair = lf.estimate_M(_t(p.x), _t(p.y), met, mode="global")
+    i, k = pair.cpu().tolist()
+    assert 0 <= i < k < p.n
+    sub = np.array([p.x[i], p.x[k]], np.float32)
+    st, Mpair, _ = oracle.estimate_M_global(sub, np.array([p.y[i], p.y[k]], np.float32), norm)
+    assert G64.item() == Mpair
+    # every sampled row's slopes stay below the global maximum
+    for r in rows[:8]:
+        xs = np.concatenate([p.x[r:r + 1], p.x]).astype(np.float32)
+        ys = np.concatenate([p.y[r:r + 1], p.y]).astype(np.float32)
+        # pairs (0, k) only: restrict by evaluating the candidates of row r
+        d = {1: np.abs(p.x.astype(np.float64) - p.x[r]).sum(1),
+             2: np.sqrt(((p.x.astype(np.float64) - p.x[r]) ** 2).sum(1)),
+             3: np.abs(p.x.astype(np.float64) - p.x[r]).max(1)}[norm]
+        dy = np.abs(p.y.astype(np.float64) - p.y[r])
+        msk = d > 0
+        assert np.max(dy[msk] / d[msk]) <= G64.item() * (1 + 1e-12)
