@@ -6,7 +6,8 @@
 // monotonicity, with the zero subgradient at kinks (|.|'(0) = 0,
 // (.)_+'(0) = 0, l2 at distance 0 -> 0, linf -> lowest maximal coordinate).
 //
-// Accumulation of dy / dM: FP32 atomics, or with LIP_FLAG_DETERMINISTIC
+// Accumulation of dy / dM: hardware FP32 atomic adds (global_atomic_add_f32 on
+// device memory, no compare-and-swap loop), or with LIP_FLAG_DETERMINISTIC
 // int64 fixed-point atomics (integer addition is associative, so the sum is
 // independent of the order): pass 1 finds the largest |contribution|, pass 2
 // adds round(contribution * 2^s) with s chosen so that q of them cannot
@@ -89,23 +90,57 @@ __device__ __forceinline__ long long to_fixed(float v, int shift)
     return (long long)rint(ldexp((double)v, shift));
 }
 
+// Adds (v1, v2) into (p1[idx], p2[idx]) for every active lane, first summing
+// the lanes of the wave that share an index (the attaining data points of
+// neighbouring queries coincide often, and same-address atomics serialise).
+// The lane-set of each sum is fixed by the data and the butterfly order by
+// the lane numbers, so a wave's contribution does not depend on timing.
+template <typename T, typename AddFn>
+__device__ __forceinline__ void wave_scatter_add(bool active, int idx, T v1, T v2, T *p1, T *p2,
+                                                 AddFn add)
+{
+    const int lane = threadIdx.x & 63;
+    unsigned long long pending = __ballot(active);
+    while (pending) {
+        const int leader = __ffsll((long long)pending) - 1;
+        const int lidx = __shfl(idx, leader);
+        const bool mine = active && idx == lidx;
+        T s1 = mine ? v1 : T(0), s2 = mine ? v2 : T(0);
+        for (int off = 32; off > 0; off >>= 1) {
+            s1 += __shfl_xor(s1, off);
+            s2 += __shfl_xor(s2, off);
+        }
+        if (lane == leader) {
+            if (p1) add(p1 + lidx, s1);
+            if (p2) add(p2 + lidx, s2);
+        }
+        pending &= ~__ballot(mine);
+        active = active && !mine;
+    }
+}
+
+struct FloatAtomic {
+    __device__ void operator()(float *p, float v) const { unsafeAtomicAdd(p, v); }
+};
 template <int D>
 __global__ void __launch_bounds__(256) backward_kernel(BwdArgs a)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    float dm_local = 0.0f;
     // indices outside [0, n) (not produced by the forward) are skipped
     const bool valid = j < a.q && a.arg_up[j] >= 0 && a.arg_up[j] < a.n && a.arg_lo[j] >= 0 &&
                        a.arg_lo[j] < a.n;
+    int ia = 0, ib = 0;
+    float Gu = 0.0f, Gl = 0.0f, cu_m = 0.0f, cl_m = 0.0f;
     if (valid) {
-        const int32_t ia = a.arg_up[j], ib = a.arg_lo[j];
+        ia = a.arg_up[j];
+        ib = a.arg_lo[j];
         const float *xj = a.xq + j * D;
         float xr[D];
 #pragma unroll
         for (int i = 0; i < D; ++i) xr[i] = xj[i];
         const float hg = a.dg ? 0.5f * a.dg[j] : 0.0f;
-        const float Gu = hg + (a.dh_up ? a.dh_up[j] : 0.0f);
-        const float Gl = hg + (a.dh_lo ? a.dh_lo[j] : 0.0f);
+        Gu = hg + (a.dh_up ? a.dh_up[j] : 0.0f);
+        Gl = hg + (a.dh_lo ? a.dh_lo[j] : 0.0f);
         float gu[D], gl[D];
         const float du = dist_and_grad<D>(a, xr, a.x + (int64_t)ia * D, true, gu);
         const float dl = dist_and_grad<D>(a, xr, a.x + (int64_t)ib * D, false, gl);
@@ -115,51 +150,56 @@ __global__ void __launch_bounds__(256) backward_kernel(BwdArgs a)
 #pragma unroll
             for (int i = 0; i < D; ++i) a.dxq[j * D + i] = Gu * Ma * gu[i] - Gl * Mb * gl[i];
         }
-        const float cu_m = Gu * du, cl_m = -(Gl * dl);
-        if (a.fixed == 0) {
-            if (a.dy) {
-                atomicAdd(a.dy + ia, Gu);
-                atomicAdd(a.dy + ib, Gl);
-            }
-            if (a.dM) {
-                if (a.Mk) {
-                    atomicAdd(a.dM + ia, cu_m);
-                    atomicAdd(a.dM + ib, cl_m);
-                } else {
-                    dm_local = cu_m + cl_m;
-                }
-            }
-        } else if (a.fixed == 1) {
-            float mx = fmaxf(fmaxf(fabsf(Gu), fabsf(Gl)), fmaxf(fabsf(cu_m), fabsf(cl_m)));
-            atomicMax(a.maxbits, __float_as_uint(mx));
-        } else {
-            const float mx = __uint_as_float(*a.maxbits);
-            // 2^shift * mx * 2q < 2^63: no int64 overflow
-            int e = 0;
-            frexpf(mx > 0.0f ? mx : 1.0f, &e);
-            int qbits = 0;
-            frexp((double)(a.q > 0 ? a.q : 1), &qbits);
-            const int shift = 61 - e - qbits;
-            if (a.dy) {
-                atomicAdd(a.acc_y + ia, (unsigned long long)to_fixed(Gu, shift));
-                atomicAdd(a.acc_y + ib, (unsigned long long)to_fixed(Gl, shift));
-            }
-            if (a.dM) {
-                if (a.Mk) {
-                    atomicAdd(a.acc_m + ia, (unsigned long long)to_fixed(cu_m, shift));
-                    atomicAdd(a.acc_m + ib, (unsigned long long)to_fixed(cl_m, shift));
-                } else {
-                    atomicAdd(a.acc_m, (unsigned long long)(to_fixed(cu_m, shift) +
-                                                            to_fixed(cl_m, shift)));
-                }
-            }
-        }
+        cu_m = Gu * du;
+        cl_m = -(Gl * dl);
     }
-    if (a.fixed == 0 && a.dM && !a.Mk) {
-        // wave reduction of the global-M contributions, one atomic per wave
-        float v = dm_local;
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-        if ((threadIdx.x & 63) == 0) atomicAdd(a.dM, v);
+    if (a.fixed == 0) {
+        float *py = a.dy, *pm = (a.dM && a.Mk) ? a.dM : nullptr;
+        if (py || pm) {
+            wave_scatter_add<float>(valid, ia, Gu, cu_m, py, pm, FloatAtomic());
+            wave_scatter_add<float>(valid, ib, Gl, cl_m, py, pm, FloatAtomic());
+        }
+        if (a.dM && !a.Mk) {
+            // global M: one sum per wave
+            float v = cu_m + cl_m;
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+            if ((threadIdx.x & 63) == 0) unsafeAtomicAdd(a.dM, v);
+        }
+    } else if (a.fixed == 1) {
+        if (valid) {
+            const float mx = fmaxf(fmaxf(fabsf(Gu), fabsf(Gl)), fmaxf(fabsf(cu_m), fabsf(cl_m)));
+            atomicMax(a.maxbits, __float_as_uint(mx));
+        }
+    } else {
+        const float mx = __uint_as_float(*a.maxbits);
+        // 2^shift * mx * 2q < 2^63: no int64 overflow
+        int e = 0;
+        frexpf(mx > 0.0f ? mx : 1.0f, &e);
+        int qbits = 0;
+        frexp((double)(a.q > 0 ? a.q : 1), &qbits);
+        const int shift = 61 - e - qbits;
+        const long long fu = valid ? to_fixed(Gu, shift) : 0, fl = valid ? to_fixed(Gl, shift) : 0;
+        const long long mu = valid ? to_fixed(cu_m, shift) : 0;
+        const long long ml = valid ? to_fixed(cl_m, shift) : 0;
+        unsigned long long *py = a.dy ? a.acc_y : nullptr;
+        unsigned long long *pm = (a.dM && a.Mk) ? a.acc_m : nullptr;
+        if (py || pm) {
+            wave_scatter_add<long long>(valid, ia, fu, mu, (long long *)py, (long long *)pm,
+                                        [](long long *p, long long v) {
+                                            atomicAdd((unsigned long long *)p,
+                                                      (unsigned long long)v);
+                                        });
+            wave_scatter_add<long long>(valid, ib, fl, ml, (long long *)py, (long long *)pm,
+                                        [](long long *p, long long v) {
+                                            atomicAdd((unsigned long long *)p,
+                                                      (unsigned long long)v);
+                                        });
+        }
+        if (a.dM && !a.Mk) {
+            long long v = mu + ml;
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+            if ((threadIdx.x & 63) == 0) atomicAdd(a.acc_m, (unsigned long long)v);
+        }
     }
 }
 

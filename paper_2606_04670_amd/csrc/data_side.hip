@@ -1,332 +1,153 @@
-// Data-side passes over all pairs of data points, in FP64:
-//  * lip_consistency - the Lipschitz condition of Sec. 1 with the
-//    monotonicity constraints of Sec. 4.1, in the pairwise form of
-//    Eqs. (5)-(6) with zero corrections;
-//  * lip_estimate_M  - the largest pairwise slope (Sec. 5) and the per-datum
-//    slope over the K nearest data (Sec. 4.3, scalar form).
-//
-// Every pair is evaluated in double precision from the FP32 inputs with a
-// fixed operation order: per coordinate in index order, delta = x_i - x_k,
-// the component (|delta|, or a positive part on a monotone coordinate) times
-// the weight, then accumulated (sum, sum of squares, or max) from 0; l2 takes
-// the square root; bounds are y_k + M_k * dist (product, then sum).  All of
-// these operations are correctly rounded, so the decisions that produce the
-// integer outputs (violation counts, partners, neighbour ranks) are
-// reproducible by any implementation that follows the same order.
-//
-// Data are first staged as FP64 records [x_0 .. x_{D-1} | y | M] so that the
-// column loop reads them with scalar loads and the VALU uses them straight
-// from SGPR pairs.  A lane owns R rows; columns are streamed.
-#include <climits>
-#include <float.h>
-
-#include "host_common.hpp"
+// Host entry points of the FP64 data-side passes (lip_consistency,
+// lip_estimate_M) and their small helper kernels; the pair kernels are in
+// data_side.hpp, instantiated per norm in data_side_{l1,l2,linf}.hip.
+#include "data_side.hpp"
 
 namespace lip {
 
-struct DsArgs {
-    const double *rec;  // staged [n][D + 2]
-    int64_t n;
-    int32_t norm;
-    int32_t has_w;
-    double w[kMaxDim];
-    int32_t kind[kMaxDim];  // 0 free, 1 increasing, -1 decreasing
-    double tol;
-    // consistency outputs
-    double *slack_up, *slack_lo;
-    int32_t *partner_up, *partner_lo;
-    unsigned long long *counts;  // [2]
-    // estimate-M outputs
-    double *row_best;     // [n] per-row best slope (global mode)
-    int32_t *row_arg;     // [n] its column, -1 none
-    int32_t *row_dup;     // [n] first coincident column with different y, -1 none
-    int32_t knn;
-    double *M64;
-    float *M32;
+// d-major FP64 staging: X[j * npad + k]; padded columns hold zeros and are
+// masked out by every kernel.  Coordinates with sign -1 (monotone
+// decreasing) are negated, which is exact and turns them into increasing
+// ones: the pair components (x_i - x_k)_+ and (x_k - x_i)_+ swap roles.
+struct Signs {
+    float s[kMaxDim];
 };
 
 template <int D>
 __global__ void stage64_kernel(const float *x, const float *y, const float *Mk, float M, int64_t n,
-                               double *out)
+                               int64_t npad, Signs sg, double *X)
 {
-    constexpr int S = D + 2;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < npad; k += stride) {
+        const bool in = k < n;
 #pragma unroll
-        for (int j = 0; j < D; ++j) out[k * S + j] = (double)x[k * D + j];
-        out[k * S + D] = (double)y[k];
-        out[k * S + D + 1] = Mk ? (double)Mk[k] : (double)M;
+        for (int j = 0; j < D; ++j)
+            X[(int64_t)j * npad + k] = in ? (double)(sg.s[j] * x[k * D + j]) : 0.0;
+        X[(int64_t)D * npad + k] = in ? (double)y[k] : 0.0;
+        X[(int64_t)(D + 1) * npad + k] = in ? (Mk ? (double)Mk[k] : (double)M) : 0.0;
     }
 }
 
-// Directional distances between row point a and column point b, FP64, the
-// fixed order described above.  With sym the monotonicity is ignored.
-template <int D, bool sym>
-__device__ __forceinline__ void dist64(const DsArgs &A, const double (&a)[D], const double *b,
-                                       double &su, double &sl)
+static hipError_t launch_stage64(int d, const float *x, const float *y, const float *Mk, float M,
+                                 int64_t n, int64_t npad, const Signs &sg, double *X, hipStream_t s)
 {
-    su = 0.0;
-    sl = 0.0;
-#pragma unroll
-    for (int i = 0; i < D; ++i) {
-        const double dl = a[i] - b[i];
-        double cu, cl;
-        const int kd = sym ? 0 : A.kind[i];
-        if (kd == 0) {
-            cu = fabs(dl);
-            cl = cu;
-        } else if (kd > 0) {
-            cu = dl > 0.0 ? dl : 0.0;
-            cl = dl < 0.0 ? -dl : 0.0;
-        } else {
-            cu = dl < 0.0 ? -dl : 0.0;
-            cl = dl > 0.0 ? dl : 0.0;
-        }
-        if (A.has_w) {
-            cu = A.w[i] * cu;
-            cl = A.w[i] * cl;
-        }
-        if (A.norm == 1) {
-            su = su + cu;
-            if (!sym) sl = sl + cl;
-        } else if (A.norm == 2) {
-            su = su + cu * cu;
-            if (!sym) sl = sl + cl * cl;
-        } else {
-            su = cu > su ? cu : su;
-            if (!sym) sl = cl > sl ? cl : sl;
-        }
+    int64_t g = (npad + 255) / 256;
+    if (g > 65536) g = 65536;
+    switch (d) {
+#define LIP_ST_CASE(DD)                                                                          \
+    case DD:                                                                                     \
+        hipLaunchKernelGGL(stage64_kernel<DD>, dim3((unsigned)g), dim3(256), 0, s, x, y, Mk, M, \
+                           n, npad, sg, X);                                                      \
+        break;
+        LIP_ST_CASE(1) LIP_ST_CASE(2) LIP_ST_CASE(3) LIP_ST_CASE(4)
+        LIP_ST_CASE(5) LIP_ST_CASE(6) LIP_ST_CASE(7) LIP_ST_CASE(8)
+        LIP_ST_CASE(9) LIP_ST_CASE(10) LIP_ST_CASE(11) LIP_ST_CASE(12)
+        LIP_ST_CASE(13) LIP_ST_CASE(14) LIP_ST_CASE(15) LIP_ST_CASE(16)
+#undef LIP_ST_CASE
+    default: return hipErrorInvalidValue;
     }
-    if (sym) sl = su;
+    return hipGetLastError();
 }
-
-typedef const double __attribute__((address_space(4))) *cdouble_ptr;
-
-// ---- consistency -------------------------------------------------------------
 
 __global__ void zero_counts_kernel(unsigned long long *c)
 {
     if (threadIdx.x < 2) c[threadIdx.x] = 0ull;
 }
 
-constexpr int kDsRows = 2;
-
-template <int D, bool self_check>
-__device__ __forceinline__ void consistency_cols(const DsArgs &A, cdouble_ptr rec, int64_t k0,
-                                                 int64_t k1, const double (&xr)[kDsRows][D],
-                                                 const double (&yr)[kDsRows],
-                                                 const int64_t (&ir)[kDsRows], double (&bu)[kDsRows],
-                                                 double (&bl)[kDsRows], int (&pu)[kDsRows],
-                                                 int (&pl)[kDsRows], int (&cu)[kDsRows],
-                                                 int (&cl)[kDsRows])
+__global__ void consistency_combine_kernel(DsArgs A)
 {
-    constexpr int S = D + 2;
-    for (int64_t k = k0; k < k1; ++k) {
-        double xk[S];
-#pragma unroll
-        for (int j = 0; j < S; ++j) xk[j] = rec[k * S + j];
-        const double yk = xk[D], mk = xk[D + 1];
-#pragma unroll
-        for (int r = 0; r < kDsRows; ++r) {
-            double du, dl;
-            dist64<D, false>(A, xr[r], xk, du, dl);
-            if (A.norm == 2) {
-                du = sqrt(du);
-                dl = sqrt(dl);
-            }
-            const double tu = (yk + mk * du) - yr[r];
-            const double tl = yr[r] - (yk - mk * dl);
-            const bool ok = !self_check || (k != ir[r]);
-            if (ok && tu < bu[r]) {
-                bu[r] = tu;
-                pu[r] = (int)k;
-            }
-            if (ok && tl < bl[r]) {
-                bl[r] = tl;
-                pl[r] = (int)k;
-            }
-            cu[r] += (ok && tu < -A.tol) ? 1 : 0;
-            cl[r] += (ok && tl < -A.tol) ? 1 : 0;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    double bu = __builtin_inf(), bl = __builtin_inf();
+    int pu = -1, pl = -1;
+    for (int c = 0; c < A.n_chunks; ++c) {
+        const int64_t o = (int64_t)c * A.n + i;
+        if (A.pv_up[o] < bu) {
+            bu = A.pv_up[o];
+            pu = A.pi_up[o];
+        }
+        if (A.pv_lo[o] < bl) {
+            bl = A.pv_lo[o];
+            pl = A.pi_lo[o];
         }
     }
+    if (A.slack_up) A.slack_up[i] = bu;
+    if (A.slack_lo) A.slack_lo[i] = bl;
+    if (A.partner_up) A.partner_up[i] = pu;
+    if (A.partner_lo) A.partner_lo[i] = pl;
 }
 
-template <int D>
-__global__ void __launch_bounds__(256) consistency_kernel(DsArgs A)
+// Single-workgroup reduction over all (chunk, row) slope partials.  Order: a
+// coincident pair with different values (lowest i, then lowest k) wins
+// outright; otherwise the largest slope, then the lowest i, then the lowest
+// k.  Every wave writes all of its rows for its chunk (a chunk left of the
+// rows has no usable column: best -1, arg -1, dup -1).
+struct SlopeKey {
+    double v;
+    long long i, k, di, dk;
+};
+
+__device__ __forceinline__ bool better_dup(const SlopeKey &a, const SlopeKey &b)
 {
-    constexpr int S = D + 2;
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t r0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + wave) * (64 * kDsRows);
-    if (r0 >= A.n) return;
-    int64_t r1 = r0 + 64 * kDsRows;
-    r1 = r1 < A.n ? r1 : A.n;
-    double xr[kDsRows][D], yr[kDsRows];
-    int64_t ir[kDsRows];
-    double bu[kDsRows], bl[kDsRows];
-    int pu[kDsRows], pl[kDsRows], cu[kDsRows], cl[kDsRows];
-#pragma unroll
-    for (int r = 0; r < kDsRows; ++r) {
-        int64_t i = r0 + r * 64 + lane;
-        ir[r] = i;
-        i = i < A.n ? i : A.n - 1;
-#pragma unroll
-        for (int j = 0; j < D; ++j) xr[r][j] = A.rec[i * S + j];
-        yr[r] = A.rec[i * S + D];
-        bu[r] = __builtin_inf();
-        bl[r] = __builtin_inf();
-        pu[r] = pl[r] = -1;
-        cu[r] = cl[r] = 0;
-    }
-    const cdouble_ptr rec = (cdouble_ptr)(A.rec);
-    consistency_cols<D, false>(A, rec, 0, r0, xr, yr, ir, bu, bl, pu, pl, cu, cl);
-    consistency_cols<D, true>(A, rec, r0, r1, xr, yr, ir, bu, bl, pu, pl, cu, cl);
-    consistency_cols<D, false>(A, rec, r1, A.n, xr, yr, ir, bu, bl, pu, pl, cu, cl);
-    unsigned long long tu = 0, tl = 0;
-#pragma unroll
-    for (int r = 0; r < kDsRows; ++r) {
-        const int64_t i = ir[r];
-        if (i >= A.n) continue;
-        if (A.slack_up) A.slack_up[i] = bu[r];
-        if (A.slack_lo) A.slack_lo[i] = bl[r];
-        if (A.partner_up) A.partner_up[i] = pu[r];
-        if (A.partner_lo) A.partner_lo[i] = pl[r];
-        tu += (unsigned long long)cu[r];
-        tl += (unsigned long long)cl[r];
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-        tu += __shfl_xor(tu, off);
-        tl += __shfl_xor(tl, off);
-    }
-    if (lane == 0) {
-        atomicAdd(A.counts, tu);
-        atomicAdd(A.counts + 1, tl);
-    }
+    if (a.di < 0) return false;
+    if (b.di < 0) return true;
+    return a.di < b.di || (a.di == b.di && a.dk < b.dk);
 }
 
-// ---- global M: max over i < k of |y_i - y_k| / dist ------------------------------
-
-constexpr int kMRows = 2;
-
-template <int D, bool diag>
-__device__ __forceinline__ void slope_cols(const DsArgs &A, cdouble_ptr rec, int64_t k0, int64_t k1,
-                                           const double (&xr)[kMRows][D], const double (&yr)[kMRows],
-                                           const int64_t (&ir)[kMRows], double (&best)[kMRows],
-                                           int (&arg)[kMRows], int (&dup)[kMRows])
+__device__ __forceinline__ bool better_slope(const SlopeKey &a, const SlopeKey &b)
 {
-    constexpr int S = D + 2;
-    for (int64_t k = k0; k < k1; ++k) {
-        double xk[S];
-#pragma unroll
-        for (int j = 0; j < D + 1; ++j) xk[j] = rec[k * S + j];
-#pragma unroll
-        for (int r = 0; r < kMRows; ++r) {
-            if (diag && !(k > ir[r])) continue;
-            double du, dl;
-            dist64<D, true>(A, xr[r], xk, du, dl);
-            if (A.norm == 2) du = sqrt(du);
-            const double dy = fabs(yr[r] - xk[D]);
-            if (du == 0.0) {
-                if (dy != 0.0 && dup[r] < 0) dup[r] = (int)k;
-                continue;
-            }
-            // dy / du > best  <=>  dy - best * du > 0, decided exactly by the
-            // sign of one fused multiply-add; only then form the quotient.
-            if (best[r] < 0.0 || fma(-best[r], du, dy) > 0.0) {
-                const double s = dy / du;
-                if (s > best[r]) {
-                    best[r] = s;
-                    arg[r] = (int)k;
-                }
-            }
-        }
-    }
+    if (a.i < 0) return false;
+    if (b.i < 0) return true;
+    if (a.v != b.v) return a.v > b.v;
+    return a.i < b.i || (a.i == b.i && a.k < b.k);
 }
 
-template <int D>
-__global__ void __launch_bounds__(256) slope_kernel(DsArgs A)
-{
-    constexpr int S = D + 2;
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t r0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + wave) * (64 * kMRows);
-    if (r0 >= A.n) return;
-    int64_t r1 = r0 + 64 * kMRows;
-    r1 = r1 < A.n ? r1 : A.n;
-    double xr[kMRows][D], yr[kMRows], best[kMRows];
-    int64_t ir[kMRows];
-    int arg[kMRows], dup[kMRows];
-#pragma unroll
-    for (int r = 0; r < kMRows; ++r) {
-        int64_t i = r0 + r * 64 + lane;
-        ir[r] = i;
-        i = i < A.n ? i : A.n - 1;
-#pragma unroll
-        for (int j = 0; j < D; ++j) xr[r][j] = A.rec[i * S + j];
-        yr[r] = A.rec[i * S + D];
-        best[r] = -1.0;
-        arg[r] = -1;
-        dup[r] = -1;
-    }
-    const cdouble_ptr rec = (cdouble_ptr)(A.rec);
-    slope_cols<D, true>(A, rec, r0, r1, xr, yr, ir, best, arg, dup);
-    slope_cols<D, false>(A, rec, r1, A.n, xr, yr, ir, best, arg, dup);
-#pragma unroll
-    for (int r = 0; r < kMRows; ++r) {
-        const int64_t i = ir[r];
-        if (i >= A.n) continue;
-        A.row_best[i] = best[r];
-        A.row_arg[i] = arg[r];
-        A.row_dup[i] = dup[r];
-    }
-}
-
-// Single-workgroup reduction of the per-row results: the first row (lowest
-// i) with a coincident pair of different values wins outright; otherwise the
-// largest slope, lowest i on ties (each row already holds its lowest k).
 __global__ void slope_reduce_kernel(DsArgs A, int64_t *pair)
 {
-    __shared__ double sb[1024];
-    __shared__ long long si[1024];
-    __shared__ long long sd[1024];
-    double best = -1.0;
-    long long bi = -1, di = LLONG_MAX;
-    for (int64_t i = threadIdx.x; i < A.n; i += blockDim.x) {
-        if (A.row_dup[i] >= 0 && i < di) di = i;
-        if (A.row_arg[i] >= 0 && (A.row_best[i] > best || (A.row_best[i] == best && i < bi))) {
-            best = A.row_best[i];
-            bi = i;
+    __shared__ SlopeKey sk[1024];
+    SlopeKey me{-1.0, -1, -1, -1, -1};
+    const int64_t total = (int64_t)A.n_chunks * A.n;
+    for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
+        const int64_t i = e % A.n;
+        const SlopeKey cand{A.row_best[e], A.row_arg[e] >= 0 ? i : -1, A.row_arg[e], -1, -1};
+        if (better_slope(cand, me)) {
+            me.v = cand.v;
+            me.i = cand.i;
+            me.k = cand.k;
+        }
+        if (A.row_dup[e] >= 0) {
+            const SlopeKey dd{0.0, -1, -1, i, A.row_dup[e]};
+            if (better_dup(dd, me)) {
+                me.di = dd.di;
+                me.dk = dd.dk;
+            }
         }
     }
-    sb[threadIdx.x] = best;
-    si[threadIdx.x] = bi;
-    sd[threadIdx.x] = di;
+    sk[threadIdx.x] = me;
     __syncthreads();
     for (int s = blockDim.x / 2; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s) {
-            const int o = threadIdx.x + s;
-            if (sd[o] < sd[threadIdx.x]) sd[threadIdx.x] = sd[o];
-            const bool take = si[o] >= 0 &&
-                              (si[threadIdx.x] < 0 || sb[o] > sb[threadIdx.x] ||
-                               (sb[o] == sb[threadIdx.x] && si[o] < si[threadIdx.x]));
-            if (take) {
-                sb[threadIdx.x] = sb[o];
-                si[threadIdx.x] = si[o];
-            }
+            const SlopeKey a = sk[threadIdx.x], b = sk[threadIdx.x + s];
+            SlopeKey r = better_slope(b, a) ? b : a;
+            const SlopeKey &dsrc = better_dup(b, a) ? b : a;
+            r.di = dsrc.di;
+            r.dk = dsrc.dk;
+            sk[threadIdx.x] = r;
         }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
+        const SlopeKey r = sk[0];
         double M;
         long long p0, p1;
-        if (sd[0] != LLONG_MAX) {
+        if (r.di >= 0) {
             M = __builtin_inf();
-            p0 = sd[0];
-            p1 = A.row_dup[sd[0]];
-        } else if (si[0] >= 0) {
-            M = sb[0];
-            p0 = si[0];
-            p1 = A.row_arg[si[0]];
+            p0 = r.di;
+            p1 = r.dk;
+        } else if (r.i >= 0) {
+            M = r.v;
+            p0 = r.i;
+            p1 = r.k;
         } else {
             M = 0.0;
             p0 = p1 = -1;
@@ -344,154 +165,58 @@ __global__ void slope_reduce_kernel(DsArgs A, int64_t *pair)
     }
 }
 
-// ---- local M from the K nearest data ---------------------------------------------
-
-// Keeps the K smallest (key, index) of the row in ascending order.  Columns
-// arrive in increasing index order, so a strict comparison ranks the lower
-// index first among equal keys.
-template <int K>
-__device__ __forceinline__ void knn_insert(double (&key)[K], int (&idx)[K], double kv, int j)
-{
-    key[K - 1] = kv;
-    idx[K - 1] = j;
-#pragma unroll
-    for (int t = K - 1; t > 0; --t) {
-        const bool sw = key[t] < key[t - 1];
-        const double a = key[t], b = key[t - 1];
-        const int ia = idx[t], ib = idx[t - 1];
-        key[t] = sw ? b : a;
-        key[t - 1] = sw ? a : b;
-        idx[t] = sw ? ib : ia;
-        idx[t - 1] = sw ? ia : ib;
-    }
-}
-
-template <int D, int K>
-__global__ void __launch_bounds__(256) knn_kernel(DsArgs A)
-{
-    constexpr int S = D + 2;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t ic = i < A.n ? i : A.n - 1;
-    double xr[D];
-#pragma unroll
-    for (int j = 0; j < D; ++j) xr[j] = A.rec[ic * S + j];
-    double key[K];
-    int idx[K];
-#pragma unroll
-    for (int t = 0; t < K; ++t) {
-        key[t] = __builtin_inf();
-        idx[t] = -1;
-    }
-    // Only the first knn (<= K) slots matter; thr is the knn-th smallest key.
-    const int kk = A.knn;
-    double thr = __builtin_inf();
-    const cdouble_ptr rec = (cdouble_ptr)(A.rec);
-    for (int64_t k = 0; k < A.n; ++k) {
-        double xk[D];
-#pragma unroll
-        for (int j = 0; j < D; ++j) xk[j] = rec[k * S + j];
-        double du, dl;
-        dist64<D, true>(A, xr, xk, du, dl);
-        // rank by the distance (l2: by the sum of squares)
-        if (k != ic && du < thr) {
-            knn_insert<K>(key, idx, du, (int)k);
-#pragma unroll
-            for (int t = 0; t < K; ++t)
-                if (t == kk - 1) thr = key[t];
-        }
-    }
-    if (i >= A.n) return;
-    const double yi = A.rec[ic * S + D];
-    double best = 0.0;
-#pragma unroll
-    for (int t = 0; t < K; ++t) {
-        if (t >= kk || idx[t] < 0) continue;
-        const double *xk = A.rec + (int64_t)idx[t] * S;
-        double du, dl;
-        double xx[D];
-#pragma unroll
-        for (int j = 0; j < D; ++j) xx[j] = xk[j];
-        dist64<D, true>(A, xr, xx, du, dl);
-        if (A.norm == 2) du = sqrt(du);
-        const double dy = fabs(yi - xk[D]);
-        if (du == 0.0) {
-            if (dy != 0.0) best = __builtin_inf();
-            continue;
-        }
-        const double s = dy / du;
-        if (s > best) best = s;
-    }
-    if (A.M64) A.M64[i] = best;
-    if (A.M32) {
-        float f = (float)best;
-        if ((double)f < best) f = nextafterf(f, __builtin_inff());
-        A.M32[i] = f;
-    }
-}
-
-// ---- host side ------------------------------------------------------------------
+static int64_t ds_npad(int64_t n) { return (n + kDsTile - 1) / kDsTile * kDsTile; }
 
 size_t data_side_ws_bytes(int64_t n, int d)
 {
-    return align_up((size_t)n * (size_t)(d + 2) * 8, 256) + align_up((size_t)n * 16, 256) + 512;
+    const size_t staged = align_up((size_t)ds_npad(n) * (size_t)(d + 2) * 8, 256);
+    const size_t cons = (size_t)kDsMaxChunks * (size_t)n * 24;
+    const size_t knn = (size_t)kKnnMaxChunks * (size_t)n * LIP_MAX_KNN * 12;
+    const size_t part = cons > knn ? cons : knn;
+    return staged + align_up(part, 256) + 4096;
 }
 
-struct DsLaunchers {
-    void (*stage)(const float *, const float *, const float *, float, int64_t, double *, hipStream_t);
-    void (*consistency)(const DsArgs &, dim3, dim3, hipStream_t);
-    void (*slope)(const DsArgs &, dim3, dim3, hipStream_t);
-    void (*knn16)(const DsArgs &, dim3, dim3, hipStream_t);
-    void (*knn32)(const DsArgs &, dim3, dim3, hipStream_t);
-};
-
-template <int D>
-static DsLaunchers ds_launchers()
+static bool get_ds(const MetricInfo &mi, bool hasw, DsLaunchers *L)
 {
-    DsLaunchers L;
-    L.stage = [](const float *x, const float *y, const float *Mk, float M, int64_t n, double *out,
-                 hipStream_t s) {
-        int64_t g = (n + 255) / 256;
-        if (g > 65536) g = 65536;
-        hipLaunchKernelGGL(stage64_kernel<D>, dim3((unsigned)g), dim3(256), 0, s, x, y, Mk, M, n, out);
-    };
-    L.consistency = [](const DsArgs &a, dim3 g, dim3 b, hipStream_t s) {
-        hipLaunchKernelGGL(consistency_kernel<D>, g, b, 0, s, a);
-    };
-    L.slope = [](const DsArgs &a, dim3 g, dim3 b, hipStream_t s) {
-        hipLaunchKernelGGL(slope_kernel<D>, g, b, 0, s, a);
-    };
-    L.knn16 = [](const DsArgs &a, dim3 g, dim3 b, hipStream_t s) {
-        hipLaunchKernelGGL((knn_kernel<D, 16>), g, b, 0, s, a);
-    };
-    L.knn32 = [](const DsArgs &a, dim3 g, dim3 b, hipStream_t s) {
-        hipLaunchKernelGGL((knn_kernel<D, 32>), g, b, 0, s, a);
-    };
-    return L;
-}
-
-static bool get_ds(int d, DsLaunchers *L)
-{
-    switch (d) {
-#define LIP_DS_CASE(DD) \
-    case DD: *L = ds_launchers<DD>(); return true;
-        LIP_DS_CASE(1) LIP_DS_CASE(2) LIP_DS_CASE(3) LIP_DS_CASE(4)
-        LIP_DS_CASE(5) LIP_DS_CASE(6) LIP_DS_CASE(7) LIP_DS_CASE(8)
-        LIP_DS_CASE(9) LIP_DS_CASE(10) LIP_DS_CASE(11) LIP_DS_CASE(12)
-        LIP_DS_CASE(13) LIP_DS_CASE(14) LIP_DS_CASE(15) LIP_DS_CASE(16)
-#undef LIP_DS_CASE
+    switch (mi.norm) {
+    case LIP_L1: return ds_table_l1(mi.d, hasw, L);
+    case LIP_L2: return ds_table_l2(mi.d, hasw, L);
+    case LIP_LINF: return ds_table_linf(mi.d, hasw, L);
     default: return false;
     }
 }
 
-static void fill_ds_metric(const MetricInfo &mi, bool use_mon, DsArgs *A)
+static bool fill_ds_metric(const MetricInfo &mi, bool use_mon, DsArgs *A, Signs *sg)
 {
-    A->norm = mi.norm;
-    A->has_w = 0;
+    bool hasw = false;
     for (int i = 0; i < kMaxDim; ++i) {
         A->w[i] = i < mi.d ? mi.w[i] : 1.0;
-        A->kind[i] = (use_mon && i < mi.d) ? mi.mon[i] : 0;
-        if (i < mi.d && mi.w[i] != 1.0) A->has_w = 1;
+        const int m = (use_mon && i < mi.d) ? mi.mon[i] : 0;
+        A->fsel[i] = m != 0 ? 0.0 : 1.0;
+        sg->s[i] = m < 0 ? -1.0f : 1.0f;
+        if (i < mi.d && mi.w[i] != 1.0) hasw = true;
     }
+    return hasw;
+}
+
+// Column split: enough waves to fill the chip, chunks a multiple of the
+// partner tile, at most max_chunks of them.
+static void choose_chunks(int64_t n, int rows_per_wave, int max_chunks, DsArgs *A)
+{
+    const int64_t row_waves = (n + rows_per_wave - 1) / rows_per_wave;
+    int64_t nc = (kDsTargetWaves + row_waves - 1) / row_waves;
+    if (nc > max_chunks) nc = max_chunks;
+    if (nc < 1) nc = 1;
+    int64_t cols = (n + nc - 1) / nc;
+    cols = (cols + kDsTile - 1) / kDsTile * kDsTile;
+    A->chunk_cols = cols;
+    A->n_chunks = (int)((n + cols - 1) / cols);
+}
+
+static unsigned grid_for_rows(int64_t n, int rows_per_wave, int n_chunks)
+{
+    const int64_t waves = (n + rows_per_wave - 1) / rows_per_wave;
+    return (unsigned)(((waves + 3) / 4) * n_chunks);
 }
 
 }  // namespace lip
@@ -508,7 +233,7 @@ extern "C" lip_status lip_consistency(const lip_metric *metric, const float *x, 
     lip_status st = parse_metric(metric, &mi);
     if (st != LIP_OK) return st;
     if (flags & ~LIP_FLAG_CHECK_FINITE) return LIP_E_ARG;
-    if (n <= 0 || n > kMaxIndex) return LIP_E_SHAPE;
+    if (n <= 0 || n > kMaxIndex - kDsTile) return LIP_E_SHAPE;
     if (!x || !y || !counts) return LIP_E_ARG;
     if (!Mk && (!(M >= 0.0f) || !__builtin_isfinite(M))) return LIP_E_VALUE;
     if (!(tol >= 0.0) || !__builtin_isfinite(tol)) return LIP_E_VALUE;
@@ -520,23 +245,35 @@ extern "C" lip_status lip_consistency(const lip_metric *metric, const float *x, 
         st = check_finite(arr, cnt, 3, ws, s);
         if (st != LIP_OK) return st;
     }
-    DsLaunchers L;
-    if (!get_ds(mi.d, &L)) return LIP_E_UNSUPPORTED;
     DsArgs A{};
-    A.rec = (const double *)ws;
+    Signs sg{};
+    const bool hasw = fill_ds_metric(mi, true, &A, &sg);
+    DsLaunchers L;
+    if (!get_ds(mi, hasw, &L)) return LIP_E_UNSUPPORTED;
     A.n = n;
+    A.npad = ds_npad(n);
+    A.X = (const double *)ws;
     A.tol = tol;
-    fill_ds_metric(mi, true, &A);
+    choose_chunks(n, 64 * kDsRows, kDsMaxChunks, &A);
+    char *p = (char *)ws + align_up((size_t)A.npad * (size_t)(mi.d + 2) * 8, 256);
+    const size_t e = (size_t)A.n_chunks * (size_t)n;
+    A.pv_up = (double *)p;
+    A.pv_lo = A.pv_up + e;
+    A.pi_up = (int32_t *)(A.pv_lo + e);
+    A.pi_lo = A.pi_up + e;
     A.slack_up = slack_up;
     A.slack_lo = slack_lo;
     A.partner_up = partner_up;
     A.partner_lo = partner_lo;
     A.counts = (unsigned long long *)counts;
-    L.stage(x, y, Mk, M, n, (double *)ws, s);
+    if (launch_stage64(mi.d, x, y, Mk, M, n, A.npad, sg, (double *)ws, s) != hipSuccess)
+        return LIP_E_DEVICE;
     hipLaunchKernelGGL(zero_counts_kernel, dim3(1), dim3(64), 0, s, A.counts);
-    const int64_t waves = (n + 64 * kDsRows - 1) / (64 * kDsRows);
-    const int64_t blocks = (waves + 3) / 4;
-    L.consistency(A, dim3((unsigned)blocks), dim3(256), s);
+    (mi.dm > 0 ? L.consistency_mon : L.consistency)(
+        A, dim3(grid_for_rows(n, 64 * kDsRows, A.n_chunks)), dim3(256), s);
+    if (A.n_chunks > 1 && (slack_up || slack_lo || partner_up || partner_lo))
+        hipLaunchKernelGGL(consistency_combine_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256),
+                           0, s, A);
     return dev_status(hipGetLastError());
 }
 
@@ -549,7 +286,7 @@ extern "C" lip_status lip_estimate_M(const lip_metric *metric, const float *x, c
     lip_status st = parse_metric(metric, &mi);
     if (st != LIP_OK) return st;
     if (flags & ~LIP_FLAG_CHECK_FINITE) return LIP_E_ARG;
-    if (n <= 0 || n > kMaxIndex) return LIP_E_SHAPE;
+    if (n <= 0 || n > kMaxIndex - kDsTile) return LIP_E_SHAPE;
     if (!x || !y) return LIP_E_ARG;
     if (mode != LIP_M_GLOBAL && mode != LIP_M_LOCAL_KNN) return LIP_E_ARG;
     if (mode == LIP_M_LOCAL_KNN && (knn < 1 || knn > LIP_MAX_KNN)) return LIP_E_VALUE;
@@ -561,30 +298,38 @@ extern "C" lip_status lip_estimate_M(const lip_metric *metric, const float *x, c
         st = check_finite(arr, cnt, 2, ws, s);
         if (st != LIP_OK) return st;
     }
-    DsLaunchers L;
-    if (!get_ds(mi.d, &L)) return LIP_E_UNSUPPORTED;
     DsArgs A{};
-    A.rec = (const double *)ws;
+    Signs sg{};
+    const bool hasw = fill_ds_metric(mi, false, &A, &sg);
+    DsLaunchers L;
+    if (!get_ds(mi, hasw, &L)) return LIP_E_UNSUPPORTED;
     A.n = n;
-    fill_ds_metric(mi, false, &A);
+    A.npad = ds_npad(n);
+    A.X = (const double *)ws;
     A.M64 = M64;
     A.M32 = M32;
-    L.stage(x, y, nullptr, 0.0f, n, (double *)ws, s);
+    char *p = (char *)ws + align_up((size_t)A.npad * (size_t)(mi.d + 2) * 8, 256);
+    if (launch_stage64(mi.d, x, y, nullptr, 0.0f, n, A.npad, sg, (double *)ws, s) != hipSuccess)
+        return LIP_E_DEVICE;
     if (mode == LIP_M_GLOBAL) {
-        char *p = (char *)ws + align_up((size_t)n * (size_t)(mi.d + 2) * 8, 256);
+        choose_chunks(n, 64 * kDsRows, kDsMaxChunks, &A);
+        const size_t e = (size_t)A.n_chunks * (size_t)n;
         A.row_best = (double *)p;
-        A.row_arg = (int32_t *)(p + (size_t)n * 8);
-        A.row_dup = A.row_arg + n;
-        const int64_t waves = (n + 64 * kMRows - 1) / (64 * kMRows);
-        L.slope(A, dim3((unsigned)((waves + 3) / 4)), dim3(256), s);
+        A.row_arg = (int32_t *)(A.row_best + e);
+        A.row_dup = A.row_arg + e;
+        L.slope(A, dim3(grid_for_rows(n, 64 * kDsRows, A.n_chunks)), dim3(256), s);
         hipLaunchKernelGGL(slope_reduce_kernel, dim3(1), dim3(1024), 0, s, A, pair);
     } else {
         A.knn = knn;
-        const dim3 grid((unsigned)((n + 255) / 256)), block(256);
-        if (knn <= 16)
-            L.knn16(A, grid, block, s);
-        else
-            L.knn32(A, grid, block, s);
+        const int K = knn <= 16 ? 16 : 32;
+        choose_chunks(n, 64, kKnnMaxChunks, &A);
+        const size_t e = (size_t)A.n_chunks * (size_t)n * (size_t)K;
+        A.kkey = (double *)p;
+        A.kidx = (int32_t *)(A.kkey + e);
+        const dim3 g(grid_for_rows(n, 64, A.n_chunks)), b(256);
+        (K == 16 ? L.knn16 : L.knn32)(A, g, b, s);
+        if (A.n_chunks > 1)
+            (K == 16 ? L.merge16 : L.merge32)(A, dim3((unsigned)((n + 255) / 256)), b, s);
     }
     return dev_status(hipGetLastError());
 }

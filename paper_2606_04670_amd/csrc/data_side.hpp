@@ -1,0 +1,637 @@
+// Data-side passes over all pairs of data points, in FP64 (kernel templates):
+//  * consistency - the Lipschitz condition of Sec. 1 with the monotonicity
+//    constraints of Sec. 4.1, in the pairwise form of Eqs. (5)-(6) with zero
+//    corrections;
+//  * slope       - the largest pairwise slope (Sec. 5, global constant);
+//  * knn         - the per-datum slope over the K nearest data (Sec. 4.3,
+//    scalar form).
+//
+// Every pair is evaluated in double precision from the FP32 inputs with a
+// fixed operation order: per coordinate in index order, delta = x_i - x_k,
+// the component (|delta|, or a positive part on a monotone coordinate) times
+// the weight, then accumulated (sum, sum of squares, or max) from 0; l2 takes
+// the square root; bounds are y_k + M_k * dist (product, then sum).  All of
+// these operations are correctly rounded, so the decisions that produce the
+// integer outputs (violation counts, partners, neighbour ranks) are
+// reproducible by any implementation that follows the same order.
+//
+// Layout.  The data are staged d-major in FP64: X[j * npad + k] for
+// j = 0..D-1 (coordinates), j = D (y) and j = D + 1 (M_k), npad a multiple of
+// 64.  The column loop handles groups of 4 consecutive columns: one scalar
+// load brings the 4 values of one coordinate into SGPRs, and the uniform
+// branch on that coordinate's monotonicity is taken once per 4 columns x R
+// rows instead of once per pair.
+//
+// Work split.  A lane owns R rows; a wave owns 64 R rows and one chunk of the
+// columns, so that the grid has several waves per SIMD even when n is only
+// ~1e5; per-chunk partial results are combined in chunk (= column) order.
+// Workgroups are numbered chunk-fastest (blockIdx % 8 picks the XCD).
+//
+// Partners without per-pair index tracking: the column loop keeps running
+// minima only and notes, per tile of kDsTile columns, whether they strictly
+// improved; the last improving tile is re-scanned with the same arithmetic
+// to find the first attaining column.  Violation counts are wave-uniform:
+// ballot + popcount into scalar registers.
+#pragma once
+
+#include <climits>
+#include <float.h>
+
+#include "host_common.hpp"
+
+namespace lip {
+
+constexpr int kDsRows = 2;        // rows per lane (consistency, slope)
+constexpr int kDsTile = 64;       // columns per partner tile
+constexpr int kDsGroup = 4;       // columns per scalar-load group
+constexpr int kDsMaxChunks = 16;  // column chunks (consistency, slope)
+constexpr int kKnnMaxChunks = 4;  // column chunks (kNN)
+constexpr int64_t kDsTargetWaves = 8192;
+
+struct DsArgs {
+    const double *X;  // staged d-major [D + 2][npad]
+    int64_t n, npad;
+    double w[kMaxDim];
+    double fsel[kMaxDim];   // 1 free, 0 monotone (decreasing ones negated at staging)
+    double tol;
+    int32_t n_chunks;
+    int32_t knn;
+    int64_t chunk_cols;  // columns per chunk (multiple of kDsTile)
+    // consistency: partials [n_chunks][n] and final outputs
+    double *pv_up, *pv_lo;
+    int32_t *pi_up, *pi_lo;
+    double *slack_up, *slack_lo;
+    int32_t *partner_up, *partner_lo;
+    unsigned long long *counts;  // [2]
+    // global slope: partials [n_chunks][n]
+    double *row_best;
+    int32_t *row_arg;
+    int32_t *row_dup;
+    // kNN: partial lists [n_chunks][n][K]
+    double *kkey;
+    int32_t *kidx;
+    double *M64;
+    float *M32;
+};
+
+typedef const double __attribute__((address_space(4))) *cdouble_ptr;
+
+// max(v, 0) and max(-v, 0) in FP64.  Written as instructions so that the
+// compiler does not first quiet (canonicalize) the operand, which the IEEE
+// mode of the kernels would otherwise require for fmax; v is always the
+// result of an arithmetic instruction here.  Equal to the definition's
+// (v > 0 ? v : 0) up to the sign of a zero, which no later step can observe
+// (sums, squares and comparisons ignore it).
+__device__ __forceinline__ double pos_part(double v)
+{
+    double r;
+    asm("v_max_f64 %0, %1, 0" : "=v"(r) : "v"(v));
+    return r;
+}
+__device__ __forceinline__ double neg_part(double v)
+{
+    double r;
+    asm("v_max_f64 %0, -%1, 0" : "=v"(r) : "v"(v));
+    return r;
+}
+__device__ __forceinline__ double max2(double a, double b)
+{
+    double r;
+    asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+// The running norm value after the first component c (FIRST) or after
+// adding one more component to s.  Starting from c instead of 0 + c
+// differs at most in the sign of a zero.
+template <int NORM, bool FIRST>
+__device__ __forceinline__ double ds_acc(double s, double c)
+{
+    if constexpr (NORM == 1) return FIRST ? c : s + c;
+    else if constexpr (NORM == 2) return FIRST ? c * c : s + c * c;
+    else return FIRST ? c : max2(s, c);
+}
+
+// Accumulate coordinate i of one pair.  A free coordinate contributes |d|
+// to both distances, a monotone one (d)_+ to the upper and (-d)_+ to the
+// lower distance (decreasing coordinates were negated at staging, which maps
+// them onto increasing ones exactly).  Without monotone coordinates (MON
+// false, and for the symmetric distance) only su is formed.  With them the
+// step is branch-free: with p = (d)_+, q = (-d)_+ and f = 1 for a free
+// coordinate, 0 for a monotone one (wave-uniform),
+//     c_up = f q + p,  c_lo = f p + q,
+// each a single fused multiply-add of exact terms (one of p, q is zero and f
+// is 0 or 1), hence exactly the component of the definition.
+template <int NORM, bool HASW, bool MON, bool FIRST>
+__device__ __forceinline__ void ds_step(double f, double w, double d, double &su, double &sl)
+{
+    if (!MON) {
+        double a = fabs(d);
+        if (HASW) a = w * a;
+        su = ds_acc<NORM, FIRST>(su, a);
+    } else {
+        const double p = pos_part(d), q = neg_part(d);
+        double cu = fma(f, q, p), cl = fma(f, p, q);
+        if (HASW) {
+            cu = w * cu;
+            cl = w * cl;
+        }
+        su = ds_acc<NORM, FIRST>(su, cu);
+        sl = ds_acc<NORM, FIRST>(sl, cl);
+    }
+}
+
+// One pair, per-lane column k (vector loads): the same operation sequence as
+// the grouped loops below.  Without MON, sl = su.
+template <int D, int NORM, bool HASW, bool MON>
+__device__ __forceinline__ void ds_dist1(const DsArgs &A, const double (&xr)[D], int64_t k,
+                                         double &su, double &sl)
+{
+    su = 0.0;
+    sl = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        const double d = xr[i] - A.X[(int64_t)i * A.npad + k];
+        if (i == 0)
+            ds_step<NORM, HASW, MON, true>(A.fsel[i], A.w[i], d, su, sl);
+        else
+            ds_step<NORM, HASW, MON, false>(A.fsel[i], A.w[i], d, su, sl);
+    }
+    if (NORM == 2) {
+        su = sqrt(su);
+        if (MON) sl = sqrt(sl);
+    }
+    if (!MON) sl = su;
+}
+
+// Distances of R rows to the columns g0 .. g0 + kDsGroup - 1 (scalar
+// loads of one coordinate of the whole group at a time).  For l2 the sums
+// of squares are returned (no root); without MON only su is formed.
+template <int D, int NORM, bool HASW, bool MON, int R>
+__device__ __forceinline__ void ds_dist_group(const DsArgs &A, cdouble_ptr X, int64_t g0,
+                                              const double (&xr)[R][D],
+                                              double (&su)[kDsGroup][R],
+                                              double (&sl)[kDsGroup][R])
+{
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        double xc[kDsGroup];
+#pragma unroll
+        for (int c = 0; c < kDsGroup; ++c) xc[c] = X[(int64_t)i * A.npad + g0 + c];
+        const double w = A.w[i], f = A.fsel[i];
+#pragma unroll
+        for (int c = 0; c < kDsGroup; ++c)
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (i == 0)
+                    ds_step<NORM, HASW, MON, true>(f, w, xr[r][i] - xc[c], su[c][r], sl[c][r]);
+                else
+                    ds_step<NORM, HASW, MON, false>(f, w, xr[r][i] - xc[c], su[c][r], sl[c][r]);
+            }
+    }
+}
+
+// Work coordinates of a wave: rows [r0, r1), columns [c0, c1).
+struct WaveRange {
+    int64_t r0, r1, c0, c1;
+    int chunk;
+};
+
+__device__ __forceinline__ bool wave_range(const DsArgs &A, int rows_per_wave, WaveRange &w)
+{
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    w.chunk = blockIdx.x % A.n_chunks;
+    const int64_t rb = (int64_t)(blockIdx.x / A.n_chunks) * (blockDim.x >> 6) + wave;
+    w.r0 = rb * rows_per_wave;
+    if (w.r0 >= A.n) return false;
+    w.r1 = w.r0 + rows_per_wave < A.n ? w.r0 + rows_per_wave : A.n;
+    w.c0 = (int64_t)w.chunk * A.chunk_cols;
+    w.c1 = w.c0 + A.chunk_cols < A.n ? w.c0 + A.chunk_cols : A.n;
+    return true;
+}
+
+// ---- consistency -------------------------------------------------------------
+
+template <int D, int NORM, bool HASW, bool MON, bool MASK>
+__device__ __forceinline__ void cons_group(const DsArgs &A, cdouble_ptr X, int64_t g0,
+                                           const double (&xr)[kDsRows][D],
+                                           const double (&yr)[kDsRows], const int (&ir)[kDsRows],
+                                           const bool (&valid)[kDsRows], double (&bu)[kDsRows],
+                                           double (&bl)[kDsRows], unsigned long long &cu,
+                                           unsigned long long &cl)
+{
+    double su[kDsGroup][kDsRows], sl[kDsGroup][kDsRows];
+    ds_dist_group<D, NORM, HASW, MON, kDsRows>(A, X, g0, xr, su, sl);
+    double yk[kDsGroup], mk[kDsGroup];
+#pragma unroll
+    for (int c = 0; c < kDsGroup; ++c) {
+        yk[c] = X[(int64_t)D * A.npad + g0 + c];
+        mk[c] = X[(int64_t)(D + 1) * A.npad + g0 + c];
+    }
+#pragma unroll
+    for (int c = 0; c < kDsGroup; ++c)
+#pragma unroll
+        for (int r = 0; r < kDsRows; ++r) {
+            double du = su[c][r], dl = MON ? sl[c][r] : su[c][r];
+            if (NORM == 2) {
+                du = sqrt(du);
+                dl = MON ? sqrt(dl) : du;
+            }
+            double tu = (yk[c] + mk[c] * du) - yr[r];
+            double tl = yr[r] - (yk[c] - mk[c] * dl);
+            if (MASK) {
+                const int64_t k = g0 + c;
+                const bool ok = k < A.n && k != ir[r];
+                tu = ok ? tu : __builtin_inf();
+                tl = ok ? tl : __builtin_inf();
+            }
+            bu[r] = fmin(bu[r], tu);
+            bl[r] = fmin(bl[r], tl);
+            cu += __popcll(__ballot(valid[r] && tu < -A.tol));
+            cl += __popcll(__ballot(valid[r] && tl < -A.tol));
+        }
+}
+
+template <int D, int NORM, bool HASW, bool MON>
+__device__ __forceinline__ void cons_pair(const DsArgs &A, const double (&xr)[D], double yr,
+                                          int64_t k, double &tu, double &tl)
+{
+    double du, dl;
+    ds_dist1<D, NORM, HASW, MON>(A, xr, k, du, dl);
+    const double yk = A.X[(int64_t)D * A.npad + k], mk = A.X[(int64_t)(D + 1) * A.npad + k];
+    tu = (yk + mk * du) - yr;
+    tl = yr - (yk - mk * dl);
+}
+
+template <int D, int NORM, bool HASW, bool MON>
+__global__ void __launch_bounds__(256) consistency_kernel(DsArgs A)
+{
+    constexpr int RW = 64 * kDsRows;
+    WaveRange w;
+    if (!wave_range(A, RW, w)) return;
+    const int lane = threadIdx.x & 63;
+    double xr[kDsRows][D], yr[kDsRows], bu[kDsRows], bl[kDsRows];
+    int ir[kDsRows], tu_t[kDsRows], tl_t[kDsRows];
+    bool valid[kDsRows];
+#pragma unroll
+    for (int r = 0; r < kDsRows; ++r) {
+        int64_t i = w.r0 + r * 64 + lane;
+        valid[r] = i < A.n;
+        i = i < A.n ? i : A.n - 1;
+        ir[r] = (int)i;
+#pragma unroll
+        for (int j = 0; j < D; ++j) xr[r][j] = A.X[(int64_t)j * A.npad + i];
+        yr[r] = A.X[(int64_t)D * A.npad + i];
+        bu[r] = __builtin_inf();
+        bl[r] = __builtin_inf();
+        tu_t[r] = tl_t[r] = -1;
+    }
+    const cdouble_ptr X = (cdouble_ptr)(A.X);
+    unsigned long long cu = 0, cl = 0;
+    int t = 0;
+    for (int64_t tb = w.c0; tb < w.c1; tb += kDsTile, ++t) {
+        const int64_t te = tb + kDsTile < w.c1 ? tb + kDsTile : w.c1;
+        double pu[kDsRows], pl[kDsRows];
+#pragma unroll
+        for (int r = 0; r < kDsRows; ++r) {
+            pu[r] = bu[r];
+            pl[r] = bl[r];
+        }
+#pragma unroll 1
+        for (int64_t g0 = tb; g0 < te; g0 += kDsGroup) {
+            const bool masked = (g0 + kDsGroup > A.n) || (g0 < w.r1 && g0 + kDsGroup > w.r0);
+            if (masked)
+                cons_group<D, NORM, HASW, MON, true>(A, X, g0, xr, yr, ir, valid, bu, bl, cu, cl);
+            else
+                cons_group<D, NORM, HASW, MON, false>(A, X, g0, xr, yr, ir, valid, bu, bl, cu, cl);
+        }
+#pragma unroll
+        for (int r = 0; r < kDsRows; ++r) {
+            tu_t[r] = bu[r] < pu[r] ? t : tu_t[r];
+            tl_t[r] = bl[r] < pl[r] ? t : tl_t[r];
+        }
+    }
+    // partners: first column of the last improving tile attaining the minimum
+#pragma unroll
+    for (int r = 0; r < kDsRows; ++r) {
+        int pu_i = -1, pl_i = -1;
+        const int64_t bu0 = w.c0 + (int64_t)(tu_t[r] < 0 ? 0 : tu_t[r]) * kDsTile;
+        const int64_t bl0 = w.c0 + (int64_t)(tl_t[r] < 0 ? 0 : tl_t[r]) * kDsTile;
+        for (int k = kDsTile - 1; k >= 0; --k) {
+            const int64_t ku = bu0 + k, kl = bl0 + k;
+            if (tu_t[r] >= 0 && ku < w.c1 && ku != ir[r]) {
+                double tu, tl;
+                cons_pair<D, NORM, HASW, MON>(A, xr[r], yr[r], ku, tu, tl);
+                if (tu == bu[r]) pu_i = (int)ku;
+            }
+            if (tl_t[r] >= 0 && kl < w.c1 && kl != ir[r]) {
+                double tu, tl;
+                cons_pair<D, NORM, HASW, MON>(A, xr[r], yr[r], kl, tu, tl);
+                if (tl == bl[r]) pl_i = (int)kl;
+            }
+        }
+        if (!valid[r]) continue;
+        const int64_t i = ir[r];
+        if (A.n_chunks == 1) {
+            if (A.slack_up) A.slack_up[i] = bu[r];
+            if (A.slack_lo) A.slack_lo[i] = bl[r];
+            if (A.partner_up) A.partner_up[i] = pu_i;
+            if (A.partner_lo) A.partner_lo[i] = pl_i;
+        } else {
+            const int64_t o = (int64_t)w.chunk * A.n + i;
+            A.pv_up[o] = bu[r];
+            A.pv_lo[o] = bl[r];
+            A.pi_up[o] = pu_i;
+            A.pi_lo[o] = pl_i;
+        }
+    }
+    if (lane == 0) {
+        atomicAdd(A.counts, cu);
+        atomicAdd(A.counts + 1, cl);
+    }
+}
+
+// ---- global M: max over i < k of |y_i - y_k| / dist ------------------------------
+
+template <int D, int NORM, bool HASW, bool MASK>
+__device__ __forceinline__ void slope_group(const DsArgs &A, cdouble_ptr X, int64_t g0,
+                                            const double (&xr)[kDsRows][D],
+                                            const double (&yr)[kDsRows], const int (&ir)[kDsRows],
+                                            double (&best)[kDsRows], int (&arg)[kDsRows],
+                                            int (&dup)[kDsRows])
+{
+    double su[kDsGroup][kDsRows], sl[kDsGroup][kDsRows];
+    ds_dist_group<D, NORM, HASW, false, kDsRows>(A, X, g0, xr, su, sl);
+    double yk[kDsGroup];
+#pragma unroll
+    for (int c = 0; c < kDsGroup; ++c) yk[c] = X[(int64_t)D * A.npad + g0 + c];
+#pragma unroll
+    for (int c = 0; c < kDsGroup; ++c)
+#pragma unroll
+        for (int r = 0; r < kDsRows; ++r) {
+            const int64_t k = g0 + c;
+            if (MASK && !(k > ir[r] && k < A.n)) continue;
+            double du = su[c][r];
+            if (NORM == 2) du = sqrt(du);
+            const double dy = fabs(yr[r] - yk[c]);
+            if (du == 0.0) {
+                if (dy != 0.0 && dup[r] < 0) dup[r] = (int)k;
+                continue;
+            }
+            // dy / du > best  <=>  dy - best * du > 0, decided exactly by the
+            // sign of one fused multiply-add; only then form the quotient.
+            if (best[r] < 0.0 || fma(-best[r], du, dy) > 0.0) {
+                const double s = dy / du;
+                if (s > best[r]) {
+                    best[r] = s;
+                    arg[r] = (int)k;
+                }
+            }
+        }
+}
+
+template <int D, int NORM, bool HASW>
+__global__ void __launch_bounds__(256) slope_kernel(DsArgs A)
+{
+    constexpr int RW = 64 * kDsRows;
+    WaveRange w;
+    if (!wave_range(A, RW, w)) return;
+    const int lane = threadIdx.x & 63;
+    double xr[kDsRows][D], yr[kDsRows], best[kDsRows];
+    int ir[kDsRows], arg[kDsRows], dup[kDsRows];
+    bool valid[kDsRows];
+#pragma unroll
+    for (int r = 0; r < kDsRows; ++r) {
+        int64_t i = w.r0 + r * 64 + lane;
+        valid[r] = i < A.n;
+        i = i < A.n ? i : A.n - 1;
+        ir[r] = (int)i;
+#pragma unroll
+        for (int j = 0; j < D; ++j) xr[r][j] = A.X[(int64_t)j * A.npad + i];
+        yr[r] = A.X[(int64_t)D * A.npad + i];
+        best[r] = -1.0;
+        arg[r] = -1;
+        dup[r] = -1;
+    }
+    const cdouble_ptr X = (cdouble_ptr)(A.X);
+    // only columns k > i: groups left of the wave's rows are skipped, groups
+    // overlapping them (or the end of the data) are masked per pair.
+    const int64_t gstart = w.c0 > (w.r0 / kDsGroup) * kDsGroup ? w.c0 : (w.r0 / kDsGroup) * kDsGroup;
+#pragma unroll 1
+    for (int64_t g0 = gstart; g0 < w.c1; g0 += kDsGroup) {
+        const bool masked = (g0 + kDsGroup > A.n) || (g0 < w.r1);
+        if (masked)
+            slope_group<D, NORM, HASW, true>(A, X, g0, xr, yr, ir, best, arg, dup);
+        else
+            slope_group<D, NORM, HASW, false>(A, X, g0, xr, yr, ir, best, arg, dup);
+    }
+#pragma unroll
+    for (int r = 0; r < kDsRows; ++r) {
+        if (!valid[r]) continue;
+        const int64_t o = (int64_t)w.chunk * A.n + ir[r];
+        A.row_best[o] = best[r];
+        A.row_arg[o] = arg[r];
+        A.row_dup[o] = dup[r];
+    }
+}
+
+// ---- local M from the K nearest data ---------------------------------------------
+
+// Keeps the K smallest (key, index) of the row in ascending order.  Columns
+// arrive in increasing index order, so a strict comparison ranks the lower
+// index first among equal keys.
+template <int K>
+__device__ __forceinline__ void knn_insert(double (&key)[K], int (&idx)[K], double kv, int j)
+{
+    key[K - 1] = kv;
+    idx[K - 1] = j;
+#pragma unroll
+    for (int t = K - 1; t > 0; --t) {
+        const bool sw = key[t] < key[t - 1];
+        const double a = key[t], b = key[t - 1];
+        const int ia = idx[t], ib = idx[t - 1];
+        key[t] = sw ? b : a;
+        key[t - 1] = sw ? a : b;
+        idx[t] = sw ? ib : ia;
+        idx[t - 1] = sw ? ia : ib;
+    }
+}
+
+// M_i = max over the neighbour list of |y_i - y_j| / dist (coincident
+// neighbours: skipped with equal y, infinite slope otherwise).
+template <int D, int NORM, bool HASW, int K>
+__device__ __forceinline__ void knn_finish(const DsArgs &A, int64_t i, const double (&xr)[D],
+                                           const int (&idx)[K])
+{
+    const double yi = A.X[(int64_t)D * A.npad + i];
+    double best = 0.0;
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+        if (t >= A.knn || idx[t] < 0) continue;
+        double du, dl;
+        ds_dist1<D, NORM, HASW, false>(A, xr, idx[t], du, dl);
+        const double dy = fabs(yi - A.X[(int64_t)D * A.npad + idx[t]]);
+        if (du == 0.0) {
+            if (dy != 0.0) best = __builtin_inf();
+            continue;
+        }
+        const double s = dy / du;
+        if (s > best) best = s;
+    }
+    if (A.M64) A.M64[i] = best;
+    if (A.M32) {
+        float f = (float)best;
+        if ((double)f < best) f = nextafterf(f, __builtin_inff());
+        A.M32[i] = f;
+    }
+}
+
+template <int D, int NORM, bool HASW, int K>
+__global__ void __launch_bounds__(256) knn_kernel(DsArgs A)
+{
+    WaveRange w;
+    if (!wave_range(A, 64, w)) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t i0 = w.r0 + lane;
+    const bool valid = i0 < A.n;
+    const int64_t i = valid ? i0 : A.n - 1;
+    double xr[1][D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) xr[0][j] = A.X[(int64_t)j * A.npad + i];
+    double key[K];
+    int idx[K];
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+        key[t] = __builtin_inf();
+        idx[t] = -1;
+    }
+    // Only the first knn (<= K) slots matter; thr is the knn-th smallest key.
+    const int kk = A.knn;
+    double thr = __builtin_inf();
+    const cdouble_ptr X = (cdouble_ptr)(A.X);
+#pragma unroll 1
+    for (int64_t g0 = w.c0; g0 < w.c1; g0 += kDsGroup) {
+        double su[kDsGroup][1], sl[kDsGroup][1];
+        // rank by the distance (l2: by the sum of squares, no root)
+        ds_dist_group<D, NORM, HASW, false, 1>(A, X, g0, xr, su, sl);
+#pragma unroll
+        for (int c = 0; c < kDsGroup; ++c) {
+            const int64_t k = g0 + c;
+            if (k < A.n && k != i && su[c][0] < thr) {
+                knn_insert<K>(key, idx, su[c][0], (int)k);
+#pragma unroll
+                for (int t = 0; t < K; ++t)
+                    if (t == kk - 1) thr = key[t];
+            }
+        }
+    }
+    if (!valid) return;
+    if (A.n_chunks == 1) {
+        knn_finish<D, NORM, HASW, K>(A, i, xr[0], idx);
+        return;
+    }
+    const int64_t o = ((int64_t)w.chunk * A.n + i) * K;
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+        A.kkey[o + t] = key[t];
+        A.kidx[o + t] = idx[t];
+    }
+}
+
+// Merges the per-chunk sorted lists of each row (chunks in column order; on
+// equal keys the lower index first) and finishes M_i.
+template <int D, int NORM, bool HASW, int K>
+__global__ void __launch_bounds__(256) knn_merge_kernel(DsArgs A)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    double xr[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) xr[j] = A.X[(int64_t)j * A.npad + i];
+    int head[kKnnMaxChunks];
+#pragma unroll
+    for (int c = 0; c < kKnnMaxChunks; ++c) head[c] = 0;
+    int idx[K];
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+        double bk = __builtin_inf();
+        int bi = -1, bc = -1;
+#pragma unroll
+        for (int c = 0; c < kKnnMaxChunks; ++c) {
+            if (c >= A.n_chunks || head[c] >= K) continue;
+            const int64_t o = ((int64_t)c * A.n + i) * K + head[c];
+            const double kv = A.kkey[o];
+            const int ki = A.kidx[o];
+            if (ki < 0) continue;
+            if (bi < 0 || kv < bk || (kv == bk && ki < bi)) {
+                bk = kv;
+                bi = ki;
+                bc = c;
+            }
+        }
+        idx[t] = bi;
+#pragma unroll
+        for (int c = 0; c < kKnnMaxChunks; ++c)
+            if (c == bc) ++head[c];
+    }
+    knn_finish<D, NORM, HASW, K>(A, i, xr, idx);
+}
+
+// ---- launcher tables ------------------------------------------------------------
+
+typedef void (*DsLaunch)(const DsArgs &, dim3, dim3, hipStream_t);
+
+struct DsLaunchers {
+    DsLaunch consistency, consistency_mon, slope, knn16, knn32, merge16, merge32;
+};
+
+template <int D, int NORM, bool HASW>
+DsLaunchers ds_launchers_for()
+{
+    DsLaunchers L;
+    L.consistency = [](const DsArgs &a, dim3 g, dim3 b, hipStream_t s) {
+        hipLaunchKernelGGL((consistency_kernel<D, NORM, HASW, false>), g, b, 0, s, a);
+    };
+    L.consistency_mon = [](const DsArgs &a, dim3 g, dim3 b, hipStream_t s) {
+        hipLaunchKernelGGL((consistency_kernel<D, NORM, HASW, true>), g, b, 0, s, a);
+    };
+    L.slope = [](const DsArgs &a, dim3 g, dim3 b, hipStream_t s) {
+        hipLaunchKernelGGL((slope_kernel<D, NORM, HASW>), g, b, 0, s, a);
+    };
+    L.knn16 = [](const DsArgs &a, dim3 g, dim3 b, hipStream_t s) {
+        hipLaunchKernelGGL((knn_kernel<D, NORM, HASW, 16>), g, b, 0, s, a);
+    };
+    L.knn32 = [](const DsArgs &a, dim3 g, dim3 b, hipStream_t s) {
+        hipLaunchKernelGGL((knn_kernel<D, NORM, HASW, 32>), g, b, 0, s, a);
+    };
+    L.merge16 = [](const DsArgs &a, dim3 g, dim3 b, hipStream_t s) {
+        hipLaunchKernelGGL((knn_merge_kernel<D, NORM, HASW, 16>), g, b, 0, s, a);
+    };
+    L.merge32 = [](const DsArgs &a, dim3 g, dim3 b, hipStream_t s) {
+        hipLaunchKernelGGL((knn_merge_kernel<D, NORM, HASW, 32>), g, b, 0, s, a);
+    };
+    return L;
+}
+
+template <int NORM>
+bool ds_table(int d, bool hasw, DsLaunchers *L)
+{
+    switch (d) {
+#define LIP_DS_CASE(DD)                                                                         \
+    case DD:                                                                                    \
+        *L = hasw ? ds_launchers_for<DD, NORM, true>() : ds_launchers_for<DD, NORM, false>(); \
+        return true;
+        LIP_DS_CASE(1) LIP_DS_CASE(2) LIP_DS_CASE(3) LIP_DS_CASE(4)
+        LIP_DS_CASE(5) LIP_DS_CASE(6) LIP_DS_CASE(7) LIP_DS_CASE(8)
+        LIP_DS_CASE(9) LIP_DS_CASE(10) LIP_DS_CASE(11) LIP_DS_CASE(12)
+        LIP_DS_CASE(13) LIP_DS_CASE(14) LIP_DS_CASE(15) LIP_DS_CASE(16)
+#undef LIP_DS_CASE
+    default: return false;
+    }
+}
+
+bool ds_table_l1(int d, bool hasw, DsLaunchers *L);
+bool ds_table_l2(int d, bool hasw, DsLaunchers *L);
+bool ds_table_linf(int d, bool hasw, DsLaunchers *L);
+
+}  // namespace lip

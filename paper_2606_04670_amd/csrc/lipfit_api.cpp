@@ -89,15 +89,16 @@ lip_tile_cfg tune_lookup(int d, int dm, int norm, int64_t n, int64_t q)
         auto it = g_tune.find(std::make_tuple(d, dm, norm));
         if (it != g_tune.end()) return it->second;
     }
-    // Default: enough waves for about 4 per SIMD (256 CUs x 4 SIMDs), data
-    // split in a power-of-two number of chunks when the queries alone do not
-    // fill the chip.
+    // Default: about 16 waves per SIMD (256 CUs x 4 SIMDs) so that the last
+    // wave of each SIMD starts early (small tail), data split in a
+    // power-of-two number of chunks when the queries alone do not fill the
+    // chip.
     lip_tile_cfg c{};
-    c.tile = 64;
+    c.tile = 32;
     c.waves = 4;
     const int R = rows_for_dim(d);
     const int64_t qwaves = (q + 64 * R - 1) / (64 * R);
-    const int64_t target = 4096;
+    const int64_t target = 16384;
     int split = 1;
     const int64_t tiles = (n + c.tile - 1) / c.tile;
     while (split < kMaxChunks && qwaves * split < target && tiles >= 4ll * split * 2 &&
