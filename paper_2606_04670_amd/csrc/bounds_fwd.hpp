@@ -20,6 +20,8 @@
 //
 // Split chunks write per-chunk partial results; a combine kernel reduces
 // them in chunk order (strict comparisons keep the lower index on ties).
+// In batched plans they instead merge packed (value, index) 64-bit keys with
+// atomic min / max, which also keeps the lowest index on ties.
 #pragma once
 
 #include <array>
@@ -72,20 +74,17 @@ __device__ __forceinline__ void eval_group(const float (&v)[group_for_dim(D) * R
     }
 }
 
+// One wave's work: queries [64 R qblock, 64 R (qblock + 1)) against data
+// chunk `chunk`.  Outputs: final values (one chunk), chunk partials, or
+// packed (value, index) keys merged with atomics (a.keys != NULL).
 template <int D, int DM, int NORM>
-__global__ void __launch_bounds__(256) bounds_fwd_kernel(FwdArgs a)
+__device__ __forceinline__ void fwd_wave(const FwdArgs &a, int chunk, int64_t qblock)
 {
     constexpr int S = Rec<D>::S;
     constexpr int R = FwdTraits<D, DM, NORM>::R;
     constexpr int kGroup = group_for_dim(D);
     constexpr int GS = kGroup * S;
     const int lane = threadIdx.x & 63;
-    // wave index is wave-uniform; readfirstlane lets the compiler keep every
-    // loop counter and address derived from it in SGPRs
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int nw = blockDim.x >> 6;
-    const int chunk = blockIdx.x % a.n_chunks;
-    const int64_t qblock = (int64_t)(blockIdx.x / a.n_chunks) * nw + wave;
     const int64_t q0 = qblock * (64 * R);
     if (q0 >= a.q) return;  // wave-uniform: no query of this wave exists
 
@@ -189,6 +188,17 @@ __global__ void __launch_bounds__(256) bounds_fwd_kernel(FwdArgs a)
             if (a.h_lo) a.h_lo[qi] = hl[r];
             if (a.arg_up) a.arg_up[qi] = au[r];
             if (a.arg_lo) a.arg_lo[qi] = al[r];
+        } else if (a.keys) {
+            // min of (key(value) << 32 | index) = min value, lowest index;
+            // max of (key(value) << 32 | ~index) = max value, lowest index,
+            // stored complemented so that both merges are atomic minima
+            // (one fill value initialises the whole key buffer)
+            const unsigned long long ku =
+                ((unsigned long long)f32_order_key(hu[r]) << 32) | (uint32_t)au[r];
+            const unsigned long long kl =
+                ((unsigned long long)f32_order_key(hl[r]) << 32) | (uint32_t)(~(uint32_t)al[r]);
+            atomicMin(a.keys + qi, ku);
+            atomicMin(a.keys + a.q + qi, ~kl);
         } else {
             const int64_t o = (int64_t)chunk * a.q + qi;
             const int64_t o2 = ((int64_t)a.n_chunks + chunk) * a.q + qi;
@@ -200,29 +210,67 @@ __global__ void __launch_bounds__(256) bounds_fwd_kernel(FwdArgs a)
     }
 }
 
+template <int D, int DM, int NORM>
+__global__ void __launch_bounds__(256) bounds_fwd_kernel(FwdArgs a)
+{
+    // wave index is wave-uniform; readfirstlane lets the compiler keep every
+    // loop counter and address derived from it in SGPRs
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nw = blockDim.x >> 6;
+    const int chunk = blockIdx.x % a.n_chunks;
+    const int64_t qblock = (int64_t)(blockIdx.x / a.n_chunks) * nw + wave;
+    fwd_wave<D, DM, NORM>(a, chunk, qblock);
+}
+
+// Persistent kernel for many independent data sets of one shape class
+// (d, monotone count, norm): every wave repeatedly takes the next work item
+// (set, query block, data chunk) from a counter; the items are ordered
+// longest first.  Each item runs the same wave body as bounds_fwd_kernel, so
+// the results are identical to per-set launches.
+template <int D, int DM, int NORM>
+__global__ void __launch_bounds__(256) batched_fwd_kernel(BatchArgs b)
+{
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        unsigned int id = 0;
+        if (lane == 0) id = atomicAdd(b.counter, 1u);
+        id = __builtin_amdgcn_readfirstlane(id);
+        if (id >= b.n_items) break;
+        const BatchItem it = b.items[id];
+        const FwdArgs a = b.sets[it.set];
+        fwd_wave<D, DM, NORM>(a, it.chunk, it.qblock);
+    }
+}
+
 template <int NORM, int D, int DM>
 void launch_fwd(const FwdArgs &a, dim3 grid, dim3 block, hipStream_t s)
 {
     hipLaunchKernelGGL((bounds_fwd_kernel<D, DM, NORM>), grid, block, 0, s, a);
 }
 
-template <int NORM, int D, int... DMs>
-constexpr std::array<FwdLauncher, D + 1> fwd_row(std::integer_sequence<int, DMs...>)
+template <int NORM, int D, int DM>
+void launch_batched(const BatchArgs &b, dim3 grid, dim3 block, hipStream_t s)
 {
-    return {{&launch_fwd<NORM, D, DMs>...}};
+    hipLaunchKernelGGL((batched_fwd_kernel<D, DM, NORM>), grid, block, 0, s, b);
+}
+
+template <int NORM, int D, int... DMs>
+constexpr std::array<FwdLaunchers, D + 1> fwd_row(std::integer_sequence<int, DMs...>)
+{
+    return {{FwdLaunchers{&launch_fwd<NORM, D, DMs>, &launch_batched<NORM, D, DMs>}...}};
 }
 
 template <int NORM, int D>
-FwdLauncher fwd_pick(int dm)
+FwdLaunchers fwd_pick(int dm)
 {
     constexpr auto row = fwd_row<NORM, D>(std::make_integer_sequence<int, D + 1>{});
     return row[dm];
 }
 
 template <int NORM>
-FwdLauncher fwd_table(int d, int dm)
+FwdLaunchers fwd_table(int d, int dm)
 {
-    if (dm < 0 || dm > d) return nullptr;
+    if (dm < 0 || dm > d) return FwdLaunchers{nullptr, nullptr};
     switch (d) {
     case 1: return fwd_pick<NORM, 1>(dm);
     case 2: return fwd_pick<NORM, 2>(dm);
@@ -240,7 +288,7 @@ FwdLauncher fwd_table(int d, int dm)
     case 14: return fwd_pick<NORM, 14>(dm);
     case 15: return fwd_pick<NORM, 15>(dm);
     case 16: return fwd_pick<NORM, 16>(dm);
-    default: return nullptr;
+    default: return FwdLaunchers{nullptr, nullptr};
     }
 }
 

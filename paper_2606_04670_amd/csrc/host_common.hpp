@@ -48,7 +48,7 @@ FwdPlan make_fwd_plan(const MetricInfo &mi, int64_t n, int64_t q, const lip_tile
 size_t staged_bytes(int64_t n, int d);
 size_t partial_bytes(int64_t q);
 
-FwdLauncher fwd_launcher(int norm, int d, int dm);
+FwdLaunchers fwd_launchers(int norm, int d, int dm);
 
 // Runs the bound path (stage -> fused kernel -> optional combine) on a
 // validated problem.  ws must hold staged_bytes + partial_bytes.

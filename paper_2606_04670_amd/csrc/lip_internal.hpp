@@ -28,9 +28,31 @@ struct FwdArgs {
     int32_t *arg_up, *arg_lo;
     float *part_v;           // [2][n_chunks][q] partial values (n_chunks > 1)
     int32_t *part_i;         // [2][n_chunks][q] partial indices
+    unsigned long long *keys;  // [2][q] packed keys (batched plans, n_chunks > 1)
+};
+
+// One work item of a batched plan: one wave's queries of one set against
+// one data chunk.
+struct BatchItem {
+    int32_t set;
+    int32_t chunk;
+    int64_t qblock;
+};
+
+struct BatchArgs {
+    const FwdArgs *sets;
+    const BatchItem *items;
+    unsigned int n_items;
+    unsigned int *counter;
 };
 
 typedef void (*FwdLauncher)(const FwdArgs &, dim3, dim3, hipStream_t);
+typedef void (*BatchLauncher)(const BatchArgs &, dim3, dim3, hipStream_t);
+
+struct FwdLaunchers {
+    FwdLauncher plain;
+    BatchLauncher batched;
+};
 
 // Staging of the data set into bound-kernel records (stage.hip).
 struct StageArgs {
@@ -60,9 +82,8 @@ hipError_t launch_combine(const CombineArgs &a, hipStream_t s);
 hipError_t launch_nonfinite(const float *v, int64_t n, int *flag, hipStream_t s);
 hipError_t launch_fill_i32(int *p, int64_t n, int v, hipStream_t s);
 
-FwdLauncher fwd_launcher_l1(int d, int dm);
-FwdLauncher fwd_launcher_l2(int d, int dm);
-FwdLauncher fwd_launcher_linf(int d, int dm);
-
+FwdLaunchers fwd_launchers_l1(int d, int dm);
+FwdLaunchers fwd_launchers_l2(int d, int dm);
+FwdLaunchers fwd_launchers_linf(int d, int dm);
 
 }  // namespace lip

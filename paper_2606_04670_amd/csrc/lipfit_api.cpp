@@ -51,13 +51,13 @@ lip_status parse_metric(const lip_metric *m, MetricInfo *out)
     return LIP_OK;
 }
 
-FwdLauncher fwd_launcher(int norm, int d, int dm)
+FwdLaunchers fwd_launchers(int norm, int d, int dm)
 {
     switch (norm) {
-    case LIP_L1: return fwd_launcher_l1(d, dm);
-    case LIP_L2: return fwd_launcher_l2(d, dm);
-    case LIP_LINF: return fwd_launcher_linf(d, dm);
-    default: return nullptr;
+    case LIP_L1: return fwd_launchers_l1(d, dm);
+    case LIP_L2: return fwd_launchers_l2(d, dm);
+    case LIP_LINF: return fwd_launchers_linf(d, dm);
+    default: return FwdLaunchers{nullptr, nullptr};
     }
 }
 
@@ -152,7 +152,7 @@ lip_status run_bounds(const MetricInfo &mi, const float *x, const float *y, int6
     const size_t sb = staged_bytes(n, mi.d);
     const size_t need = sb + (p.n_chunks > 1 ? partial_bytes(q) : 0);
     if (ws_bytes < need) return LIP_E_WORKSPACE;
-    FwdLauncher launch = fwd_launcher(mi.norm, mi.d, mi.dm);
+    FwdLauncher launch = fwd_launchers(mi.norm, mi.d, mi.dm).plain;
     if (!launch) return LIP_E_UNSUPPORTED;
     float *staged = (float *)ws;
 
