@@ -27,18 +27,40 @@ sys.path.insert(0, ROOT)
 
 METRIC = ("query×data pair-evals/s (d=4, N=1e5, Q=1e6) fwd and fwd+bwd; % VALU peak")
 
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz -> VALU lane-operations/s.
-VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz = VALU issue slots per
+# second (one slot = one lane-operation at the base issue rate).
+VALU_PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 FP32_DATASHEET_TFLOPS = 157.3
+FP64_VALU_PEAK_SLOTS = VALU_PEAK_SLOTS
 
-# Minimal VALU instructions per (query, datum) pair of the fused bound kernel
-# for d = 4 with 2 monotone coordinates (derivation in the design notes):
-# coordinate differences / maxima, accumulation, two FMAs for the bounds and
-# one min3/max3 per pair for the running min and max.
-ALG_OPS_PER_PAIR = {"l1": 11, "l2": 19, "linf": 10}
+# Issue cost of one instruction in slots, from the measured single-kind
+# rates on this chip (profiles/valu_issue_rates_gfx950.txt): v_add/v_sub_f32
+# issue at twice the base rate (~65 T lane-ops/s), v_sqrt_f32 at half
+# (~19 T), FMA / mul / max / min / med3 / min3 / max3 at the base rate.
+SLOT = {"add": 0.5, "fma": 1.0, "max": 1.0, "med3": 1.0, "minmax3": 1.0, "sqrt": 2.0}
+
+# Minimal instruction mix per (query, datum) pair of the fused bound kernel,
+# d = 4 with 2 monotone coordinates (derivation in the design notes):
+MIX = {
+    # 2 sub + 1 add(|a|,|b|) + 2 add + 1 sub; 2 med3; 2 FMA; min3/max3 per 2 pairs x 2 bounds
+    "l1": {"add": 6, "med3": 2, "fma": 2, "minmax3": 1},
+    # 4 sub; max + 2 max3; 2 FMA; min3/max3
+    "linf": {"add": 4, "max": 3, "fma": 2, "minmax3": 1},
+    # 4 sub; mul + FMA (free); 2 max + 2 min + 4 FMA (monotone); 2 sqrt; 2 FMA; min3/max3
+    "l2": {"add": 4, "fma": 8, "max": 4, "sqrt": 2, "minmax3": 1},
+}
+SLOTS_PER_PAIR = {nm: sum(SLOT[c] * k for c, k in mix.items()) for nm, mix in MIX.items()}
+INSTR_PER_PAIR = {nm: sum(mix.values()) for nm, mix in MIX.items()}
 # Conventional FLOP per pair (each add/sub/min/max/abs-accumulate 1, FMA 2,
 # sqrt 1) used for the datasheet comparison.
 FLOP_PER_PAIR = {"l1": 16, "l2": 24, "linf": 16}
+# FP64 instructions per ordered data pair of the consistency kernel with
+# monotone coordinates (d = 4): 4 differences; per coordinate 2 positive
+# parts + 2 selector FMAs; 3 + 3 accumulations (l2: products and sums,
+# 6 + 6) and 2 square roots (l2, ~10 instructions each); 2 x (mul, add, add)
+# for the bounds; 2 minima; 2 compares.
+FP64_OPS_PER_PAIR = {"l1": 4 + 16 + 6 + 6 + 2 + 2, "linf": 4 + 16 + 6 + 6 + 2 + 2,
+                     "l2": 4 + 16 + 12 + 20 + 6 + 2 + 2}
 
 
 def parse():
@@ -50,7 +72,79 @@ def parse():
     ap.add_argument("--cpu-queries", type=int, default=8192,
                     help="queries per norm in the oracle's CPU-baseline sample")
     ap.add_argument("--norms", default="l1,l2,linf")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the BF16-vs-FP32 and batched-vs-per-set comparisons")
     return ap.parse_args()
+
+
+def _time_ms(torch, fn, reps):
+    """Mean time of fn() over reps runs (one untimed warm-up), HIP events on
+    the current stream."""
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def extra_bf16(lf, W, torch, dev, reps=3):
+    """l2, d = 16, N = Q = 1e6 (x ~ N(0, I), M = 1): BF16-MFMA filter + FP32
+    re-scoring against the plain FP32 path, results compared for identity."""
+    p = W.mixed_l2()
+    x = torch.from_numpy(p.x).to(dev)
+    y = torch.from_numpy(p.y).to(dev)
+    xq = torch.from_numpy(p.xq).to(dev)
+    met = lf.Metric(p.d, "l2")
+    outs = {}
+
+    def run(bf):
+        outs[bf] = lf.fit_eval(x, y, xq, met, M=p.M, bf16=bf)
+
+    t32 = _time_ms(torch, lambda: run(False), reps)
+    t16 = _time_ms(torch, lambda: run(True), reps)
+    same = all(torch.equal(outs[True][k], outs[False][k]) or
+               bool(((outs[True][k] == outs[False][k]) |
+                     (outs[True][k].isnan() & outs[False][k].isnan())).all())
+               for k in outs[True])
+    pairs = float(p.n) * float(p.q)
+    ks = 1 if p.d + 6 <= 16 else 2
+    mfma_flop_per_pair = 2 * 16 * ks  # one 32x32x16 BF16 MFMA per 1024 pairs per K-step
+    rate16 = pairs / (t16 * 1e-3)
+    return {"workload": f"mixed_l2 d={p.d} N={p.n} Q={p.q} M={p.M} l2",
+            "fp32_ms": t32, "bf16_ms": t16, "speedup": t32 / t16,
+            "fp32_pair_evals_per_s": pairs / (t32 * 1e-3), "bf16_pair_evals_per_s": rate16,
+            "identical_to_fp32": bool(same),
+            "bf16_mfma_issued_tflops": mfma_flop_per_pair * rate16 / 1e12,
+            "bf16_mfma_frac_of_2500_tflops": mfma_flop_per_pair * rate16 / 2.5e15,
+            "note": "bf16_ms includes the y sort and staging of the data (per call)"}
+
+
+def extra_batched(lf, W, torch, dev, reps=3):
+    """512 independent l2 sets (N log-uniform in [500, 50000], d in 2..10,
+    Q = 4N): one graph launch of a plan against per-set lip_fit_eval calls."""
+    probs = W.batched()
+    sets = []
+    for pb in probs:
+        sets.append(dict(x=torch.from_numpy(pb.x).to(dev), y=torch.from_numpy(pb.y).to(dev),
+                         xq=torch.from_numpy(pb.xq).to(dev),
+                         metric=lf.Metric(pb.d, pb.norm, mon=pb.mon, w=pb.w), M=pb.M))
+    plan = lf.Plan(sets)
+
+    def per_set():
+        for s_ in sets:
+            lf.fit_eval(s_["x"], s_["y"], s_["xq"], s_["metric"], M=s_["M"])
+
+    t_plan = _time_ms(torch, plan.execute, reps)
+    t_sets = _time_ms(torch, per_set, reps)
+    plan.close()
+    pairs = float(sum(pb.n * pb.q for pb in probs))
+    return {"workload": f"batched {len(probs)} sets, l2, sum N*Q = {pairs:.3e}",
+            "plan_ms": t_plan, "per_set_ms": t_sets, "speedup": t_sets / t_plan,
+            "plan_pair_evals_per_s": pairs / (t_plan * 1e-3)}
 
 
 def main():
@@ -120,24 +214,27 @@ def main():
     for nm in norms:
         f = stage_ms[nm]["forward"]
         b = stage_ms[nm]["backward"]
+        rate = pairs / (f * 1e-3)
         per_norm[nm] = {
-            "fwd_pair_evals_per_s": pairs / (f * 1e-3),
+            "fwd_pair_evals_per_s": rate,
             "fwd_bwd_pair_evals_per_s": pairs / ((f + b) * 1e-3),
             "fwd_ms": f, "bwd_ms": b,
             "knn16_ms": stage_ms[nm]["knn"], "consistency_fp64_ms": stage_ms[nm]["consistency"],
-            "valu_frac": ALG_OPS_PER_PAIR[nm] * pairs / (f * 1e-3) / VALU_PEAK_OPS,
-            "datasheet_fp32_frac": FLOP_PER_PAIR[nm] * pairs / (f * 1e-3) / 1e12
-            / FP32_DATASHEET_TFLOPS,
+            # fraction of the VALU issue peak spent on the minimal instruction mix
+            "valu_frac": SLOTS_PER_PAIR[nm] * rate / VALU_PEAK_SLOTS,
+            "datasheet_fp32_frac": FLOP_PER_PAIR[nm] * rate / 1e12 / FP32_DATASHEET_TFLOPS,
+            "consistency_fp64_valu_frac": FP64_OPS_PER_PAIR[nm] * float(N) * float(N)
+            / (stage_ms[nm]["consistency"] * 1e-3) / FP64_VALU_PEAK_SLOTS,
         }
     # dominant kernel: the forward bound kernel of the slowest norm
     dom = max(norms, key=lambda nm: stage_ms[nm]["forward"])
     f_ms = stage_ms[dom]["forward"]
-    achieved = ALG_OPS_PER_PAIR[dom] * pairs / (f_ms * 1e-3) / 1e12
-    peak = VALU_PEAK_OPS / 1e12
+    achieved = SLOTS_PER_PAIR[dom] * pairs / (f_ms * 1e-3) / 1e12
+    peak = VALU_PEAK_SLOTS / 1e12
     roofline = {"bound": "alu", "kernel": f"bounds_fwd_kernel<4,2,{nid[dom]}> ({dom})",
-                "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "Tops/s",
-                "frac": round(achieved / peak, 4), "traffic": None,
-                "ops_per_pair": ALG_OPS_PER_PAIR[dom]}
+                "achieved": round(achieved, 3), "peak": round(peak, 3),
+                "unit": "T VALU-slot/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "slots_per_pair": SLOTS_PER_PAIR[dom], "instructions_per_pair": INSTR_PER_PAIR[dom]}
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -154,6 +251,11 @@ def main():
                "sample": f"forward bounds (FP64) of {qs} seeded queries x all {N} data, "
                          f"norms {'/'.join(norms)}, {tc1 - tc0:.1f} s"}
 
+    extras = None
+    if not a.no_extras:
+        extras = {"bf16_vs_fp32": extra_bf16(lf, W, torch, dev),
+                  "batched_vs_per_set": extra_batched(lf, W, torch, dev)}
+
     rec = {
         "metric": METRIC, "value": value, "unit": "pair-evals/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms_step, "higher_is_better": True,
@@ -162,7 +264,7 @@ def main():
                    "monotone": "increasing in coordinates 1 and 3", "M": "per-point, kNN-16",
                    "step": "per norm: kNN-16 M_k (f64) + consistency (f64) + forward (f32) "
                            "+ backward (f32)", "parallelism": "single GPU"},
-        "per_norm": per_norm, "roofline": roofline, "cpu_baseline": cpu,
+        "per_norm": per_norm, "roofline": roofline, "cpu_baseline": cpu, "extras": extras,
     }
     print(json.dumps(rec))
 

@@ -31,6 +31,10 @@ CFLAGS = [
     "-Wall", "-Wno-unused-command-line-argument", "-Wno-unused-result",
 ]
 
+# Per-file extras.  bf16_l2.hip: MFMA results in VGPRs (the filter reads
+# every accumulator right away; the AGPR form would add a copy per value).
+FILE_FLAGS = {"bf16_l2.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
 
 def _headers():
     return glob.glob(os.path.join(CSRC, "*.hpp")) + [os.path.join(ROOT, "include", "lipfit.h")]
@@ -46,7 +50,8 @@ def _compile(src: str, force: bool) -> str:
     if not force and os.path.exists(obj) and os.path.getmtime(obj) >= newest:
         return obj
     lang = ["-x", "hip"] if src.endswith(".hip") else []
-    cmd = [HIPCC, *CFLAGS, *lang, "-c", src, "-o", obj + ".tmp"]
+    cmd = [HIPCC, *CFLAGS, *FILE_FLAGS.get(os.path.basename(src), []), *lang, "-c", src,
+           "-o", obj + ".tmp"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     err = "\n".join(l for l in (r.stderr or "").splitlines()
                     if "packed-fp32-ops" not in l and "is not a recognized feature" not in l)

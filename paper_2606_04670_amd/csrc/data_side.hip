@@ -49,6 +49,80 @@ static hipError_t launch_stage64(int d, const float *x, const float *y, const fl
     return hipGetLastError();
 }
 
+// ---- spatial order of the data for the kNN pass ----------------------------------
+//
+// Morton (bit-interleaved) code of the coordinates quantised to b bits each
+// (b = 32 / d, at least 1) inside the data's bounding box, packed as
+// (code << 32 | index) and sorted: consecutive positions are spatial
+// neighbours.  Only the order of the rows and the threshold pass depend on
+// it; every kNN list is still formed from all columns in index order.
+
+__device__ __forceinline__ unsigned long long f64_key(double v)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+__device__ __forceinline__ double f64_unkey(unsigned long long k)
+{
+    return __longlong_as_double((long long)((k >> 63) ? (k & 0x7FFFFFFFFFFFFFFFull) : ~k));
+}
+
+__global__ void bbox_init_kernel(unsigned long long *bb, int d)
+{
+    const int j = threadIdx.x;
+    if (j < d) {
+        bb[j] = ~0ull;  // min keys
+        bb[kMaxDim + j] = 0ull;  // max keys
+    }
+}
+
+__global__ void bbox_kernel(const double *X, int64_t n, int64_t npad, int d, unsigned long long *bb)
+{
+    for (int j = 0; j < d; ++j) {
+        double lo = __builtin_inf(), hi = -__builtin_inf();
+        const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+        for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
+            const double v = X[(int64_t)j * npad + k];
+            lo = fmin(lo, v);
+            hi = fmax(hi, v);
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            lo = fmin(lo, __shfl_xor(lo, off));
+            hi = fmax(hi, __shfl_xor(hi, off));
+        }
+        if ((threadIdx.x & 63) == 0) {
+            atomicMin(bb + j, f64_key(lo));
+            atomicMax(bb + kMaxDim + j, f64_key(hi));
+        }
+    }
+}
+
+__global__ void morton_kernel(const double *X, int64_t n, int64_t npad, int d, int64_t P,
+                              const unsigned long long *bb, unsigned long long *keys)
+{
+    const int bits = 32 / d > 0 ? (32 / d < 16 ? 32 / d : 16) : 1;
+    const double cells = (double)(1u << bits);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < P; k += stride) {
+        if (k >= n) {
+            keys[k] = ~0ull;
+            continue;
+        }
+        uint32_t q[kMaxDim];
+        for (int j = 0; j < d; ++j) {
+            const double lo = f64_unkey(bb[j]), hi = f64_unkey(bb[kMaxDim + j]);
+            double t = hi > lo ? (X[(int64_t)j * npad + k] - lo) / (hi - lo) * cells : 0.0;
+            t = t < 0.0 ? 0.0 : (t > cells - 1.0 ? cells - 1.0 : t);  // NaN -> cells - 1
+            q[j] = (uint32_t)t;
+        }
+        unsigned long long code = 0;
+        for (int b = bits - 1; b >= 0; --b)
+            for (int j = 0; j < d; ++j) code = (code << 1) | ((q[j] >> b) & 1u);
+        keys[k] = (code << 32) | (uint32_t)k;
+    }
+}
+
 __global__ void zero_counts_kernel(unsigned long long *c)
 {
     if (threadIdx.x < 2) c[threadIdx.x] = 0ull;
@@ -171,7 +245,9 @@ size_t data_side_ws_bytes(int64_t n, int d)
 {
     const size_t staged = align_up((size_t)ds_npad(n) * (size_t)(d + 2) * 8, 256);
     const size_t cons = (size_t)kDsMaxChunks * (size_t)n * 24;
-    const size_t knn = (size_t)kKnnMaxChunks * (size_t)n * LIP_MAX_KNN * 12;
+    const size_t knn = align_up((size_t)kKnnMaxChunks * (size_t)n * LIP_MAX_KNN * 12, 256) +
+                       align_up((size_t)sort_len(n) * 8, 256) + align_up((size_t)n * 8, 256) +
+                       2 * kMaxDim * 8;
     const size_t part = cons > knn ? cons : knn;
     return staged + align_up(part, 256) + 4096;
 }
@@ -326,6 +402,26 @@ extern "C" lip_status lip_estimate_M(const lip_metric *metric, const float *x, c
         const size_t e = (size_t)A.n_chunks * (size_t)n * (size_t)K;
         A.kkey = (double *)p;
         A.kidx = (int32_t *)(A.kkey + e);
+        char *q = p + align_up((size_t)kKnnMaxChunks * (size_t)n * LIP_MAX_KNN * 12, 256);
+        const int64_t P = sort_len(n);
+        unsigned long long *order = (unsigned long long *)q;
+        q += align_up((size_t)P * 8, 256);
+        A.tau = (double *)q;
+        q += align_up((size_t)n * 8, 256);
+        unsigned long long *bb = (unsigned long long *)q;
+        // spatial order of the rows and the per-row threshold pass
+        int64_t gb = (n + 255) / 256;
+        if (gb > 1024) gb = 1024;
+        hipLaunchKernelGGL(bbox_init_kernel, dim3(1), dim3(64), 0, s, bb, mi.d);
+        hipLaunchKernelGGL(bbox_kernel, dim3((unsigned)gb), dim3(256), 0, s, A.X, n, A.npad, mi.d,
+                           bb);
+        int64_t gm = (P + 255) / 256;
+        if (gm > 65536) gm = 65536;
+        hipLaunchKernelGGL(morton_kernel, dim3((unsigned)gm), dim3(256), 0, s, A.X, n, A.npad,
+                           mi.d, P, bb, order);
+        if (launch_sort_u64(order, P, s) != hipSuccess) return LIP_E_DEVICE;
+        A.order = order;
+        (K == 16 ? L.tau16 : L.tau32)(A, dim3((unsigned)((n + 63) / 64)), dim3(64), s);
         const dim3 g(grid_for_rows(n, 64, A.n_chunks)), b(256);
         (K == 16 ? L.knn16 : L.knn32)(A, g, b, s);
         if (A.n_chunks > 1)

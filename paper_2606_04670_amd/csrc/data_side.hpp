@@ -46,6 +46,7 @@ constexpr int kDsTile = 64;       // columns per partner tile
 constexpr int kDsGroup = 4;       // columns per scalar-load group
 constexpr int kDsMaxChunks = 16;  // column chunks (consistency, slope)
 constexpr int kKnnMaxChunks = 4;  // column chunks (kNN)
+constexpr int kKnnWin = 192;      // spatial-order window of the kNN threshold pass
 constexpr int64_t kDsTargetWaves = 8192;
 
 struct DsArgs {
@@ -70,6 +71,8 @@ struct DsArgs {
     // kNN: partial lists [n_chunks][n][K]
     double *kkey;
     int32_t *kidx;
+    const unsigned long long *order;  // kNN row order: (Morton code << 32 | index), sorted
+    double *tau;                       // [n] per-row bound on the knn-th smallest key
     double *M64;
     float *M32;
 };
@@ -486,15 +489,86 @@ __device__ __forceinline__ void knn_finish(const DsArgs &A, int64_t i, const dou
     }
 }
 
+// Smallest double above a finite t.
+__device__ __forceinline__ double next_up(double t)
+{
+    const long long b = __double_as_longlong(t);
+    if (t == 0.0) return __longlong_as_double(1ll);
+    return __longlong_as_double(t > 0.0 ? b + 1 : b - 1);
+}
+
+// Threshold pass.  A wave takes 64 consecutive rows of the spatial (Morton)
+// order and the kKnnWin data around them in that order, staged in LDS; each
+// row keeps the knn smallest keys over that window (itself excluded).  The
+// knn-th of them bounds the knn-th smallest key over all data from above, so
+// the full scan can skip every column above it.  Keys are formed with the
+// same operation sequence as in the full scan.
+template <int D, int NORM, bool HASW, int K>
+__global__ void __launch_bounds__(64) knn_tau_kernel(DsArgs A)
+{
+    __shared__ double win[D][kKnnWin];
+    __shared__ int32_t wid[kKnnWin];
+    const int lane = threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * 64;
+    int64_t wlo = r0 - (kKnnWin - 64) / 2;
+    if (wlo + kKnnWin > A.n) wlo = A.n - kKnnWin;
+    if (wlo < 0) wlo = 0;
+    const int nw = (int)(A.n - wlo < kKnnWin ? A.n - wlo : kKnnWin);
+    for (int t = lane; t < nw; t += 64) {
+        const int64_t c = (int64_t)(uint32_t)(A.order[wlo + t] & 0xFFFFFFFFull);
+        wid[t] = (int32_t)c;
+#pragma unroll
+        for (int j = 0; j < D; ++j) win[j][t] = A.X[(int64_t)j * A.npad + c];
+    }
+    __syncthreads();
+    const int64_t pos = r0 + lane;
+    if (pos >= A.n) return;
+    const int64_t i = (int64_t)(uint32_t)(A.order[pos] & 0xFFFFFFFFull);
+    double xr[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) xr[j] = A.X[(int64_t)j * A.npad + i];
+    double key[K];
+    int idx[K];
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+        key[t] = __builtin_inf();
+        idx[t] = -1;
+    }
+    const int kk = A.knn;
+    double thr = __builtin_inf();
+#pragma unroll 1
+    for (int t = 0; t < nw; ++t) {
+        double su = 0.0, sl = 0.0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const double dd = xr[j] - win[j][t];
+            if (j == 0)
+                ds_step<NORM, HASW, false, true>(1.0, A.w[j], dd, su, sl);
+            else
+                ds_step<NORM, HASW, false, false>(1.0, A.w[j], dd, su, sl);
+        }
+        if (wid[t] != (int32_t)i && su < thr) {
+            knn_insert<K>(key, idx, su, wid[t]);
+#pragma unroll
+            for (int q = 0; q < K; ++q)
+                if (q == kk - 1) thr = key[q];
+        }
+    }
+    A.tau[i] = thr;
+}
+
 template <int D, int NORM, bool HASW, int K>
 __global__ void __launch_bounds__(256) knn_kernel(DsArgs A)
 {
     WaveRange w;
     if (!wave_range(A, 64, w)) return;
     const int lane = threadIdx.x & 63;
-    const int64_t i0 = w.r0 + lane;
-    const bool valid = i0 < A.n;
-    const int64_t i = valid ? i0 : A.n - 1;
+    const int64_t p0 = w.r0 + lane;
+    const bool valid = p0 < A.n;
+    const int64_t pc = valid ? p0 : A.n - 1;
+    // rows in spatial order (when given), so that the 64 rows of a wave are
+    // neighbours and share most of their candidate columns
+    const int64_t i = A.order ? (int64_t)(uint32_t)(A.order[pc] & 0xFFFFFFFFull) : pc;
     double xr[1][D];
 #pragma unroll
     for (int j = 0; j < D; ++j) xr[0][j] = A.X[(int64_t)j * A.npad + i];
@@ -505,9 +579,15 @@ __global__ void __launch_bounds__(256) knn_kernel(DsArgs A)
         key[t] = __builtin_inf();
         idx[t] = -1;
     }
-    // Only the first knn (<= K) slots matter; thr is the knn-th smallest key.
+    // Only the first knn (<= K) slots matter; thr is the knn-th smallest key,
+    // and never above the row's bound from the threshold pass (a column with
+    // a key equal to that bound is still taken).
     const int kk = A.knn;
     double thr = __builtin_inf();
+    if (A.tau) {
+        const double t0 = A.tau[i];
+        thr = t0 < __builtin_inf() ? next_up(t0) : t0;
+    }
     const cdouble_ptr X = (cdouble_ptr)(A.X);
 #pragma unroll 1
     for (int64_t g0 = w.c0; g0 < w.c1; g0 += kDsGroup) {
@@ -519,9 +599,13 @@ __global__ void __launch_bounds__(256) knn_kernel(DsArgs A)
             const int64_t k = g0 + c;
             if (k < A.n && k != i && su[c][0] < thr) {
                 knn_insert<K>(key, idx, su[c][0], (int)k);
+                if (kk == K) {
+                    thr = key[K - 1] < thr ? key[K - 1] : thr;
+                } else {
 #pragma unroll
-                for (int t = 0; t < K; ++t)
-                    if (t == kk - 1) thr = key[t];
+                    for (int t = 0; t < K; ++t)
+                        if (t == kk - 1) thr = key[t] < thr ? key[t] : thr;
+                }
             }
         }
     }
@@ -582,7 +666,7 @@ __global__ void __launch_bounds__(256) knn_merge_kernel(DsArgs A)
 typedef void (*DsLaunch)(const DsArgs &, dim3, dim3, hipStream_t);
 
 struct DsLaunchers {
-    DsLaunch consistency, consistency_mon, slope, knn16, knn32, merge16, merge32;
+    DsLaunch consistency, consistency_mon, slope, knn16, knn32, merge16, merge32, tau16, tau32;
 };
 
 template <int D, int NORM, bool HASW>
@@ -603,6 +687,12 @@ DsLaunchers ds_launchers_for()
     };
     L.knn32 = [](const DsArgs &a, dim3 g, dim3 b, hipStream_t s) {
         hipLaunchKernelGGL((knn_kernel<D, NORM, HASW, 32>), g, b, 0, s, a);
+    };
+    L.tau16 = [](const DsArgs &a, dim3 g, dim3 b, hipStream_t s) {
+        hipLaunchKernelGGL((knn_tau_kernel<D, NORM, HASW, 16>), g, b, 0, s, a);
+    };
+    L.tau32 = [](const DsArgs &a, dim3 g, dim3 b, hipStream_t s) {
+        hipLaunchKernelGGL((knn_tau_kernel<D, NORM, HASW, 32>), g, b, 0, s, a);
     };
     L.merge16 = [](const DsArgs &a, dim3 g, dim3 b, hipStream_t s) {
         hipLaunchKernelGGL((knn_merge_kernel<D, NORM, HASW, 16>), g, b, 0, s, a);

@@ -82,6 +82,11 @@ hipError_t launch_combine(const CombineArgs &a, hipStream_t s);
 hipError_t launch_nonfinite(const float *v, int64_t n, int *flag, hipStream_t s);
 hipError_t launch_fill_i32(int *p, int64_t n, int v, hipStream_t s);
 
+// Ascending in-place sort of P 64-bit keys, P = sort_len(n) (a power of two
+// >= max(n, 1024); the caller pads with ~0) (sort.hip).
+int64_t sort_len(int64_t n);
+hipError_t launch_sort_u64(unsigned long long *keys, int64_t P, hipStream_t s);
+
 FwdLaunchers fwd_launchers_l1(int d, int dm);
 FwdLaunchers fwd_launchers_l2(int d, int dm);
 FwdLaunchers fwd_launchers_linf(int d, int dm);
