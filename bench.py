@@ -63,6 +63,39 @@ FP64_OPS_PER_PAIR = {"l1": 4 + 16 + 6 + 6 + 2 + 2, "linf": 4 + 16 + 6 + 6 + 2 + 
                      "l2": 4 + 16 + 12 + 20 + 6 + 2 + 2}
 
 
+# HBM traffic of the forward kernel, from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# runs scaled by a 1 GiB copy kernel (profiles/, with the command that made
+# it).  Reported only while the kernel's sources are the ones profiled.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "bounds_fwd_monotone_local_traffic.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2606_04670_amd", "csrc", f)
+                  for f in ("bounds_fwd.hpp", "lip_device.hpp", "lip_internal.hpp",
+                            "bounds_fwd_l1.hip", "bounds_fwd_l2.hip", "bounds_fwd_linf.hip")]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(norm):
+    """Bytes per launch of the forward kernel for `norm`, or None."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            for line in fh:
+                if line.startswith("TRAFFIC_JSON "):
+                    rec = json.loads(line[len("TRAFFIC_JSON "):])
+                    if rec.get("source_sha256") != kernel_source_hash():
+                        return None
+                    return rec["bytes_per_launch"].get(norm)
+    except OSError:
+        return None
+    return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -233,7 +266,8 @@ def main():
     peak = VALU_PEAK_SLOTS / 1e12
     roofline = {"bound": "alu", "kernel": f"bounds_fwd_kernel<4,2,{nid[dom]}> ({dom})",
                 "achieved": round(achieved, 3), "peak": round(peak, 3),
-                "unit": "T VALU-slot/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "unit": "T VALU-slot/s", "frac": round(achieved / peak, 4),
+                "traffic": measured_traffic(dom),
                 "slots_per_pair": SLOTS_PER_PAIR[dom], "instructions_per_pair": INSTR_PER_PAIR[dom]}
 
     cpu = None

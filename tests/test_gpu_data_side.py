@@ -166,3 +166,35 @@ def test_estimates_monotone_local_workload_sampled(lf, norm):
         dy = np.abs(p.y.astype(np.float64) - p.y[r])
         msk = d > 0
         assert np.max(dy[msk] / d[msk]) <= G64.item() * (1 + 1e-12)
+
+
+@pytest.mark.parametrize("norm", [1, 2, 3])
+def test_estimate_knn_lattice_ties_chunked(lf, norm):
+    """Integer lattice data (many exactly equal distances, duplicated points
+    with equal and with different y) at N = 8,000: several column chunks and
+    a spatial row order whose windows hold many ties.  Neighbour ranking by
+    (distance, index) must match the oracle exactly."""
+    rng = np.random.default_rng(81 + norm)
+    x = rng.integers(0, 10, (8000, 3)).astype(np.float32)
+    y = (x @ np.array([1.0, -2.0, 0.5], np.float32)).astype(np.float32)
+    odd = rng.random(8000) < 0.02  # a few duplicates disagree: infinite slopes
+    y[odd] += np.float32(0.25)
+    met = lf.Metric(3, norm)
+    M64, M32, _ = lf.estimate_M(_t(x), _t(y), met, mode="knn", knn=16)
+    st, Mo, _ = oracle.estimate_M_knn(x, y, norm, K=16)
+    np.testing.assert_array_equal(M64.cpu().numpy(), Mo)
+
+
+def test_estimate_knn_high_dim_clustered(lf):
+    """d = 16, clustered data (the spatial order is coarse at 2 bits per
+    coordinate), weighted l2, K = 16 and K = 7."""
+    rng = np.random.default_rng(83)
+    centres = rng.standard_normal((12, 16))
+    x = (centres[rng.integers(0, 12, 3000)] + 0.05 * rng.standard_normal((3000, 16))).astype(np.float32)
+    y = rng.standard_normal(3000).astype(np.float32)
+    w = (0.5 + rng.random(16)).astype(np.float32)
+    met = lf.Metric(16, 2, w=w)
+    for K in (16, 7):
+        M64, _, _ = lf.estimate_M(_t(x), _t(y), met, mode="knn", knn=K)
+        st, Mo, _ = oracle.estimate_M_knn(x, y, 2, K=K, w=w)
+        np.testing.assert_array_equal(M64.cpu().numpy(), Mo)
