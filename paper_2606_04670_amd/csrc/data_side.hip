@@ -269,6 +269,7 @@ static bool fill_ds_metric(const MetricInfo &mi, bool use_mon, DsArgs *A, Signs 
         A->w[i] = i < mi.d ? mi.w[i] : 1.0;
         const int m = (use_mon && i < mi.d) ? mi.mon[i] : 0;
         A->fsel[i] = m != 0 ? 0.0 : 1.0;
+        if (i < mi.d && m == 0) A->fmask |= 1 << i;
         sg->s[i] = m < 0 ? -1.0f : 1.0f;
         if (i < mi.d && mi.w[i] != 1.0) hasw = true;
     }

@@ -34,8 +34,10 @@
 // ballot + popcount into scalar registers.
 #pragma once
 
+#include <array>
 #include <climits>
 #include <float.h>
+#include <utility>
 
 #include "host_common.hpp"
 
@@ -55,6 +57,7 @@ struct DsArgs {
     double w[kMaxDim];
     double fsel[kMaxDim];   // 1 free, 0 monotone (decreasing ones negated at staging)
     double tol;
+    int32_t fmask;          // bit i: coordinate i free (consistency with monotone coordinates)
     int32_t n_chunks;
     int32_t knn;
     int64_t chunk_cols;  // columns per chunk (multiple of kDsTile)
@@ -167,10 +170,36 @@ __device__ __forceinline__ void ds_dist1(const DsArgs &A, const double (&xr)[D],
     if (!MON) sl = su;
 }
 
+// Component step with the coordinate's kind known at compile time: a free
+// coordinate adds |d| to both distances, a monotone one (d)_+ to the upper
+// and (-d)_+ to the lower one.  Bit for bit the values of the branch-free
+// ds_step (fma(1, q, p) = p + q = |d| and fma(0, q, p) = p exactly, since
+// one of p, q is zero).
+template <int NORM, bool HASW, bool FREE, bool FIRST>
+__device__ __forceinline__ void ds_step_kind(double w, double d, double &su, double &sl)
+{
+    if constexpr (FREE) {
+        double a = fabs(d);
+        if (HASW) a = w * a;
+        su = ds_acc<NORM, FIRST>(su, a);
+        sl = ds_acc<NORM, FIRST>(sl, a);
+    } else {
+        double p = pos_part(d), q = neg_part(d);
+        if (HASW) {
+            p = w * p;
+            q = w * q;
+        }
+        su = ds_acc<NORM, FIRST>(su, p);
+        sl = ds_acc<NORM, FIRST>(sl, q);
+    }
+}
+
 // Distances of R rows to the columns g0 .. g0 + kDsGroup - 1 (scalar
 // loads of one coordinate of the whole group at a time).  For l2 the sums
-// of squares are returned (no root); without MON only su is formed.
-template <int D, int NORM, bool HASW, bool MON, int R>
+// of squares are returned (no root); without MON only su is formed.  FM >= 0
+// gives the free / monotone kind of every coordinate at compile time (bit i
+// set: coordinate i free); FM < 0 reads it from A.fsel at run time.
+template <int D, int NORM, bool HASW, bool MON, int R, int FM = -1>
 __device__ __forceinline__ void ds_dist_group(const DsArgs &A, cdouble_ptr X, int64_t g0,
                                               const double (&xr)[R][D],
                                               double (&su)[kDsGroup][R],
@@ -186,10 +215,21 @@ __device__ __forceinline__ void ds_dist_group(const DsArgs &A, cdouble_ptr X, in
         for (int c = 0; c < kDsGroup; ++c)
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                if (i == 0)
-                    ds_step<NORM, HASW, MON, true>(f, w, xr[r][i] - xc[c], su[c][r], sl[c][r]);
-                else
-                    ds_step<NORM, HASW, MON, false>(f, w, xr[r][i] - xc[c], su[c][r], sl[c][r]);
+                const double d = xr[r][i] - xc[c];
+                if constexpr (MON && FM >= 0) {
+                    const bool fr = (FM >> i) & 1;
+                    if (i == 0) {
+                        if (fr) ds_step_kind<NORM, HASW, true, true>(w, d, su[c][r], sl[c][r]);
+                        else ds_step_kind<NORM, HASW, false, true>(w, d, su[c][r], sl[c][r]);
+                    } else {
+                        if (fr) ds_step_kind<NORM, HASW, true, false>(w, d, su[c][r], sl[c][r]);
+                        else ds_step_kind<NORM, HASW, false, false>(w, d, su[c][r], sl[c][r]);
+                    }
+                } else if (i == 0) {
+                    ds_step<NORM, HASW, MON, true>(f, w, d, su[c][r], sl[c][r]);
+                } else {
+                    ds_step<NORM, HASW, MON, false>(f, w, d, su[c][r], sl[c][r]);
+                }
             }
     }
 }
@@ -215,7 +255,7 @@ __device__ __forceinline__ bool wave_range(const DsArgs &A, int rows_per_wave, W
 
 // ---- consistency -------------------------------------------------------------
 
-template <int D, int NORM, bool HASW, bool MON, bool MASK>
+template <int D, int NORM, bool HASW, bool MON, bool MASK, int FM>
 __device__ __forceinline__ void cons_group(const DsArgs &A, cdouble_ptr X, int64_t g0,
                                            const double (&xr)[kDsRows][D],
                                            const double (&yr)[kDsRows], const int (&ir)[kDsRows],
@@ -224,7 +264,7 @@ __device__ __forceinline__ void cons_group(const DsArgs &A, cdouble_ptr X, int64
                                            unsigned long long &cl)
 {
     double su[kDsGroup][kDsRows], sl[kDsGroup][kDsRows];
-    ds_dist_group<D, NORM, HASW, MON, kDsRows>(A, X, g0, xr, su, sl);
+    ds_dist_group<D, NORM, HASW, MON, kDsRows, FM>(A, X, g0, xr, su, sl);
     double yk[kDsGroup], mk[kDsGroup];
 #pragma unroll
     for (int c = 0; c < kDsGroup; ++c) {
@@ -266,7 +306,7 @@ __device__ __forceinline__ void cons_pair(const DsArgs &A, const double (&xr)[D]
     tl = yr - (yk - mk * dl);
 }
 
-template <int D, int NORM, bool HASW, bool MON>
+template <int D, int NORM, bool HASW, bool MON, int FM = -1>
 __global__ void __launch_bounds__(256) consistency_kernel(DsArgs A)
 {
     constexpr int RW = 64 * kDsRows;
@@ -304,9 +344,9 @@ __global__ void __launch_bounds__(256) consistency_kernel(DsArgs A)
         for (int64_t g0 = tb; g0 < te; g0 += kDsGroup) {
             const bool masked = (g0 + kDsGroup > A.n) || (g0 < w.r1 && g0 + kDsGroup > w.r0);
             if (masked)
-                cons_group<D, NORM, HASW, MON, true>(A, X, g0, xr, yr, ir, valid, bu, bl, cu, cl);
+                cons_group<D, NORM, HASW, MON, true, FM>(A, X, g0, xr, yr, ir, valid, bu, bl, cu, cl);
             else
-                cons_group<D, NORM, HASW, MON, false>(A, X, g0, xr, yr, ir, valid, bu, bl, cu, cl);
+                cons_group<D, NORM, HASW, MON, false, FM>(A, X, g0, xr, yr, ir, valid, bu, bl, cu, cl);
         }
 #pragma unroll
         for (int r = 0; r < kDsRows; ++r) {
@@ -669,6 +709,18 @@ struct DsLaunchers {
     DsLaunch consistency, consistency_mon, slope, knn16, knn32, merge16, merge32, tau16, tau32;
 };
 
+// Dimensions up to which the consistency pass has one kernel per free /
+// monotone pattern of the coordinates.
+constexpr int kDsMaskDims = 4;
+
+typedef void (*DsKernel)(DsArgs);
+
+template <int D, int NORM, bool HASW, int... FMs>
+constexpr std::array<DsKernel, sizeof...(FMs)> cons_mask_table(std::integer_sequence<int, FMs...>)
+{
+    return {{&consistency_kernel<D, NORM, HASW, true, FMs>...}};
+}
+
 template <int D, int NORM, bool HASW>
 DsLaunchers ds_launchers_for()
 {
@@ -677,6 +729,14 @@ DsLaunchers ds_launchers_for()
         hipLaunchKernelGGL((consistency_kernel<D, NORM, HASW, false>), g, b, 0, s, a);
     };
     L.consistency_mon = [](const DsArgs &a, dim3 g, dim3 b, hipStream_t s) {
+        if constexpr (D <= kDsMaskDims) {
+            // every free / monotone pattern of a low dimension has its own kernel
+            constexpr auto tbl = cons_mask_table<D, NORM, HASW>(std::make_integer_sequence<int, (1 << D)>{});
+            if (a.fmask >= 0 && a.fmask < (1 << D)) {
+                hipLaunchKernelGGL(tbl[a.fmask], g, b, 0, s, a);
+                return;
+            }
+        }
         hipLaunchKernelGGL((consistency_kernel<D, NORM, HASW, true>), g, b, 0, s, a);
     };
     L.slope = [](const DsArgs &a, dim3 g, dim3 b, hipStream_t s) {

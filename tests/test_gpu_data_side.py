@@ -198,3 +198,28 @@ def test_estimate_knn_high_dim_clustered(lf):
         M64, _, _ = lf.estimate_M(_t(x), _t(y), met, mode="knn", knn=K)
         st, Mo, _ = oracle.estimate_M_knn(x, y, 2, K=K, w=w)
         np.testing.assert_array_equal(M64.cpu().numpy(), Mo)
+
+
+def _patterns(d):
+    import itertools
+    return [np.array(m, np.int8) for m in itertools.product((-1, 0, 1), repeat=d)]
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 4])
+def test_consistency_every_pattern_low_dim(lf, d):
+    """Up to d = 4 every free / increasing / decreasing pattern has its own
+    kernel; each must reproduce the oracle exactly (all patterns for d <= 3,
+    a seeded third of them for d = 4), norms and weights varied."""
+    pats = _patterns(d)
+    if d == 4:
+        rng = np.random.default_rng(4)
+        pats = [pats[i] for i in sorted(rng.choice(len(pats), 27, replace=False))]
+    for k, mon in enumerate(pats):
+        norm = 1 + k % 3
+        p = W.random_problem(900 + 10 * d + k, n=333 + 17 * k, q=1, d=d, norm=norm, mon=mon,
+                             local=(k % 2 == 0), weighted=(k % 4 == 1))
+        g = _consistency(lf, p, 1.25, p.Mk)
+        o = oracle.consistency(p.x, p.y, norm, M=1.25, Mk=p.Mk, mon=p.mon, w=p.w)
+        for key in ("slack_up", "slack_lo", "partner_up", "partner_lo"):
+            np.testing.assert_array_equal(g[key], o[key], err_msg=f"d={d} mon={mon.tolist()} {key}")
+        assert g["counts"].tolist() == [o["viol_up"].sum(), o["viol_lo"].sum()], mon.tolist()
