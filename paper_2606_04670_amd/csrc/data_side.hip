@@ -245,7 +245,7 @@ size_t data_side_ws_bytes(int64_t n, int d)
 {
     const size_t staged = align_up((size_t)ds_npad(n) * (size_t)(d + 2) * 8, 256);
     const size_t cons = (size_t)kDsMaxChunks * (size_t)n * 24;
-    const size_t knn = align_up((size_t)kKnnMaxChunks * (size_t)n * LIP_MAX_KNN * 12, 256) +
+    const size_t knn = align_up((size_t)n * 4, 256) + align_up((size_t)n * kKnnCap * 4, 256) +
                        align_up((size_t)sort_len(n) * 8, 256) + align_up((size_t)n * 8, 256) +
                        2 * kMaxDim * 8;
     const size_t part = cons > knn ? cons : knn;
@@ -399,17 +399,18 @@ extern "C" lip_status lip_estimate_M(const lip_metric *metric, const float *x, c
     } else {
         A.knn = knn;
         const int K = knn <= 16 ? 16 : 32;
-        choose_chunks(n, 64, kKnnMaxChunks, &A);
-        const size_t e = (size_t)A.n_chunks * (size_t)n * (size_t)K;
-        A.kkey = (double *)p;
-        A.kidx = (int32_t *)(A.kkey + e);
-        char *q = p + align_up((size_t)kKnnMaxChunks * (size_t)n * LIP_MAX_KNN * 12, 256);
+        char *q = p;
+        A.kcnt = (int32_t *)q;
+        q += align_up((size_t)n * 4, 256);
+        A.kcand = (int32_t *)q;
+        q += align_up((size_t)n * kKnnCap * 4, 256);
         const int64_t P = sort_len(n);
         unsigned long long *order = (unsigned long long *)q;
         q += align_up((size_t)P * 8, 256);
         A.tau = (double *)q;
         q += align_up((size_t)n * 8, 256);
         unsigned long long *bb = (unsigned long long *)q;
+        A.x32 = x;
         // spatial order of the rows and the per-row threshold pass
         int64_t gb = (n + 255) / 256;
         if (gb > 1024) gb = 1024;
@@ -423,10 +424,12 @@ extern "C" lip_status lip_estimate_M(const lip_metric *metric, const float *x, c
         if (launch_sort_u64(order, P, s) != hipSuccess) return LIP_E_DEVICE;
         A.order = order;
         (K == 16 ? L.tau16 : L.tau32)(A, dim3((unsigned)((n + 63) / 64)), dim3(64), s);
-        const dim3 g(grid_for_rows(n, 64, A.n_chunks)), b(256);
-        (K == 16 ? L.knn16 : L.knn32)(A, g, b, s);
-        if (A.n_chunks > 1)
-            (K == 16 ? L.merge16 : L.merge32)(A, dim3((unsigned)((n + 255) / 256)), b, s);
+        // FP32 candidate scan over all pairs, then the exact ranking per row
+        if (launch_fill_i32(A.kcnt, n, 0, s) != hipSuccess) return LIP_E_DEVICE;
+        const int rows = 64 * rows_for_dim(mi.d);
+        choose_chunks(n, rows, kKnnMaxChunks, &A);
+        L.scan(A, dim3(grid_for_rows(n, rows, A.n_chunks)), dim3(256), s);
+        (K == 16 ? L.select16 : L.select32)(A, dim3((unsigned)((n + 255) / 256)), dim3(256), s);
     }
     return dev_status(hipGetLastError());
 }

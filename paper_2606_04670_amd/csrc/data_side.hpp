@@ -37,6 +37,7 @@
 #include <array>
 #include <climits>
 #include <float.h>
+#include <type_traits>
 #include <utility>
 
 #include "host_common.hpp"
@@ -47,7 +48,7 @@ constexpr int kDsRows = 2;        // rows per lane (consistency, slope)
 constexpr int kDsTile = 64;       // columns per partner tile
 constexpr int kDsGroup = 4;       // columns per scalar-load group
 constexpr int kDsMaxChunks = 16;  // column chunks (consistency, slope)
-constexpr int kKnnMaxChunks = 4;  // column chunks (kNN)
+constexpr int kKnnMaxChunks = 32; // column chunks (kNN candidate scan)
 constexpr int kKnnWin = 192;      // spatial-order window of the kNN threshold pass
 constexpr int64_t kDsTargetWaves = 8192;
 
@@ -71,9 +72,10 @@ struct DsArgs {
     double *row_best;
     int32_t *row_arg;
     int32_t *row_dup;
-    // kNN: partial lists [n_chunks][n][K]
-    double *kkey;
-    int32_t *kidx;
+    // kNN: per-row candidate counters [n] and lists [n][kKnnCap]
+    const float *x32;  // the caller's x [n][D] (FP32 candidate scan)
+    int32_t *kcnt;
+    int32_t *kcand;
     const unsigned long long *order;  // kNN row order: (Morton code << 32 | index), sorted
     double *tau;                       // [n] per-row bound on the knn-th smallest key
     double *M64;
@@ -597,21 +599,163 @@ __global__ void __launch_bounds__(64) knn_tau_kernel(DsArgs A)
     A.tau[i] = thr;
 }
 
-template <int D, int NORM, bool HASW, int K>
-__global__ void __launch_bounds__(256) knn_kernel(DsArgs A)
+// Candidate scan.  In FP32, every pair (row i, column k) of the rows' spatial
+// order x the chunk's columns is tested against the row's bound from the
+// threshold pass, tau32 >= tau (1 + 2^-17) + 2^-120.  The FP32 key (the same
+// sum / sum of squares / max as the FP64 key, each operation rounded to
+// FP32) is within (d + 3) 2^-24 relative of the exact value, so every column
+// whose FP64 key is <= tau passes.  Passing columns (a few dozen per row)
+// are appended to the row's candidate list with an atomic counter; the
+// select pass ranks them exactly.  Rows per lane follow the FP32 bound
+// kernel; columns come through scalar loads in double-buffered groups.
+constexpr int kKnnCap = 512;  // candidate slots per row (a few dozen are typical)
+
+constexpr int knn_group(int D) { return D <= 4 ? 4 : (D <= 8 ? 2 : 1); }
+
+__device__ __forceinline__ float knn_tau32(double t)
 {
-    WaveRange w;
-    if (!wave_range(A, 64, w)) return;
-    const int lane = threadIdx.x & 63;
-    const int64_t p0 = w.r0 + lane;
-    const bool valid = p0 < A.n;
-    const int64_t pc = valid ? p0 : A.n - 1;
-    // rows in spatial order (when given), so that the 64 rows of a wave are
-    // neighbours and share most of their candidate columns
-    const int64_t i = A.order ? (int64_t)(uint32_t)(A.order[pc] & 0xFFFFFFFFull) : pc;
-    double xr[1][D];
+    if (!(t < __builtin_inf())) return __builtin_inff();
+    const double v = t * (1.0 + 0x1p-17) + 0x1p-120;
+    float f = (float)v;
+    if ((double)f < v) f = __uint_as_float(__float_as_uint(f) + 1u);  // v >= 0: next float up
+    return f;
+}
+
+template <int D, int NORM, bool HASW>
+__device__ __forceinline__ float knn_key32(const float (&xr)[D], const float *v, const float (&w)[D])
+{
+    float s = 0.0f;
 #pragma unroll
-    for (int j = 0; j < D; ++j) xr[0][j] = A.X[(int64_t)j * A.npad + i];
+    for (int j = 0; j < D; ++j) {
+        float a = fabsf(xr[j] - v[j]);
+        if (HASW) a = a * w[j];
+        if (NORM == 1) s = j == 0 ? a : s + a;
+        else if (NORM == 2) s = j == 0 ? a * a : fmaf(a, a, s);
+        else s = j == 0 ? a : fmaxf(s, a);
+    }
+    return s;
+}
+
+template <int D, int NORM, bool HASW>
+__global__ void __launch_bounds__(256) knn_scan_kernel(DsArgs A)
+{
+    constexpr int R = rows_for_dim(D);
+    constexpr int G = knn_group(D);
+    WaveRange w;
+    if (!wave_range(A, 64 * R, w)) return;
+    const int lane = threadIdx.x & 63;
+    float xr[R][D], tr[R];
+    int32_t ir[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t p0 = w.r0 + r * 64 + lane;
+        const bool valid = p0 < A.n;
+        const int64_t pc = valid ? p0 : A.n - 1;
+        const int64_t i = (int64_t)(uint32_t)(A.order[pc] & 0xFFFFFFFFull);
+        ir[r] = (int32_t)i;
+#pragma unroll
+        for (int j = 0; j < D; ++j) xr[r][j] = A.x32[i * D + j];
+        tr[r] = valid ? knn_tau32(A.tau[i]) : -1.0f;  // an invalid lane never passes
+    }
+    float wv[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) wv[j] = (float)A.w[j];
+    const cfloat_ptr xc = as_const(A.x32);
+
+    auto hits = [&](int64_t g, const float (&v)[G * D]) {
+        bool any = false;
+        float key[G][R];
+#pragma unroll
+        for (int c = 0; c < G; ++c)
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                key[c][r] = knn_key32<D, NORM, HASW>(xr[r], v + c * D, wv);
+                any = any || key[c][r] <= tr[r];
+            }
+        if (__builtin_amdgcn_ballot_w64(any) == 0) return;
+#pragma unroll
+        for (int c = 0; c < G; ++c)
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int64_t k = g + c;
+                if (key[c][r] <= tr[r] && k < w.c1) {
+                    const int slot = atomicAdd(A.kcnt + ir[r], 1);
+                    if (slot < kKnnCap) A.kcand[(int64_t)ir[r] * kKnnCap + slot] = (int32_t)k;
+                }
+            }
+    };
+    auto load = [&](int64_t g, float (&v)[G * D]) {
+        if (g + G <= A.n) {
+#pragma unroll
+            for (int e = 0; e < G * D; ++e) v[e] = xc[g * D + e];
+        } else {
+#pragma unroll
+            for (int c = 0; c < G; ++c) {
+                const int64_t k = g + c < A.n ? g + c : A.n - 1;
+#pragma unroll
+                for (int j = 0; j < D; ++j) v[c * D + j] = xc[k * D + j];
+            }
+        }
+    };
+    // two groups per iteration, the next one requested before use
+    float va[G * D], vb[G * D];
+    int64_t g = w.c0;
+    if (g < w.c1) load(g, va);
+#pragma unroll 1
+    for (; g + G < w.c1; g += 2 * G) {
+        load(g + G, vb);
+        hits(g, va);
+        if (g + 2 * G < w.c1) load(g + 2 * G, va);
+        hits(g + G, vb);
+    }
+    if (g < w.c1) hits(g, va);
+}
+
+// K smallest (key, index) pairs in lexicographic order (candidates arrive
+// in any order).
+template <int K>
+__device__ __forceinline__ void knn_insert_lex(double (&key)[K], int (&idx)[K], double kv, int j)
+{
+    if (!(kv < key[K - 1] || (kv == key[K - 1] && j < idx[K - 1]))) return;
+    key[K - 1] = kv;
+    idx[K - 1] = j;
+#pragma unroll
+    for (int t = K - 1; t > 0; --t) {
+        const bool sw = key[t] < key[t - 1] || (key[t] == key[t - 1] && idx[t] < idx[t - 1]);
+        const double a = key[t], b = key[t - 1];
+        const int ia = idx[t], ib = idx[t - 1];
+        key[t] = sw ? b : a;
+        key[t - 1] = sw ? a : b;
+        idx[t] = sw ? ib : ia;
+        idx[t - 1] = sw ? ia : ib;
+    }
+}
+
+// FP64 key of one pair with the operation sequence of ds_dist_group (l2:
+// the sum of squares).
+template <int D, int NORM, bool HASW>
+__device__ __forceinline__ double knn_key64(const DsArgs &A, const double (&xr)[D], int64_t k)
+{
+    double su = 0.0, sl = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        const double dd = xr[j] - A.X[(int64_t)j * A.npad + k];
+        if (j == 0) ds_step<NORM, HASW, false, true>(1.0, A.w[j], dd, su, sl);
+        else ds_step<NORM, HASW, false, false>(1.0, A.w[j], dd, su, sl);
+    }
+    return su;
+}
+
+// Exact ranking: the row's candidates (or, if they overflowed the list,
+// every column) by (FP64 key, index), then M_i over the first knn.
+template <int D, int NORM, bool HASW, int K>
+__global__ void __launch_bounds__(256) knn_select_kernel(DsArgs A)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    double xr[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) xr[j] = A.X[(int64_t)j * A.npad + i];
     double key[K];
     int idx[K];
 #pragma unroll
@@ -619,84 +763,18 @@ __global__ void __launch_bounds__(256) knn_kernel(DsArgs A)
         key[t] = __builtin_inf();
         idx[t] = -1;
     }
-    // Only the first knn (<= K) slots matter; thr is the knn-th smallest key,
-    // and never above the row's bound from the threshold pass (a column with
-    // a key equal to that bound is still taken).
-    const int kk = A.knn;
-    double thr = __builtin_inf();
-    if (A.tau) {
-        const double t0 = A.tau[i];
-        thr = t0 < __builtin_inf() ? next_up(t0) : t0;
-    }
-    const cdouble_ptr X = (cdouble_ptr)(A.X);
-#pragma unroll 1
-    for (int64_t g0 = w.c0; g0 < w.c1; g0 += kDsGroup) {
-        double su[kDsGroup][1], sl[kDsGroup][1];
-        // rank by the distance (l2: by the sum of squares, no root)
-        ds_dist_group<D, NORM, HASW, false, 1>(A, X, g0, xr, su, sl);
-#pragma unroll
-        for (int c = 0; c < kDsGroup; ++c) {
-            const int64_t k = g0 + c;
-            if (k < A.n && k != i && su[c][0] < thr) {
-                knn_insert<K>(key, idx, su[c][0], (int)k);
-                if (kk == K) {
-                    thr = key[K - 1] < thr ? key[K - 1] : thr;
-                } else {
-#pragma unroll
-                    for (int t = 0; t < K; ++t)
-                        if (t == kk - 1) thr = key[t] < thr ? key[t] : thr;
-                }
-            }
+    const int cnt = A.kcnt[i];
+    if (cnt <= kKnnCap) {
+        for (int t = 0; t < cnt; ++t) {
+            const int k = A.kcand[i * kKnnCap + t];
+            if (k == (int)i) continue;
+            knn_insert_lex<K>(key, idx, knn_key64<D, NORM, HASW>(A, xr, k), k);
         }
-    }
-    if (!valid) return;
-    if (A.n_chunks == 1) {
-        knn_finish<D, NORM, HASW, K>(A, i, xr[0], idx);
-        return;
-    }
-    const int64_t o = ((int64_t)w.chunk * A.n + i) * K;
-#pragma unroll
-    for (int t = 0; t < K; ++t) {
-        A.kkey[o + t] = key[t];
-        A.kidx[o + t] = idx[t];
-    }
-}
-
-// Merges the per-chunk sorted lists of each row (chunks in column order; on
-// equal keys the lower index first) and finishes M_i.
-template <int D, int NORM, bool HASW, int K>
-__global__ void __launch_bounds__(256) knn_merge_kernel(DsArgs A)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= A.n) return;
-    double xr[D];
-#pragma unroll
-    for (int j = 0; j < D; ++j) xr[j] = A.X[(int64_t)j * A.npad + i];
-    int head[kKnnMaxChunks];
-#pragma unroll
-    for (int c = 0; c < kKnnMaxChunks; ++c) head[c] = 0;
-    int idx[K];
-#pragma unroll
-    for (int t = 0; t < K; ++t) {
-        double bk = __builtin_inf();
-        int bi = -1, bc = -1;
-#pragma unroll
-        for (int c = 0; c < kKnnMaxChunks; ++c) {
-            if (c >= A.n_chunks || head[c] >= K) continue;
-            const int64_t o = ((int64_t)c * A.n + i) * K + head[c];
-            const double kv = A.kkey[o];
-            const int ki = A.kidx[o];
-            if (ki < 0) continue;
-            if (bi < 0 || kv < bk || (kv == bk && ki < bi)) {
-                bk = kv;
-                bi = ki;
-                bc = c;
-            }
+    } else {
+        for (int64_t k = 0; k < A.n; ++k) {
+            if (k == i) continue;
+            knn_insert_lex<K>(key, idx, knn_key64<D, NORM, HASW>(A, xr, k), (int)k);
         }
-        idx[t] = bi;
-#pragma unroll
-        for (int c = 0; c < kKnnMaxChunks; ++c)
-            if (c == bc) ++head[c];
     }
     knn_finish<D, NORM, HASW, K>(A, i, xr, idx);
 }
@@ -706,7 +784,7 @@ __global__ void __launch_bounds__(256) knn_merge_kernel(DsArgs A)
 typedef void (*DsLaunch)(const DsArgs &, dim3, dim3, hipStream_t);
 
 struct DsLaunchers {
-    DsLaunch consistency, consistency_mon, slope, knn16, knn32, merge16, merge32, tau16, tau32;
+    DsLaunch consistency, consistency_mon, slope, scan, select16, select32, tau16, tau32;
 };
 
 // Dimensions up to which the consistency pass has one kernel per free /
@@ -742,23 +820,20 @@ DsLaunchers ds_launchers_for()
     L.slope = [](const DsArgs &a, dim3 g, dim3 b, hipStream_t s) {
         hipLaunchKernelGGL((slope_kernel<D, NORM, HASW>), g, b, 0, s, a);
     };
-    L.knn16 = [](const DsArgs &a, dim3 g, dim3 b, hipStream_t s) {
-        hipLaunchKernelGGL((knn_kernel<D, NORM, HASW, 16>), g, b, 0, s, a);
+    L.scan = [](const DsArgs &a, dim3 g, dim3 b, hipStream_t s) {
+        hipLaunchKernelGGL((knn_scan_kernel<D, NORM, HASW>), g, b, 0, s, a);
     };
-    L.knn32 = [](const DsArgs &a, dim3 g, dim3 b, hipStream_t s) {
-        hipLaunchKernelGGL((knn_kernel<D, NORM, HASW, 32>), g, b, 0, s, a);
+    L.select16 = [](const DsArgs &a, dim3 g, dim3 b, hipStream_t s) {
+        hipLaunchKernelGGL((knn_select_kernel<D, NORM, HASW, 16>), g, b, 0, s, a);
+    };
+    L.select32 = [](const DsArgs &a, dim3 g, dim3 b, hipStream_t s) {
+        hipLaunchKernelGGL((knn_select_kernel<D, NORM, HASW, 32>), g, b, 0, s, a);
     };
     L.tau16 = [](const DsArgs &a, dim3 g, dim3 b, hipStream_t s) {
         hipLaunchKernelGGL((knn_tau_kernel<D, NORM, HASW, 16>), g, b, 0, s, a);
     };
     L.tau32 = [](const DsArgs &a, dim3 g, dim3 b, hipStream_t s) {
         hipLaunchKernelGGL((knn_tau_kernel<D, NORM, HASW, 32>), g, b, 0, s, a);
-    };
-    L.merge16 = [](const DsArgs &a, dim3 g, dim3 b, hipStream_t s) {
-        hipLaunchKernelGGL((knn_merge_kernel<D, NORM, HASW, 16>), g, b, 0, s, a);
-    };
-    L.merge32 = [](const DsArgs &a, dim3 g, dim3 b, hipStream_t s) {
-        hipLaunchKernelGGL((knn_merge_kernel<D, NORM, HASW, 32>), g, b, 0, s, a);
     };
     return L;
 }
