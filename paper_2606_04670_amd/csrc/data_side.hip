@@ -123,6 +123,89 @@ __global__ void morton_kernel(const double *X, int64_t n, int64_t npad, int d, i
     }
 }
 
+// FP32 records of the consistency filter: [npad][d + 2] = (signed x, y, M_k),
+// all exact copies of the FP32 inputs (padding zero, masked by the kernel).
+__global__ void stage32_kernel(const float *x, const float *y, const float *Mk, float M, int64_t n,
+                               int64_t npad, int d, Signs sg, float *c32)
+{
+    const int S = d + 2;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < npad; k += stride) {
+        const bool in = k < n;
+        for (int j = 0; j < d; ++j) c32[k * S + j] = in ? sg.s[j] * x[k * d + j] : 0.0f;
+        c32[k * S + d] = in ? y[k] : 0.0f;
+        c32[k * S + d + 1] = in ? (Mk ? Mk[k] : M) : 0.0f;
+    }
+}
+
+// E = 2^-18 (max M_k * max pairwise distance + 2 max |y|), the bound on
+// |FP32 slack - FP64 slack| used by the filtered consistency kernel (the
+// distance bound is the norm of the weighted bounding-box extent).  Not
+// finite or above 2^100: +inf, which sends every pair to FP64.
+__global__ void __launch_bounds__(1024) cons_bound_kernel(const float *c32, int64_t n, int d,
+                                                           DsArgs A, double *E)
+{
+    __shared__ double red[3 + 2 * kMaxDim][32];
+    const int S = d + 2;
+    double ymax = 0.0, mmax = 0.0, lo[kMaxDim], hi[kMaxDim];
+    for (int j = 0; j < kMaxDim; ++j) {
+        lo[j] = __builtin_inf();
+        hi[j] = -__builtin_inf();
+    }
+    for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
+        ymax = fmax(ymax, fabs((double)c32[k * S + d]));
+        mmax = fmax(mmax, (double)c32[k * S + d + 1]);
+        for (int j = 0; j < d; ++j) {
+            const double v = c32[k * S + j];
+            lo[j] = fmin(lo[j], v);
+            hi[j] = fmax(hi[j], v);
+        }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    auto wmax = [&](double v) {
+        for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+        return v;
+    };
+    ymax = wmax(ymax);
+    mmax = wmax(mmax);
+    for (int j = 0; j < d; ++j) {
+        lo[j] = -wmax(-lo[j]);
+        hi[j] = wmax(hi[j]);
+    }
+    if (lane == 0) {
+        red[0][wv] = ymax;
+        red[1][wv] = mmax;
+        for (int j = 0; j < d; ++j) {
+            red[3 + j][wv] = lo[j];
+            red[3 + kMaxDim + j][wv] = hi[j];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = (int)(blockDim.x >> 6);
+        double ym = 0.0, mm = 0.0, dist = 0.0;
+        for (int q = 0; q < nw; ++q) {
+            ym = fmax(ym, red[0][q]);
+            mm = fmax(mm, red[1][q]);
+        }
+        for (int j = 0; j < d; ++j) {
+            double l = __builtin_inf(), h = -__builtin_inf();
+            for (int q = 0; q < nw; ++q) {
+                l = fmin(l, red[3 + j][q]);
+                h = fmax(h, red[3 + kMaxDim + j][q]);
+            }
+            const double span = A.w[j] * (h - l);
+            // l1: sum; l2: root of the sum of squares; linf: max
+            if (span > 0.0)
+                dist = A.norm == 1 ? dist + span : (A.norm == 2 ? dist + span * span : fmax(dist, span));
+        }
+        if (A.norm == 2) dist = sqrt(dist);
+        double e = 0x1p-18 * (mm * dist + 2.0 * ym) + 0x1p-126;
+        if (!(e < 0x1p100)) e = __builtin_inf();
+        E[0] = e;
+    }
+}
+
 __global__ void zero_counts_kernel(unsigned long long *c)
 {
     if (threadIdx.x < 2) c[threadIdx.x] = 0ull;
@@ -244,7 +327,8 @@ static int64_t ds_npad(int64_t n) { return (n + kDsTile - 1) / kDsTile * kDsTile
 size_t data_side_ws_bytes(int64_t n, int d)
 {
     const size_t staged = align_up((size_t)ds_npad(n) * (size_t)(d + 2) * 8, 256);
-    const size_t cons = (size_t)kDsMaxChunks * (size_t)n * 24;
+    const size_t cons = align_up((size_t)kDsMaxChunks * (size_t)n * 24, 256) +
+                        align_up((size_t)ds_npad(n) * (size_t)(d + 2) * 4, 256) + 256;
     const size_t knn = align_up((size_t)n * 4, 256) + align_up((size_t)n * kKnnCap * 4, 256) +
                        align_up((size_t)sort_len(n) * 8, 256) + align_up((size_t)n * 8, 256) +
                        2 * kMaxDim * 8;
@@ -331,13 +415,22 @@ extern "C" lip_status lip_consistency(const lip_metric *metric, const float *x, 
     A.npad = ds_npad(n);
     A.X = (const double *)ws;
     A.tol = tol;
-    choose_chunks(n, 64 * kDsRows, kDsMaxChunks, &A);
+    // l2 runs the FP32-filtered kernel (kC32Rows rows per lane), l1 / linf the
+    // FP64 kernel (kDsRows)
+    const int rows = 64 * (mi.norm == LIP_L2 ? kC32Rows : kDsRows);
+    choose_chunks(n, rows, kDsMaxChunks, &A);
     char *p = (char *)ws + align_up((size_t)A.npad * (size_t)(mi.d + 2) * 8, 256);
     const size_t e = (size_t)A.n_chunks * (size_t)n;
     A.pv_up = (double *)p;
     A.pv_lo = A.pv_up + e;
     A.pi_up = (int32_t *)(A.pv_lo + e);
     A.pi_lo = A.pi_up + e;
+    char *q = p + align_up((size_t)kDsMaxChunks * (size_t)n * 24, 256);
+    float *c32 = (float *)q;
+    q += align_up((size_t)A.npad * (size_t)(mi.d + 2) * 4, 256);
+    double *cE = (double *)q;
+    A.c32 = c32;
+    A.cE = cE;
     A.slack_up = slack_up;
     A.slack_lo = slack_lo;
     A.partner_up = partner_up;
@@ -345,9 +438,18 @@ extern "C" lip_status lip_consistency(const lip_metric *metric, const float *x, 
     A.counts = (unsigned long long *)counts;
     if (launch_stage64(mi.d, x, y, Mk, M, n, A.npad, sg, (double *)ws, s) != hipSuccess)
         return LIP_E_DEVICE;
+    if (mi.norm == LIP_L2) {
+        int64_t g32 = (A.npad + 255) / 256;
+        if (g32 > 65536) g32 = 65536;
+        hipLaunchKernelGGL(stage32_kernel, dim3((unsigned)g32), dim3(256), 0, s, x, y, Mk, M, n,
+                           A.npad, mi.d, sg, c32);
+        A.norm = mi.norm;
+        hipLaunchKernelGGL(cons_bound_kernel, dim3(1), dim3(1024), 0, s, (const float *)c32, n,
+                           mi.d, A, cE);
+    }
     hipLaunchKernelGGL(zero_counts_kernel, dim3(1), dim3(64), 0, s, A.counts);
-    (mi.dm > 0 ? L.consistency_mon : L.consistency)(
-        A, dim3(grid_for_rows(n, 64 * kDsRows, A.n_chunks)), dim3(256), s);
+    (mi.dm > 0 ? L.consistency_mon : L.consistency)(A, dim3(grid_for_rows(n, rows, A.n_chunks)),
+                                                    dim3(256), s);
     if (A.n_chunks > 1 && (slack_up || slack_lo || partner_up || partner_lo))
         hipLaunchKernelGGL(consistency_combine_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256),
                            0, s, A);

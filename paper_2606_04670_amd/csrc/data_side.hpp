@@ -59,6 +59,7 @@ struct DsArgs {
     double fsel[kMaxDim];   // 1 free, 0 monotone (decreasing ones negated at staging)
     double tol;
     int32_t fmask;          // bit i: coordinate i free (consistency with monotone coordinates)
+    int32_t norm;           // 1 l1, 2 l2, 3 linf
     int32_t n_chunks;
     int32_t knn;
     int64_t chunk_cols;  // columns per chunk (multiple of kDsTile)
@@ -68,6 +69,8 @@ struct DsArgs {
     double *slack_up, *slack_lo;
     int32_t *partner_up, *partner_lo;
     unsigned long long *counts;  // [2]
+    const float *c32;   // FP32 records [npad][D + 2] (signed x, y, M_k) for the FP32 filter
+    const double *cE;   // [1] error bound E of the FP32 slack
     // global slope: partials [n_chunks][n]
     double *row_best;
     int32_t *row_arg;
@@ -779,6 +782,246 @@ __global__ void __launch_bounds__(256) knn_select_kernel(DsArgs A)
     knn_finish<D, NORM, HASW, K>(A, i, xr, idx);
 }
 
+// ---- consistency with an FP32 filter -----------------------------------------
+//
+// The same outputs as consistency_kernel, bit for bit, with most pairs
+// decided in FP32.  For a pair, t32 (the slack evaluated in FP32 from the
+// same inputs: distance components, weights, sum / sum of squares + square
+// root / max, then fma(M_k, dist, y_k) - y_i) differs from the FP64 slack by
+// at most E = 2^-18 (max M_k * max dist + 2 max |y|) (at most (d + 8) 2^-24
+// relative in the distance, three more roundings in the bound; a factor two
+// spare).  With V- <= -tol - E and V+ >= -tol + E (FP32, rounded outwards):
+//   t32 <  V-             : a violation (t < -tol) for certain;
+//   t32 >= V+             : no violation for certain;
+//   otherwise             : ambiguous, decided in FP64;
+//   t32 <= U + E (FP32)   : may lower the running minimum U, evaluated in
+//                            FP64 (strict improvement in column order keeps
+//                            the lowest index, as the partner requires).
+// Pairs that need FP64 are evaluated with cons_pair (the FP64 kernel's own
+// operation sequence).  A NaN t32 or an infinite E sends the pair to FP64.
+constexpr int kC32Rows = 4;
+
+constexpr int c32_group(int D) { return D <= 4 ? 2 : 1; }
+
+// Neighbouring floats of a finite f (toward -inf / +inf).
+__device__ __forceinline__ float f32_prev(float f)
+{
+    if (f == 0.0f) return -0x1p-149f;
+    const uint32_t b = __float_as_uint(f);
+    return __uint_as_float(f > 0.0f ? b - 1u : b + 1u);
+}
+__device__ __forceinline__ float f32_next(float f)
+{
+    if (f == 0.0f) return 0x1p-149f;
+    const uint32_t b = __float_as_uint(f);
+    return __uint_as_float(f > 0.0f ? b + 1u : b - 1u);
+}
+
+// v rounded to FP32 toward -inf / +inf (infinities and NaN pass through).
+__device__ __forceinline__ float f32_down(double v)
+{
+    float f = (float)v;
+    if ((double)f > v && __builtin_isfinite(f)) f = f32_prev(f);
+    return f;
+}
+
+__device__ __forceinline__ float f32_up(double v)
+{
+    float f = (float)v;
+    if ((double)f < v && __builtin_isfinite(f)) f = f32_next(f);
+    return f;
+}
+
+// FP32 distance components of one pair: free coordinates |d| to both sums,
+// monotone ones (d)_+ to the upper and (-d)_+ to the lower sum; FM >= 0 gives
+// the kinds at compile time, FM < 0 reads A.fsel.
+template <int D, int NORM, bool HASW, bool MON, int FM>
+__device__ __forceinline__ void c32_dist(const DsArgs &A, const float (&xr)[D], const float *xc,
+                                         float &du, float &dl)
+{
+    float su = 0.0f, sl = 0.0f;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        const float d = xr[j] - xc[j];
+        float cu, cl;
+        bool fr;
+        if constexpr (!MON) fr = true;
+        else if constexpr (FM >= 0) fr = (FM >> j) & 1;
+        else fr = false;
+        if (fr) {
+            cu = cl = fabsf(d);
+        } else if constexpr (MON && FM >= 0) {
+            cu = fmaxf(d, 0.0f);
+            cl = fmaxf(-d, 0.0f);
+        } else {
+            const float f = (float)A.fsel[j];
+            const float p = fmaxf(d, 0.0f), q = fmaxf(-d, 0.0f);
+            cu = fmaf(f, q, p);
+            cl = fmaf(f, p, q);
+        }
+        if (HASW) {
+            const float wj = (float)A.w[j];
+            cu *= wj;
+            cl *= wj;
+        }
+        if (NORM == 1) {
+            su = j == 0 ? cu : su + cu;
+            if (MON) sl = j == 0 ? cl : sl + cl;
+        } else if (NORM == 2) {
+            su = j == 0 ? cu * cu : fmaf(cu, cu, su);
+            if (MON) sl = j == 0 ? cl * cl : fmaf(cl, cl, sl);
+        } else {
+            su = j == 0 ? cu : fmaxf(su, cu);
+            if (MON) sl = j == 0 ? cl : fmaxf(sl, cl);
+        }
+    }
+    if (NORM == 2) {
+        su = __builtin_amdgcn_sqrtf(su);
+        if (MON) sl = __builtin_amdgcn_sqrtf(sl);
+    }
+    du = su;
+    dl = MON ? sl : su;
+}
+
+template <int D, int NORM, bool HASW, bool MON, int FM = -1>
+__global__ void __launch_bounds__(256) consistency32_kernel(DsArgs A)
+{
+    constexpr int R = kC32Rows;
+    constexpr int S = D + 2;
+    constexpr int G = c32_group(D);
+    WaveRange w;
+    if (!wave_range(A, 64 * R, w)) return;
+    const int lane = threadIdx.x & 63;
+    const double E = A.cE[0];
+    const float vlo = f32_down(-A.tol - E), vhi = f32_up(-A.tol + E);
+    float xr[R][D], yr[R], umin[R], lmin[R];
+    double xd[R][D], yd[R], bu[R], bl[R];
+    int ir[R], pu[R], pl[R];
+    bool valid[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        int64_t i = w.r0 + r * 64 + lane;
+        valid[r] = i < A.n;
+        i = valid[r] ? i : A.n - 1;
+        ir[r] = (int)i;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            xr[r][j] = A.c32[i * S + j];
+            xd[r][j] = (double)xr[r][j];
+        }
+        yr[r] = A.c32[i * S + D];
+        yd[r] = (double)yr[r];
+        bu[r] = bl[r] = __builtin_inf();
+        umin[r] = lmin[r] = __builtin_inff();
+        pu[r] = pl[r] = -1;
+    }
+    unsigned long long cu = 0, cl = 0;  // certain violations (wave-uniform)
+    unsigned int xu = 0, xl = 0;        // violations decided in FP64 (per lane)
+    const cfloat_ptr C = as_const(A.c32);
+
+    auto visit = [&](int64_t g, const float (&v)[G * S], auto mask_tag) {
+        constexpr bool MASK = decltype(mask_tag)::value;
+        bool any = false;
+        bool eu[G][R], el[G][R], au[G][R], al[G][R];
+#pragma unroll
+        for (int c = 0; c < G; ++c) {
+            const float yk = v[c * S + D], mk = v[c * S + D + 1];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                float du, dl;
+                c32_dist<D, NORM, HASW, MON, FM>(A, xr[r], v + c * S, du, dl);
+                const float tu = fmaf(mk, du, yk) - yr[r];
+                const float tl = yr[r] - fmaf(-mk, dl, yk);
+                bool ok = valid[r];
+                if (MASK) ok = ok && (g + c) < A.n && (int)(g + c) != ir[r];
+                const bool su = tu < vlo, sl = tl < vlo;  // violations for certain
+                au[c][r] = ok && !su && !(tu >= vhi);   // ambiguous
+                al[c][r] = ok && !sl && !(tl >= vhi);
+                bool okm = true;
+                if (MASK) okm = (g + c) < A.n && (int)(g + c) != ir[r];
+                eu[c][r] = au[c][r] || (okm && !(tu > umin[r]));
+                el[c][r] = al[c][r] || (okm && !(tl > lmin[r]));
+                cu += __popcll(__ballot(ok && su));
+                cl += __popcll(__ballot(ok && sl));
+                any = any || eu[c][r] || el[c][r];
+            }
+        }
+        if (__builtin_amdgcn_ballot_w64(any) == 0) return;
+#pragma unroll
+        for (int c = 0; c < G; ++c)
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (!(eu[c][r] || el[c][r])) continue;
+                const int64_t k = g + c;
+                double tu, tl;
+                cons_pair<D, NORM, HASW, MON>(A, xd[r], yd[r], k, tu, tl);
+                if (au[c][r] && tu < -A.tol) ++xu;
+                if (al[c][r] && tl < -A.tol) ++xl;
+                if (eu[c][r] && tu < bu[r]) {
+                    bu[r] = tu;
+                    pu[r] = (int)k;
+                    umin[r] = f32_up(tu + E);
+                }
+                if (el[c][r] && tl < bl[r]) {
+                    bl[r] = tl;
+                    pl[r] = (int)k;
+                    lmin[r] = f32_up(tl + E);
+                }
+            }
+    };
+    auto load = [&](int64_t g, float (&v)[G * S]) {
+#pragma unroll
+        for (int e = 0; e < G * S; ++e) v[e] = C[g * S + e];
+    };
+    // Groups that overlap the end of the data or this wave's own rows check
+    // bounds and the diagonal per pair.
+    auto masked = [&](int64_t g) { return g + G > A.n || (g < w.r1 && g + G > w.r0); };
+    float va[G * S], vb[G * S];
+    int64_t g = w.c0;
+    if (g < w.c1) load(g, va);
+#pragma unroll 1
+    for (; g + G < w.c1; g += 2 * G) {
+        load(g + G, vb);
+        if (masked(g)) visit(g, va, std::true_type{});
+        else visit(g, va, std::false_type{});
+        if (g + 2 * G < w.c1) load(g + 2 * G, va);
+        if (masked(g + G)) visit(g + G, vb, std::true_type{});
+        else visit(g + G, vb, std::false_type{});
+    }
+    if (g < w.c1) {
+        if (masked(g)) visit(g, va, std::true_type{});
+        else visit(g, va, std::false_type{});
+    }
+
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (!valid[r]) continue;
+        const int64_t i = ir[r];
+        if (A.n_chunks == 1) {
+            if (A.slack_up) A.slack_up[i] = bu[r];
+            if (A.slack_lo) A.slack_lo[i] = bl[r];
+            if (A.partner_up) A.partner_up[i] = pu[r];
+            if (A.partner_lo) A.partner_lo[i] = pl[r];
+        } else {
+            const int64_t o = (int64_t)w.chunk * A.n + i;
+            A.pv_up[o] = bu[r];
+            A.pv_lo[o] = bl[r];
+            A.pi_up[o] = pu[r];
+            A.pi_lo[o] = pl[r];
+        }
+    }
+    unsigned long long tu = xu, tl = xl;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        tu += __shfl_xor(tu, off);
+        tl += __shfl_xor(tl, off);
+    }
+    if (lane == 0) {
+        atomicAdd(A.counts, cu + tu);
+        atomicAdd(A.counts + 1, cl + tl);
+    }
+}
+
 // ---- launcher tables ------------------------------------------------------------
 
 typedef void (*DsLaunch)(const DsArgs &, dim3, dim3, hipStream_t);
@@ -793,10 +1036,17 @@ constexpr int kDsMaskDims = 4;
 
 typedef void (*DsKernel)(DsArgs);
 
+// Per-pattern kernels of the consistency pass: the FP32-filtered kernel for
+// l2 (where FP32 saves the two FP64 square roots of every pair), the FP64
+// kernel for l1 and linf (where the filter's bookkeeping costs about what it
+// saves).
 template <int D, int NORM, bool HASW, int... FMs>
 constexpr std::array<DsKernel, sizeof...(FMs)> cons_mask_table(std::integer_sequence<int, FMs...>)
 {
-    return {{&consistency_kernel<D, NORM, HASW, true, FMs>...}};
+    if constexpr (NORM == 2)
+        return {{&consistency32_kernel<D, NORM, HASW, true, FMs>...}};
+    else
+        return {{&consistency_kernel<D, NORM, HASW, true, FMs>...}};
 }
 
 template <int D, int NORM, bool HASW>
@@ -804,7 +1054,10 @@ DsLaunchers ds_launchers_for()
 {
     DsLaunchers L;
     L.consistency = [](const DsArgs &a, dim3 g, dim3 b, hipStream_t s) {
-        hipLaunchKernelGGL((consistency_kernel<D, NORM, HASW, false>), g, b, 0, s, a);
+        if constexpr (NORM == 2)
+            hipLaunchKernelGGL((consistency32_kernel<D, NORM, HASW, false>), g, b, 0, s, a);
+        else
+            hipLaunchKernelGGL((consistency_kernel<D, NORM, HASW, false>), g, b, 0, s, a);
     };
     L.consistency_mon = [](const DsArgs &a, dim3 g, dim3 b, hipStream_t s) {
         if constexpr (D <= kDsMaskDims) {
@@ -815,7 +1068,10 @@ DsLaunchers ds_launchers_for()
                 return;
             }
         }
-        hipLaunchKernelGGL((consistency_kernel<D, NORM, HASW, true>), g, b, 0, s, a);
+        if constexpr (NORM == 2)
+            hipLaunchKernelGGL((consistency32_kernel<D, NORM, HASW, true>), g, b, 0, s, a);
+        else
+            hipLaunchKernelGGL((consistency_kernel<D, NORM, HASW, true>), g, b, 0, s, a);
     };
     L.slope = [](const DsArgs &a, dim3 g, dim3 b, hipStream_t s) {
         hipLaunchKernelGGL((slope_kernel<D, NORM, HASW>), g, b, 0, s, a);
