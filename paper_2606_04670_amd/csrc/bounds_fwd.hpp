@@ -211,7 +211,7 @@ __device__ __forceinline__ void fwd_wave(const FwdArgs &a, int chunk, int64_t qb
 }
 
 template <int D, int DM, int NORM>
-__global__ void __launch_bounds__(256) bounds_fwd_kernel(FwdArgs a)
+__device__ __forceinline__ void fwd_block(const FwdArgs &a)
 {
     // wave index is wave-uniform; readfirstlane lets the compiler keep every
     // loop counter and address derived from it in SGPRs
@@ -221,6 +221,25 @@ __global__ void __launch_bounds__(256) bounds_fwd_kernel(FwdArgs a)
     const int64_t qblock = (int64_t)(blockIdx.x / a.n_chunks) * nw + wave;
     fwd_wave<D, DM, NORM>(a, chunk, qblock);
 }
+
+template <int D, int DM, int NORM>
+__global__ void __launch_bounds__(256) bounds_fwd_kernel(FwdArgs a)
+{
+    fwd_block<D, DM, NORM>(a);
+}
+
+// The same kernel held to 128 VGPRs (4 waves per SIMD) for the norms and
+// dimensions where that costs no spills (l2 and linf, d = 3..8; the l1 form
+// with its extra per-query sum spills): more waves to hide the latency of
+// the square roots and of the scalar loads.
+template <int D, int DM, int NORM>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+bounds_fwd_kernel_o4(FwdArgs a)
+{
+    fwd_block<D, DM, NORM>(a);
+}
+
+constexpr bool fwd_use_o4(int D, int NORM) { return NORM != kNormL1 && D >= 3 && D <= 8; }
 
 // Persistent kernel for many independent data sets of one shape class
 // (d, monotone count, norm): every wave repeatedly takes the next work item
@@ -245,7 +264,10 @@ __global__ void __launch_bounds__(256) batched_fwd_kernel(BatchArgs b)
 template <int NORM, int D, int DM>
 void launch_fwd(const FwdArgs &a, dim3 grid, dim3 block, hipStream_t s)
 {
-    hipLaunchKernelGGL((bounds_fwd_kernel<D, DM, NORM>), grid, block, 0, s, a);
+    if constexpr (fwd_use_o4(D, NORM))
+        hipLaunchKernelGGL((bounds_fwd_kernel_o4<D, DM, NORM>), grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL((bounds_fwd_kernel<D, DM, NORM>), grid, block, 0, s, a);
 }
 
 template <int NORM, int D, int DM>

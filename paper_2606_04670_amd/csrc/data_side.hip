@@ -138,10 +138,12 @@ __global__ void stage32_kernel(const float *x, const float *y, const float *Mk, 
     }
 }
 
-// E = 2^-18 (max M_k * max pairwise distance + 2 max |y|), the bound on
-// |FP32 slack - FP64 slack| used by the filtered consistency kernel (the
-// distance bound is the norm of the weighted bounding-box extent).  Not
-// finite or above 2^100: +inf, which sends every pair to FP64.
+// E = 2^-18 (max M_k * max pairwise distance + 2 max |y|) + max M_k 2^-60
+// + 2^-126, the bound on |FP32 slack - FP64 slack| used by the filtered
+// consistency kernel (the distance bound is the norm of the weighted
+// bounding-box extent).  Data whose FP32 evaluation could overflow (extent
+// >= 2^60 or bounds >= 2^100), or non-finite values, give +inf, which sends
+// every pair to FP64.
 __global__ void __launch_bounds__(1024) cons_bound_kernel(const float *c32, int64_t n, int d,
                                                            DsArgs A, double *E)
 {
@@ -200,8 +202,12 @@ __global__ void __launch_bounds__(1024) cons_bound_kernel(const float *c32, int6
                 dist = A.norm == 1 ? dist + span : (A.norm == 2 ? dist + span * span : fmax(dist, span));
         }
         if (A.norm == 2) dist = sqrt(dist);
-        double e = 0x1p-18 * (mm * dist + 2.0 * ym) + 0x1p-126;
-        if (!(e < 0x1p100)) e = __builtin_inf();
+        // relative part; the absolute part covers FP32 underflow of squared
+        // components (a distance error of at most 2^-72) and of the sums
+        double e = 0x1p-18 * (mm * dist + 2.0 * ym) + mm * 0x1p-60 + 0x1p-126;
+        // FP32 squares and bounds must stay finite: components below 2^60,
+        // bounds below 2^100; otherwise every pair goes to FP64
+        if (!(dist < 0x1p60) || !(mm * dist + ym < 0x1p100) || !(e < 0x1p100)) e = __builtin_inf();
         E[0] = e;
     }
 }

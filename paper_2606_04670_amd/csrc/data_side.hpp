@@ -788,9 +788,10 @@ __global__ void __launch_bounds__(256) knn_select_kernel(DsArgs A)
 // decided in FP32.  For a pair, t32 (the slack evaluated in FP32 from the
 // same inputs: distance components, weights, sum / sum of squares + square
 // root / max, then fma(M_k, dist, y_k) - y_i) differs from the FP64 slack by
-// at most E = 2^-18 (max M_k * max dist + 2 max |y|) (at most (d + 8) 2^-24
-// relative in the distance, three more roundings in the bound; a factor two
-// spare).  With V- <= -tol - E and V+ >= -tol + E (FP32, rounded outwards):
+// at most E = 2^-18 (max M_k * max dist + 2 max |y|) + max M_k 2^-60 + 2^-126
+// (at most (d + 8) 2^-24 relative in the distance, three more roundings in
+// the bound, a factor two spare; the absolute terms cover FP32 underflow).
+// Data whose FP32 evaluation could overflow get E = +inf.  With V- <= -tol - E and V+ >= -tol + E (FP32, rounded outwards):
 //   t32 <  V-             : a violation (t < -tol) for certain;
 //   t32 >= V+             : no violation for certain;
 //   otherwise             : ambiguous, decided in FP64;

@@ -223,3 +223,45 @@ def test_consistency_every_pattern_low_dim(lf, d):
         for key in ("slack_up", "slack_lo", "partner_up", "partner_lo"):
             np.testing.assert_array_equal(g[key], o[key], err_msg=f"d={d} mon={mon.tolist()} {key}")
         assert g["counts"].tolist() == [o["viol_up"].sum(), o["viol_lo"].sum()], mon.tolist()
+
+
+def test_consistency_l2_filter_off_for_huge_values(lf):
+    """Coordinates ~1e30 make the FP32 slack bound infinite (FP32 squares
+    overflow): every pair goes to FP64, results still exact."""
+    p = W.random_problem(990, n=700, q=1, d=3, norm=2, mon=np.array([1, 0, 0], np.int8))
+    x = p.x.copy()
+    x[::3] *= np.float32(1e30)
+    p2 = W.Problem("huge", x, p.y, 1.5, None, p.xq, 2, p.mon, p.w)
+    g = _consistency(lf, p2, 1.5, None)
+    o = oracle.consistency(x, p.y, 2, M=1.5, mon=p.mon)
+    for key in ("slack_up", "slack_lo", "partner_up", "partner_lo"):
+        np.testing.assert_array_equal(g[key], o[key])
+    assert g["counts"].tolist() == [o["viol_up"].sum(), o["viol_lo"].sum()]
+
+
+@pytest.mark.parametrize("tol", [0.0, 1e-3, 0.25])
+def test_consistency_l2_tolerance_band(lf, tol):
+    """Slacks spread around -tol (data with a scaled-down M): the FP32
+    filter's ambiguous band around the tolerance is decided in FP64."""
+    p = W.random_problem(995, n=3000, q=1, d=4, norm=2, mon=np.array([1, 0, -1, 0], np.int8),
+                         local=True)
+    mk = (p.Mk * np.float32(0.2)).astype(np.float32)
+    g = _consistency(lf, p, 0.0, mk, tol=tol)
+    o = oracle.consistency(p.x, p.y, 2, Mk=mk, mon=p.mon, tol=tol)
+    for key in ("slack_up", "slack_lo", "partner_up", "partner_lo"):
+        np.testing.assert_array_equal(g[key], o[key])
+    assert g["counts"].tolist() == [o["viol_up"].sum(), o["viol_lo"].sum()]
+
+
+def test_consistency_l2_tiny_values(lf):
+    """Coordinates ~1e-25: FP32 squares of the differences underflow; the
+    absolute part of the filter's bound keeps every decision exact."""
+    p = W.random_problem(996, n=900, q=1, d=3, norm=2, mon=np.array([0, 1, 0], np.int8))
+    x = (p.x * np.float32(1e-25)).astype(np.float32)
+    y = (p.y * np.float32(1e-24)).astype(np.float32)
+    p2 = W.Problem("tiny", x, y, 1.5, None, p.xq, 2, p.mon, p.w)
+    g = _consistency(lf, p2, 1.5, None)
+    o = oracle.consistency(x, y, 2, M=1.5, mon=p.mon)
+    for key in ("slack_up", "slack_lo", "partner_up", "partner_lo"):
+        np.testing.assert_array_equal(g[key], o[key])
+    assert g["counts"].tolist() == [o["viol_up"].sum(), o["viol_lo"].sum()]
