@@ -29,7 +29,7 @@
 // four are allowed) and S32_k >= (1 - 2^-24)^(d+2) S_k (every step rounds a
 // non-negative sum), so S_k <= r_k^2 (1 + 2.1e-6) with
 // r_k = (T' - y_k) / M_k.  Symmetrically for the lower bound with
-// T'_lo = T_lo - 2^-21|T_lo| - 2^-126.  Per tile of 32 data the kernel uses
+// T'_lo = T_lo - 2^-21|T_lo| - 2^-126.  Per tile of 64 data the kernel uses
 //     r = max(T'_up - ymin, ymax - T'_lo) * (1 + 2^-16) / Mmin,
 // which dominates every r_k of the tile with a 1.5e-5 relative margin (more
 // than the 2.1e-6 plus the rounding of the four operations), and a pair is a
@@ -40,17 +40,18 @@
 // candidate.
 //
 // Order of the data.  The data are sorted by y (sort of packed (y, index)
-// keys) and cut into tiles of 32, so a tile's y range is narrow
+// keys) and cut into tiles of 64, so a tile's y range is narrow
 // and the tile-level radius is close to the per-datum one.  Each data chunk
 // takes every C-th tile of the sorted order and visits them from both ends
 // alternately (lowest y, highest y, second lowest, ...), so that both
 // thresholds tighten within the first tiles.
 //
 // Work decomposition.  A wave owns 4 blocks of 32 queries (B operands, in
-// VGPRs for the whole scan) and one data chunk; per tile it issues 4 (d <= 10)
-// or 8 v_mfma_f32_32x32x16_bf16.  Lane l holds column l % 32 (one query) and
-// 16 rows (data) of each 32 x 32 result, so the tile test is a min over 16
-// accumulators, one fma and one compare per lane and block.  Candidates go
+// VGPRs for the whole scan) and one data chunk; per tile of 64 data it issues
+// 8 (d <= 10) or 16 v_mfma_f32_32x32x16_bf16.  Lane l holds column l % 32 (one
+// query) and 32 rows (data) of each block's two 32 x 32 results, so the tile
+// test is a min over 32 accumulators, the radius (4 instructions), one fma
+// and one compare per lane and block.  Candidates go
 // to a per-wave queue in LDS; when it holds 64 entries the whole wave
 // re-scores 64 pairs at once (one per lane) with the FP32 pair formula and
 // merges them into per-query packed (value, index) keys in LDS with 64-bit
@@ -65,7 +66,8 @@
 namespace lip {
 namespace {
 
-constexpr int kBTile = 32;   // data per tile (MFMA rows)
+constexpr int kBTile = 64;   // data per tile (two 32-row MFMA blocks, one y range)
+constexpr int kRB = kBTile / 32;
 constexpr int kBQB = 4;      // 32-query blocks per wave
 constexpr int kBWaves = 4;   // waves per workgroup
 constexpr int kBCap = 256;   // re-scoring queue entries per wave
@@ -164,8 +166,9 @@ __global__ void __launch_bounds__(256) bf16_stage_kernel(Bf16Stage a)
     constexpr int S = Rec<D>::S;
     constexpr int KS = ksteps(D);
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (p >= a.n_pad) return;  // whole tiles (n_pad is a multiple of 32)
-    const int row = (int)(p % kBTile);
+    if (p >= a.n_pad) return;  // whole tiles (n_pad is a multiple of 64)
+    const int within = (int)(p % kBTile);
+    const int rb = within / 32, row = within % 32;
     const int64_t j = p / kBTile;
     int64_t s = scan_to_sorted(p, a.C, a.per, a.rem);
     if (s >= a.n) s = a.n - 1;  // padding repeats the largest-y datum
@@ -209,19 +212,19 @@ __global__ void __launch_bounds__(256) bf16_stage_kernel(Bf16Stage a)
             uint32_t e8[8];
 #pragma unroll
             for (int e = 0; e < 8; ++e) e8[e] = row_e[16 * ks + 8 * g + e];
-            a.A[(j * KS + ks) * 64 + 32 * g + row] = pack8(e8);
+            a.A[((j * kRB + rb) * KS + ks) * 64 + 32 * g + row] = pack8(e8);
         }
     }
 
-    // tile statistics over the 32 lanes of this tile
+    // tile statistics over the 64 lanes (one wave) of this tile
     float ymin = y, ymax = flag ? __builtin_inff() : y, mmin = m;
 #pragma unroll
-    for (int off = 16; off > 0; off >>= 1) {
-        ymin = fminf(ymin, __shfl_xor(ymin, off, 32));
-        ymax = fmaxf(ymax, __shfl_xor(ymax, off, 32));
-        mmin = fminf(mmin, __shfl_xor(mmin, off, 32));
+    for (int off = 32; off > 0; off >>= 1) {
+        ymin = fminf(ymin, __shfl_xor(ymin, off));
+        ymax = fmaxf(ymax, __shfl_xor(ymax, off));
+        mmin = fminf(mmin, __shfl_xor(mmin, off));
     }
-    if (row == 0) {
+    if (within == 0) {
         const float inv = mmin > 0.0f ? (1.0f / mmin) * (1.0f + 0x1p-16f) : __builtin_nanf("");
         a.stats[j] = make_float4(ymin, ymax, inv, 0.0f);
     }
@@ -257,6 +260,7 @@ __global__ void __launch_bounds__(256) bf16_bounds_kernel(Bf16Args a)
     __shared__ uint2 queue[kBWaves][kBCap];
     __shared__ unsigned long long kup[kBWaves][32 * QB];
     __shared__ unsigned long long klo[kBWaves][32 * QB];
+    __shared__ uint32_t evm[kBWaves][QB][64];  // candidate rows of the last tile, per block and lane
 
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -363,93 +367,162 @@ __global__ void __launch_bounds__(256) bf16_bounds_kernel(Bf16Args a)
         }
     };
 
-    // Queue every (row, block) bit of pm for tile j.
-    auto append = [&](uint64_t pm, int64_t j) {
+    // Queue every candidate bit of pm (block b, tile j): bit 16 rb + i is
+    // accumulator i of row block rb.
+    auto append = [&](uint32_t pm, int b, int64_t j) {
         for (;;) {
             const bool has = pm != 0;
             const uint64_t mask = __builtin_amdgcn_ballot_w64(has);
             if (mask == 0) break;
             if (qcount > kBCap - 64) drain();
-            const int bit = has ? __builtin_ctzll(pm) : 0;
+            const int bit = has ? __builtin_ctz(pm) : 0;
             pm &= pm - 1;
             const int pos = qcount + __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
             if (has) {
-                const int b = bit >> 4, i = bit & 15;
+                const int rb = bit >> 4, i = bit & 15;
                 // row of accumulator i in lane l of a 32x32 MFMA result
-                const int rrow = 8 * (i >> 2) + 4 * grp + (i & 3);
+                const int rrow = 32 * rb + 8 * (i >> 2) + 4 * grp + (i & 3);
                 queue[w][pos] = make_uint2((uint32_t)(j * kBTile + rrow), (uint32_t)(32 * b + col));
             }
             qcount += __builtin_popcountll(mask);
         }
-        if (qcount >= 64) drain();
     };
 
     const cfloat_ptr stc = as_const((const float *)a.stats);
-    // Tile test for all blocks: returns the candidate bits (block b, row i at
-    // bit 16 b + i) of this lane.  The MFMAs of block b + 1 are issued before
+    // Tile test for all blocks.  The MFMAs of block b + 1 are issued before
     // the test of block b reads its accumulators.
-    auto mma = [&](const uint4 (&av)[KS], int b) -> f32x16 {
-        f32x16 acc = {};
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av[0]),
-                                                      __builtin_bit_cast(bf16x8, bop[b][0]), acc,
-                                                      0, 0, 0);
-        if constexpr (KS == 2)
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av[1]),
-                                                          __builtin_bit_cast(bf16x8, bop[b][1]),
-                                                          acc, 0, 0, 0);
+    struct Acc2 {
+        f32x16 v[kRB];
+    };
+    auto mma = [&](const uint4 (&av)[kRB][KS], int b) -> Acc2 {
+        Acc2 acc;
+#pragma unroll
+        for (int rb = 0; rb < kRB; ++rb) {
+            acc.v[rb] = f32x16{};
+            acc.v[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av[rb][0]),
+                                                                __builtin_bit_cast(bf16x8, bop[b][0]),
+                                                                acc.v[rb], 0, 0, 0);
+        }
+        if constexpr (KS == 2) {
+#pragma unroll
+            for (int rb = 0; rb < kRB; ++rb)
+                acc.v[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                    __builtin_bit_cast(bf16x8, av[rb][1]), __builtin_bit_cast(bf16x8, bop[b][1]),
+                    acc.v[rb], 0, 0, 0);
+        }
         return acc;
     };
-    auto tile_test = [&](const uint4 (&av)[KS], float symin, float symax, float sinv) -> uint64_t {
-        uint64_t pm = 0;
-        f32x16 acc[2];
+    // Returns a wave-uniform mask of the blocks with candidates; their per-lane
+    // row bits are left in evm (LDS), so the common path carries no masks.
+    auto tile_test = [&](const uint4 (&av)[kRB][KS], float symin, float symax,
+                         float sinv) -> uint32_t {
+        uint32_t ev = 0;
+        Acc2 acc[2];
         acc[0] = mma(av, 0);
 #pragma unroll
         for (int b = 0; b < QB; ++b) {
             if (b + 1 < QB) acc[(b + 1) & 1] = mma(av, b + 1);
-            const f32x16 &c = acc[b & 1];
+            const Acc2 &c = acc[b & 1];
             const float r = fmaxf(tu[b] - symin, symax - tl[b]) * sinv;
-            float lm = fmin_nan(fmin_nan(c[0], c[1]), c[2]);
+            float lm = fmin_nan(fmin_nan(c.v[0][0], c.v[0][1]), c.v[0][2]);
 #pragma unroll
-            for (int i = 3; i < 15; i += 2) lm = fmin_nan(fmin_nan(lm, c[i]), c[i + 1]);
-            lm = fmin_nan(lm, c[15]);
+            for (int i = 3; i < 15; i += 2) lm = fmin_nan(fmin_nan(lm, c.v[0][i]), c.v[0][i + 1]);
+            lm = fmin_nan(fmin_nan(lm, c.v[0][15]), c.v[1][0]);
+#pragma unroll
+            for (int i = 1; i < 15; i += 2) lm = fmin_nan(fmin_nan(lm, c.v[1][i]), c.v[1][i + 1]);
+            lm = fmin_nan(lm, c.v[1][15]);
             const bool pass = !(fmaf(r, -fabsf(r), lm) > kTiny);
-            if (__builtin_amdgcn_ballot_w64(pass) != 0) {
+            // interleave the next block's MFMAs with this block's test so that
+            // the matrix and vector pipes work at the same time
+            if (b + 1 < QB) {
 #pragma unroll
-                for (int i = 0; i < 16; ++i)
-                    if (!(fmaf(r, -fabsf(r), c[i]) > kTiny)) pm |= 1ull << (16 * b + i);
+                for (int k = 0; k < kRB * KS; ++k) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x002, 5, 0);
+                }
+            }
+            if (__builtin_amdgcn_ballot_w64(pass) != 0) {
+                // bit 16 rb + i, shifted in from the top bit down (no mask
+                // constants held in registers)
+                uint32_t m = 0;
+#pragma unroll
+                for (int rb = kRB - 1; rb >= 0; --rb)
+#pragma unroll
+                    for (int i = 15; i >= 0; --i)
+                        m = (m << 1) | (uint32_t)!(fmaf(r, -fabsf(r), c.v[rb][i]) > kTiny);
+                evm[w][b][lane] = m;
+                ev |= 1u << b;
             }
         }
-        return pm;
+        return ev;
+    };
+    auto handle = [&](uint32_t ev, int64_t j) {
+        if (ev == 0) return;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+#pragma unroll
+        for (int b = 0; b < QB; ++b)
+            if ((ev >> b) & 1u) append(evm[w][b][lane], b, j);
+        if (qcount >= 64) drain();
     };
 
     // A operands and tile statistics are loaded one tile ahead
-    const uint4 *Ab = a.A + lane;
-    uint4 ba[KS], bb[KS];
+    constexpr int TS = kRB * KS * 64;  // uint4 per tile
+    const uint4 *Ab = a.A + jb * TS + lane;
+    auto load_a = [&](const uint4 *ptr, uint4 (&av)[kRB][KS]) {
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) ba[ks] = Ab[(jb * KS + ks) * 64];
+        for (int rb = 0; rb < kRB; ++rb)
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) av[rb][ks] = ptr[(rb * KS + ks) * 64];
+    };
+    uint4 ba[kRB][KS], bb[kRB][KS];
+
+    // Warm start: in the chunk's first two tiles (lowest and highest y), each
+    // lane re-scores, per block, the datum with the smallest L (y is nearly
+    // constant inside a tile, so that is about the tile's best pair for both
+    // bounds).  The thresholds then start close to their final values; the
+    // two tiles are tested again in full below.
+#pragma unroll 1
+    for (int64_t t0 = 0; t0 < (cnt < 2 ? cnt : 2); ++t0) {
+        load_a(Ab + t0 * TS, ba);
+#pragma unroll
+        for (int b = 0; b < QB; ++b) {
+            const Acc2 c = mma(ba, b);
+            float best = c.v[0][0];
+            int bi = 0;
+#pragma unroll
+            for (int rb = 0; rb < kRB; ++rb)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const bool lt = c.v[rb][i] < best;
+                    best = lt ? c.v[rb][i] : best;
+                    bi = lt ? 16 * rb + i : bi;
+                }
+            const int rb = bi >> 4, i = bi & 15;
+            const int rrow = 32 * rb + 8 * (i >> 2) + 4 * grp + (i & 3);
+            queue[w][qcount + lane] =
+                make_uint2((uint32_t)((jb + t0) * kBTile + rrow), (uint32_t)(32 * b + col));
+            qcount += 64;
+        }
+        drain();
+    }
+
+    load_a(Ab, ba);
     float sa0 = stc[4 * jb], sa1 = stc[4 * jb + 1], sa2 = stc[4 * jb + 2];
     int64_t t = 0;
     for (; t + 1 < cnt; t += 2) {
         const int64_t j = jb + t;
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) bb[ks] = Ab[((j + 1) * KS + ks) * 64];
+        load_a(Ab + (t + 1) * TS, bb);
         const float sb0 = stc[4 * (j + 1)], sb1 = stc[4 * (j + 1) + 1], sb2 = stc[4 * (j + 1) + 2];
-        uint64_t pm = tile_test(ba, sa0, sa1, sa2);
-        if (__builtin_amdgcn_ballot_w64(pm != 0) != 0) append(pm, j);
-        const int64_t jn = t + 2 < cnt ? j + 2 : j + 1;
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) ba[ks] = Ab[(jn * KS + ks) * 64];
-        sa0 = stc[4 * jn];
-        sa1 = stc[4 * jn + 1];
-        sa2 = stc[4 * jn + 2];
-        pm = tile_test(bb, sb0, sb1, sb2);
-        if (__builtin_amdgcn_ballot_w64(pm != 0) != 0) append(pm, j + 1);
+        handle(tile_test(ba, sa0, sa1, sa2), j);
+        const int64_t tn = t + 2 < cnt ? t + 2 : t + 1;
+        load_a(Ab + tn * TS, ba);
+        sa0 = stc[4 * (jb + tn)];
+        sa1 = stc[4 * (jb + tn) + 1];
+        sa2 = stc[4 * (jb + tn) + 2];
+        handle(tile_test(bb, sb0, sb1, sb2), j + 1);
     }
-    if (t < cnt) {
-        const uint64_t pm = tile_test(ba, sa0, sa1, sa2);
-        if (__builtin_amdgcn_ballot_w64(pm != 0) != 0) append(pm, jb + t);
-    }
+    if (t < cnt) handle(tile_test(ba, sa0, sa1, sa2), jb + t);
     if (qcount > 0) drain();
 
     if (grp == 0) {
@@ -546,7 +619,7 @@ Bf16Layout bf16_layout(int64_t n, int64_t q, int d)
     L.sort = take((size_t)L.P * 8);
     L.rec = take((size_t)L.n_pad * (d + 3) * 4);
     L.idx = take((size_t)L.n_pad * 4);
-    L.A = take((size_t)L.nt * ksteps(d) * 64 * 16);
+    L.A = take((size_t)L.nt * kRB * ksteps(d) * 64 * 16);
     L.stats = take((size_t)L.nt * 16);
     L.keys = take((size_t)(q > 0 ? q : 1) * 2 * 8);
     L.total = off;
@@ -585,7 +658,7 @@ lip_status run_bounds_bf16(const MetricInfo &mi, const float *x, const float *y,
     // data chunks: enough waves to fill the chip, at least 8 tiles a chunk
     const int64_t qwaves = (q + 32 * kBQB - 1) / (32 * kBQB);
     int C = 1;
-    while (C < kMaxChunks && qwaves * C < 4096 && L.nt >= 16ll * C) C *= 2;
+    while (C < kMaxChunks && qwaves * C < 4096 && L.nt >= 8ll * C) C *= 2;
     const int64_t per = L.nt / C, rem = L.nt % C;
 
     Bf16Stage sa{};
