@@ -12,6 +12,8 @@ OpenMP over queries/rows), written from the paper's definitions:
   * global constant:        Sec. 5 (``lipschitz_constant``), max pairwise slope
   * per-point constants:    Sec. 4.3, scalar form over the 16 nearest data
   * subgradients:           chain rule through the selected data points
+  * step-function M_k(t):   Sec. 4.3, quantile knots from sampled distances,
+                            per-datum tables, bounds with M_k(dist)
 This module only marshals numpy arrays into that library.
 """
 from __future__ import annotations
@@ -66,6 +68,15 @@ def _load():
         lib.orc_grad.argtypes = [i32, i32, P, P, P, P, i64, f64, P, P, i64, P, P, P, P, P,
                                  P, P, P]
         lib.orc_grad.restype = None
+        lib.orc_knots.argtypes = [i32, i32, P, P, P, i64, P, i32, P]
+        lib.orc_knots.restype = None
+        lib.orc_local_steps.argtypes = [i32, i32, P, P, P, i64, P, i32, P, i64, P, P]
+        lib.orc_local_steps.restype = i32
+        lib.orc_bounds_step.argtypes = [i32, i32, P, P, P, P, i64, P, i32, P, P, P, i64,
+                                        P, P, P, P, P]
+        lib.orc_bounds_step.restype = None
+        lib.orc_candidates_step.argtypes = [i32, i32, P, P, P, P, i64, P, i32, P, P, P, P, P]
+        lib.orc_candidates_step.restype = None
         _lib = lib
     return _lib
 
@@ -174,3 +185,72 @@ def grad(x, y, xq, norm: int, arg_up, arg_lo, dg=None, dh_up=None, dh_lo=None,
     _load().orc_grad(d, norm, _p(w), _p(mon), _p(x), _p(y), n, float(M), _p(Mk), _p(xq), q,
                      _p(au), _p(al), _p(dg), _p(dh_up), _p(dh_lo), _p(dxq), _p(dy), _p(dM))
     return dxq, dy, dM
+
+
+def knots(x, pairs, probs, norm: int, w=None):
+    """Quantile knots (float64[K]) of the sampled inter-point distances."""
+    d = int(np.shape(x)[1])
+    x = _f32(x)
+    w = np.ones(d, np.float64) if w is None else np.ascontiguousarray(w, np.float64)
+    pr = np.ascontiguousarray(pairs, np.int64).reshape(-1, 2)
+    pb = np.ascontiguousarray(probs, np.float64)
+    out = np.empty(pb.shape[0], np.float64)
+    _load().orc_knots(d, norm, _p(w), _p(x), _p(pr), pr.shape[0], _p(pb), pb.shape[0], _p(out))
+    return out
+
+
+def local_steps(x, y, knots_, norm: int, w=None, rows: Optional[Sequence[int]] = None):
+    """(status, d1[rows] float64, V[rows, K+2] float64): step tables of Sec. 4.3."""
+    d = int(np.shape(x)[1])
+    x, y, w, _ = _common(x, y, w, None, d)
+    kn = np.ascontiguousarray(knots_, np.float64)
+    K = kn.shape[0]
+    rows_a = None if rows is None else np.ascontiguousarray(rows, np.int64)
+    nr = x.shape[0] if rows_a is None else rows_a.shape[0]
+    d1 = np.empty(nr, np.float64)
+    V = np.empty((nr, K + 2), np.float64)
+    st = _load().orc_local_steps(d, norm, _p(w), _p(x), _p(y), x.shape[0], _p(kn), K,
+                                 _p(rows_a), nr, _p(d1), _p(V))
+    return int(st), d1, V
+
+
+def bounds_step(x, y, xq, norm: int, knots_, d1, V32, mon=None, w=None):
+    """H_up, H_lo, g (float64), arg_up, arg_lo (int64) with M_k(dist) from the tables."""
+    d = int(np.shape(x)[1])
+    x, y, w, mon = _common(x, y, w, mon, d)
+    xq = _f32(xq).reshape(-1, d)
+    kn = np.ascontiguousarray(knots_, np.float64)
+    d1 = np.ascontiguousarray(d1, np.float64)
+    V32 = _f32(V32)
+    assert V32.shape == (x.shape[0], kn.shape[0] + 2)
+    q = xq.shape[0]
+    hu, hl, g = (np.empty(q, np.float64) for _ in range(3))
+    au, al = np.empty(q, np.int64), np.empty(q, np.int64)
+    _load().orc_bounds_step(d, norm, _p(w), _p(mon), _p(x), _p(y), x.shape[0], _p(kn),
+                            kn.shape[0], _p(d1), _p(V32), _p(xq), q, _p(hu), _p(hl), _p(g),
+                            _p(au), _p(al))
+    return hu, hl, g, au, al
+
+
+def candidates_step(x, y, xq1, norm: int, knots_, d1, V32, mon=None, w=None):
+    """(u[n], l[n]) float64 for one query with M_k(dist) from the tables."""
+    d = int(np.shape(x)[1])
+    x, y, w, mon = _common(x, y, w, mon, d)
+    q1 = _f32(xq1).reshape(d)
+    kn = np.ascontiguousarray(knots_, np.float64)
+    d1 = np.ascontiguousarray(d1, np.float64)
+    V32 = _f32(V32)
+    n = x.shape[0]
+    u, l = np.empty(n, np.float64), np.empty(n, np.float64)
+    _load().orc_candidates_step(d, norm, _p(w), _p(mon), _p(x), _p(y), n, _p(kn), kn.shape[0],
+                                _p(d1), _p(V32), _p(q1), _p(u), _p(l))
+    return u, l
+
+
+def round_up_f32(v) -> np.ndarray:
+    """float64 -> float32 rounded toward +inf (the constants the bounds multiply)."""
+    v = np.asarray(v, np.float64)
+    f = v.astype(np.float32)
+    low = f.astype(np.float64) < v
+    f[low] = np.nextafter(f[low], np.float32(np.inf))
+    return f

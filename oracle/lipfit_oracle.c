@@ -403,3 +403,161 @@ void orc_grad(int d, int norm, const double *w, const signed char *mon,
     free(gu);
     free(gl);
 }
+
+/* ---- step-function local constants (Sec. 4.3) -------------------------------
+ *
+ * Reading used here (the section describes the construction in words only):
+ *  - Knots q_1 <= ... <= q_K are shared by all data: quantiles of the
+ *    distribution of inter-point distances, estimated from a sample of pairs
+ *    (orc_knots).  The sample itself is an input.
+ *  - For datum k, d1_k is the distance to its nearest other datum (positive
+ *    distances only; coincident data with the same value are skipped).
+ *  - M_k(t) is non-decreasing and piecewise constant:
+ *        t <= d1_k                   -> V_k,0   = max slope over the data at distance <= d1_k
+ *        otherwise, the first s with t <= q_s -> V_k,s = max slope over the data at
+ *                                                 distance <= max(q_s, d1_k)
+ *        t > q_K                     -> V_k,K+1 = max slope over all data
+ *    where the slope of a pair is |y_k - y_j| / dist(x^k, x^j) with the
+ *    symmetric distance (monotonicity ignored).  An empty set gives 0.
+ *  - A coincident datum with a different value makes the slope infinite: the
+ *    whole row is +inf and the function returns 3.
+ *  - Bounds use the datum's function at the pair's own distance:
+ *        u_k = y_k + M_k(dist_up) dist_up,   l_k = y_k - M_k(dist_lo) dist_lo.
+ */
+
+static int cmp_double(const void *pa, const void *pb)
+{
+    double a = *(const double *)pa, b = *(const double *)pb;
+    return (a > b) - (a < b);
+}
+
+/* Knots as quantiles of sampled inter-point distances: the m pairs
+ * (pairs[2s], pairs[2s+1]) give distances with the symmetric distance, sorted
+ * ascending as r_0 <= ... <= r_{m-1}; knot j is the inverse of the empirical
+ * distribution function at probs[j]: r_c with c = ceil(probs[j] * m) - 1,
+ * clamped to [0, m - 1]. */
+void orc_knots(int d, int norm, const double *w, const float *x, const long *pairs, long m,
+               const double *probs, int K, double *knots)
+{
+    double *r = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
+    for (long s = 0; s < m; ++s) {
+        double du, dl;
+        dist_pair(d, norm, w, NULL, x + pairs[2 * s] * (long)d, x + pairs[2 * s + 1] * (long)d,
+                  &du, &dl, NULL, NULL);
+        r[s] = du;
+    }
+    qsort(r, (size_t)m, sizeof(double), cmp_double);
+    for (int j = 0; j < K; ++j) {
+        long c = (long)ceil(probs[j] * (double)m) - 1;
+        if (c < 0) c = 0;
+        if (c > m - 1) c = m - 1;
+        knots[j] = r[c];
+    }
+    free(r);
+}
+
+/* The step table of every requested row i (all rows when rows == NULL):
+ * d1[r] and V[r * (K + 2) + s], s = 0..K+1, as defined above, written from
+ * the definition: first the pair list of the row, then one pass per entry. */
+int orc_local_steps(int d, int norm, const double *w, const float *x, const float *y, long n,
+                    const double *knots, int K, const long *rows, long n_rows, double *d1,
+                    double *V)
+{
+    if (!rows) n_rows = n;
+    int status = 0;
+#pragma omp parallel
+    {
+        double *t = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+        double *sl = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+#pragma omp for schedule(dynamic, 4) reduction(max : status)
+        for (long r = 0; r < n_rows; ++r) {
+            long i = rows ? rows[r] : r;
+            double *v = V + r * (long)(K + 2);
+            int infinite = 0;
+            /* pair list: distance and slope of every j != i with a positive distance */
+            long m = 0;
+            for (long j = 0; j < n; ++j) {
+                if (j == i) continue;
+                double du, dl;
+                dist_pair(d, norm, w, NULL, x + i * (long)d, x + j * (long)d, &du, &dl, NULL, NULL);
+                double dy = fabs((double)y[i] - (double)y[j]);
+                if (du == 0.0) {
+                    if (dy != 0.0) infinite = 1;
+                    continue;
+                }
+                t[m] = du;
+                sl[m] = dy / du;
+                ++m;
+            }
+            double nn = INFINITY;
+            for (long a = 0; a < m; ++a)
+                if (t[a] < nn) nn = t[a];
+            d1[r] = nn;
+            for (int s = 0; s < K + 2; ++s) {
+                /* radius of entry s: d1 (s = 0), max(q_s, d1) (1 <= s <= K), all (K + 1) */
+                double rad = s == 0 ? nn : (s <= K ? (knots[s - 1] > nn ? knots[s - 1] : nn) : INFINITY);
+                double best = 0.0;
+                for (long a = 0; a < m; ++a)
+                    if (t[a] <= rad && sl[a] > best) best = sl[a];
+                v[s] = infinite ? INFINITY : best;
+            }
+            if (infinite) status = 3;
+        }
+        free(t);
+        free(sl);
+    }
+    return status;
+}
+
+/* M_k(t) from the row's table (d1 and V[0..K+1], as float values widened). */
+static double step_value(double t, double d1, const float *v, const double *knots, int K)
+{
+    if (t <= d1) return (double)v[0];
+    for (int s = 1; s <= K; ++s)
+        if (t <= knots[s - 1]) return (double)v[s];
+    return (double)v[K + 1];
+}
+
+/* Eq. (2) and Eq. (3) with the step-function constants: the table is given as
+ * d1 [n] (FP64) and V [n][K+2] (FP32, the values the bounds multiply).  Lowest
+ * index among exact ties.  Any output pointer may be NULL. */
+void orc_bounds_step(int d, int norm, const double *w, const signed char *mon, const float *x,
+                     const float *y, long n, const double *knots, int K, const double *d1,
+                     const float *V, const float *xq, long q, double *h_up, double *h_lo,
+                     double *g, long *arg_up, long *arg_lo)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long j = 0; j < q; ++j) {
+        const float *xj = xq + j * (long)d;
+        double best_u = INFINITY, best_l = -INFINITY;
+        long au = -1, al = -1;
+        for (long k = 0; k < n; ++k) {
+            double du, dl;
+            dist_pair(d, norm, w, mon, xj, x + k * (long)d, &du, &dl, NULL, NULL);
+            const float *vk = V + k * (long)(K + 2);
+            double u = (double)y[k] + step_value(du, d1[k], vk, knots, K) * du;
+            double l = (double)y[k] - step_value(dl, d1[k], vk, knots, K) * dl;
+            if (u < best_u) { best_u = u; au = k; }
+            if (l > best_l) { best_l = l; al = k; }
+        }
+        if (h_up) h_up[j] = best_u;
+        if (h_lo) h_lo[j] = best_l;
+        if (g) g[j] = 0.5 * (best_u + best_l);
+        if (arg_up) arg_up[j] = au;
+        if (arg_lo) arg_lo[j] = al;
+    }
+}
+
+/* Every candidate of one query under the step-function constants. */
+void orc_candidates_step(int d, int norm, const double *w, const signed char *mon,
+                         const float *x, const float *y, long n, const double *knots, int K,
+                         const double *d1, const float *V, const float *xq1, double *u, double *l)
+{
+    for (long k = 0; k < n; ++k) {
+        double du, dl;
+        dist_pair(d, norm, w, mon, xq1, x + k * (long)d, &du, &dl, NULL, NULL);
+        const float *vk = V + k * (long)(K + 2);
+        u[k] = (double)y[k] + step_value(du, d1[k], vk, knots, K) * du;
+        l[k] = (double)y[k] - step_value(dl, d1[k], vk, knots, K) * dl;
+    }
+}
