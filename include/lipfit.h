@@ -174,6 +174,74 @@ lip_status lip_estimate_M(const lip_metric *metric, const float *x, const float 
                           int32_t mode, int32_t knn, double *M64, float *M32, int64_t *pair,
                           void *ws, size_t ws_bytes, uint32_t flags, lip_stream stream);
 
+/* ---- step-function local constants (Sec. 4.3) ----------------------------
+ * Each datum k gets a non-decreasing, piecewise constant M_k(t) of the
+ * distance t, built from the data:
+ *   knots     q_1 <= ... <= q_K (K <= LIP_MAX_KNOTS), shared by all data:
+ *             quantiles of the inter-point distance distribution, estimated
+ *             from a sample of pairs (lip_local_knots);
+ *   d1_k      the distance from x^k to its nearest other datum;
+ *   M_k(t)  = V_k,0   for t <= d1_k  (largest slope among the data at
+ *                                      distance <= d1_k),
+ *           = V_k,s   for the first s with t <= q_s (largest slope among the
+ *                                      data at distance <= max(q_s, d1_k)),
+ *           = V_k,K+1 for t > q_K     (largest slope over all data),
+ * where a slope is |y_k - y_j| / dist(x^k, x^j) with the symmetric distance
+ * (monotonicity ignored) and an empty set gives 0.  The bounds of Eq. (2)
+ * then use u_k = y_k + M_k(dist_up) dist_up, l_k = y_k - M_k(dist_lo) dist_lo.
+ * With the symmetric distance the result interpolates the data. */
+#define LIP_MAX_KNOTS 8
+
+/* Knots as quantiles of sampled inter-point distances, in FP64 from the
+ * FP32 inputs (symmetric distance, coordinates accumulated in index order).
+ *   pairs [m][2]   HOST int64 indices into x (the random sample is the
+ *                  caller's; i == j is allowed and gives distance 0)
+ *   probs [K]      HOST probabilities in (0, 1], non-decreasing
+ *   knots [K]      DEVICE FP64 output: with the sampled distances sorted
+ *                  ascending as r_0..r_{m-1}, knots[j] = r_c,
+ *                  c = ceil(probs[j] * m) - 1 clamped to [0, m - 1]
+ *                  (the inverse empirical distribution function).
+ * 1 <= m <= 2^26.  Needs ws of lip_workspace_size(m, 0, d, 0) bytes; copies
+ * pairs into it (a host-to-device copy on `stream`). */
+lip_status lip_local_knots(const lip_metric *metric, const float *x, int64_t n,
+                           const int64_t *pairs, int64_t m, const double *probs, int32_t K,
+                           double *knots, void *ws, size_t ws_bytes, uint32_t flags,
+                           lip_stream stream);
+
+/* Per-datum step tables of M_k(t) in FP64 (all pairs, no distance matrix).
+ *   knots [K]          HOST, non-decreasing, >= 0 (K = 0 allowed)
+ *   d1 [n]             DEVICE FP64 output (required): nearest positive
+ *                      distance, +inf when there is none
+ *   V64 [n][K+2]       DEVICE FP64 output, optional: V_k,0 .. V_k,K+1
+ *   V32 [n][K+2]       DEVICE FP32 output, optional: V64 rounded up (the
+ *                      values lip_fit_eval_steps multiplies, so the data
+ *                      stay interpolated)
+ * Coincident data with equal values are skipped; with different values the
+ * slope is infinite and the datum's whole row is +inf (such a table is not a
+ * valid input of lip_fit_eval_steps).  Needs ws. */
+lip_status lip_local_steps(const lip_metric *metric, const float *x, const float *y, int64_t n,
+                           const double *knots, int32_t K, double *d1, double *V64, float *V32,
+                           void *ws, size_t ws_bytes, uint32_t flags, lip_stream stream);
+
+/* The step tables as inputs of the bound evaluation. */
+typedef struct {
+    int32_t K;            /* number of knots, 0..LIP_MAX_KNOTS */
+    const double *knots;  /* HOST [K], non-decreasing, >= 0 */
+    const double *d1;     /* DEVICE [n], from lip_local_steps */
+    const float *V;       /* DEVICE [n][K+2], finite, >= 0 */
+} lip_steps;
+
+/* Eq. (2)-(3) with M_k(dist) of the step tables in place of M.  Outputs and
+ * rules as in lip_fit_eval (all optional, lowest index on ties).  Distances
+ * are formed in FP64 (index order, as in the consistency check), so the
+ * segment of every pair is decided exactly as by the definition; the bound
+ * candidates are FP32: y_k + M fl32(dist) (l2: the FP32 root of the FP32
+ * sum of squares).  LIP_FLAG_BF16 is not supported here. */
+lip_status lip_fit_eval_steps(const lip_metric *metric, const float *x, const float *y, int64_t n,
+                              const lip_steps *steps, const float *xq, int64_t q, float *g,
+                              float *h_up, float *h_lo, int32_t *arg_up, int32_t *arg_lo,
+                              void *ws, size_t ws_bytes, uint32_t flags, lip_stream stream);
+
 /* ---- many independent fits in one launch ------------------------------------
  * One entry per data set: its own metric, data, constants, queries and
  * outputs (all device pointers except metric.w / metric.mon).  Outputs as in

@@ -21,7 +21,7 @@ LIP_FLAG_CHECK_FINITE = 1 << 0
 LIP_FLAG_BF16 = 1 << 1
 LIP_FLAG_DETERMINISTIC = 1 << 2
 LIP_M_GLOBAL, LIP_M_LOCAL_KNN = 0, 1
-LIP_MAX_DIM, LIP_MAX_KNN = 16, 32
+LIP_MAX_DIM, LIP_MAX_KNN, LIP_MAX_KNOTS = 16, 32, 8
 
 P = ctypes.c_void_p
 i32, i64, u32, f32, f64, sz = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_float,
@@ -34,6 +34,10 @@ class LipMetric(ctypes.Structure):
 
 class LipTileCfg(ctypes.Structure):
     _fields_ = [("tile", i32), ("split", i32), ("waves", i32), ("reserved", i32)]
+
+
+class LipSteps(ctypes.Structure):
+    _fields_ = [("K", i32), ("knots", P), ("d1", P), ("V", P)]
 
 
 class LipBatchDesc(ctypes.Structure):
@@ -50,6 +54,9 @@ _SIGS = {
                                P]),
     "lip_consistency": (i32, [P, P, P, i64, f32, P, f64, P, P, P, P, P, P, sz, u32, P]),
     "lip_estimate_M": (i32, [P, P, P, i64, i32, i32, P, P, P, P, sz, u32, P]),
+    "lip_local_knots": (i32, [P, P, i64, P, i64, P, i32, P, P, sz, u32, P]),
+    "lip_local_steps": (i32, [P, P, P, i64, P, i32, P, P, P, P, sz, u32, P]),
+    "lip_fit_eval_steps": (i32, [P, P, P, i64, P, P, i64, P, P, P, P, P, P, sz, u32, P]),
     "lip_plan_create": (i32, [P, P, i32, u32, P]),
     "lip_plan_execute": (i32, [P, P]),
     "lip_plan_destroy": (i32, [P]),

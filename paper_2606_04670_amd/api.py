@@ -7,6 +7,10 @@ runs in the library's kernels.  Functions mirror the C entry points:
     backward            -> lip_fit_backward
     consistency         -> lip_consistency                (Sec. 1, 4.1, Eqs. 5-6)
     estimate_M          -> lip_estimate_M                 (Sec. 5, Sec. 4.3)
+    local_knots         -> lip_local_knots                (Sec. 4.3, step-function M_k(t))
+    local_steps         -> lip_local_steps
+    fit_eval_steps      -> lip_fit_eval_steps
+    StepModel           -> the three above in sequence
     Plan                -> lip_plan_create / execute / destroy
     LipFitFn            -> torch.autograd.Function over fit_eval + backward
 """
@@ -189,6 +193,116 @@ def estimate_M(x, y, metric: Metric, mode: str = "global", knn: int = 16):
                             _ptr(pair), _ptr(ws), ws.numel(), 0, _stream(dev))
     L.check("lip_estimate_M", st)
     return M64, M32, pair
+
+
+# ---- step-function local constants (Sec. 4.3) ------------------------------------
+
+
+def _host_f64(a) -> np.ndarray:
+    if isinstance(a, torch.Tensor):
+        a = a.detach().cpu().numpy()
+    return np.ascontiguousarray(np.asarray(a, np.float64).reshape(-1))
+
+
+def local_knots(x: torch.Tensor, metric: Metric, pairs, probs) -> torch.Tensor:
+    """Quantile knots (float64 [K], on x's device) of the distances of the
+    sampled pairs (host int array [m, 2]) at the probabilities probs."""
+    x = _f32(x, "x")
+    dev = x.device
+    pr = np.ascontiguousarray(np.asarray(pairs, np.int64).reshape(-1, 2))
+    pb = _host_f64(probs)
+    K = pb.shape[0]
+    out = torch.empty(K, dtype=torch.float64, device=dev)
+    lib = L.load()
+    ws = workspace(dev, lib.lip_workspace_size(max(pr.shape[0], x.shape[0]), 0, metric.d, 0))
+    st = lib.lip_local_knots(metric.ref(), _ptr(x), x.shape[0],
+                             pr.ctypes.data_as(ctypes.c_void_p), pr.shape[0],
+                             pb.ctypes.data_as(ctypes.c_void_p), K, _ptr(out) if K else None,
+                             _ptr(ws), ws.numel(), 0, _stream(dev))
+    L.check("lip_local_knots", st)
+    return out
+
+
+def local_steps(x: torch.Tensor, y: torch.Tensor, metric: Metric, knots):
+    """Step tables: (d1 float64 [n], V64 float64 [n, K+2], V32 float32 [n, K+2]).
+    knots: host array-like or tensor (copied to the host)."""
+    x = _f32(x, "x")
+    dev = x.device
+    y = _f32(y, "y", dev)
+    n = x.shape[0]
+    kn = _host_f64(knots)
+    K = kn.shape[0]
+    d1 = torch.empty(n, dtype=torch.float64, device=dev)
+    V64 = torch.empty((n, K + 2), dtype=torch.float64, device=dev)
+    V32 = torch.empty((n, K + 2), dtype=torch.float32, device=dev)
+    lib = L.load()
+    ws = workspace(dev, lib.lip_workspace_size(n, 0, metric.d, 0))
+    st = lib.lip_local_steps(metric.ref(), _ptr(x), _ptr(y), n,
+                             kn.ctypes.data_as(ctypes.c_void_p) if K else None, K, _ptr(d1),
+                             _ptr(V64), _ptr(V32), _ptr(ws), ws.numel(), 0, _stream(dev))
+    L.check("lip_local_steps", st)
+    return d1, V64, V32
+
+
+def fit_eval_steps(x, y, xq, metric: Metric, knots, d1: torch.Tensor, V: torch.Tensor,
+                   want=("g", "h_up", "h_lo", "arg_up", "arg_lo"),
+                   check_finite: bool = False) -> Dict[str, torch.Tensor]:
+    """Eq. (2)-(3) with the step-function constants M_k(dist)."""
+    x = _f32(x, "x")
+    dev = x.device
+    y = _f32(y, "y", dev)
+    xq = _f32(xq, "xq", dev)
+    V = _f32(V, "V", dev)
+    if d1.dtype != torch.float64 or d1.device != dev:
+        raise ValueError("d1 must be a float64 tensor on the data's device")
+    d1 = d1.contiguous()
+    kn = _host_f64(knots)
+    K = kn.shape[0]
+    n, q = x.shape[0], xq.shape[0]
+    if tuple(V.shape) != (n, K + 2) or tuple(d1.shape) != (n,):
+        raise ValueError("table shapes must be d1 [n] and V [n, K+2]")
+    out = {}
+    for k in want:
+        if k in ("g", "h_up", "h_lo"):
+            out[k] = torch.empty(q, dtype=torch.float32, device=dev)
+        elif k in ("arg_up", "arg_lo"):
+            out[k] = torch.empty(q, dtype=torch.int32, device=dev)
+        else:
+            raise ValueError(k)
+    steps = L.LipSteps(K, kn.ctypes.data_as(ctypes.c_void_p) if K else None, d1.data_ptr(),
+                       V.data_ptr())
+    flags = L.LIP_FLAG_CHECK_FINITE if check_finite else 0
+    lib = L.load()
+    ws = workspace(dev, lib.lip_workspace_size(n, q, metric.d, flags))
+    st = lib.lip_fit_eval_steps(metric.ref(), _ptr(x), _ptr(y), n, ctypes.byref(steps), _ptr(xq),
+                                q, _ptr(out.get("g")), _ptr(out.get("h_up")),
+                                _ptr(out.get("h_lo")), _ptr(out.get("arg_up")),
+                                _ptr(out.get("arg_lo")), _ptr(ws), ws.numel(), flags,
+                                _stream(dev))
+    L.check("lip_fit_eval_steps", st)
+    return out
+
+
+class StepModel:
+    """compute_local_lipschitz / values_local of Sec. 5 with the step-function
+    constants of Sec. 4.3: knots from m sampled pairs (drawn here with a seeded
+    numpy generator: the random sample is an input of the method), the tables,
+    then evaluation at any queries."""
+
+    def __init__(self, x, y, metric: Metric, K: int = 4, m: int = 65536, seed: int = 0,
+                 probs=None):
+        self.x, self.y, self.metric = _f32(x, "x"), _f32(y, "y"), metric
+        n = self.x.shape[0]
+        rng = np.random.default_rng(seed)
+        self.pairs = rng.integers(0, n, size=(m, 2))
+        self.probs = (np.arange(1, K + 1, dtype=np.float64) / (K + 1) if probs is None
+                      else _host_f64(probs))
+        self.knots = local_knots(self.x, metric, self.pairs, self.probs).cpu().numpy()
+        self.d1, self.V64, self.V32 = local_steps(self.x, self.y, metric, self.knots)
+
+    def __call__(self, xq, want=("g", "h_up", "h_lo", "arg_up", "arg_lo")):
+        return fit_eval_steps(self.x, self.y, xq, self.metric, self.knots, self.d1, self.V32,
+                              want=want)
 
 
 class LipFitFn(torch.autograd.Function):

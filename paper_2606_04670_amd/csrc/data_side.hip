@@ -9,10 +9,6 @@ namespace lip {
 // masked out by every kernel.  Coordinates with sign -1 (monotone
 // decreasing) are negated, which is exact and turns them into increasing
 // ones: the pair components (x_i - x_k)_+ and (x_k - x_i)_+ swap roles.
-struct Signs {
-    float s[kMaxDim];
-};
-
 template <int D>
 __global__ void stage64_kernel(const float *x, const float *y, const float *Mk, float M, int64_t n,
                                int64_t npad, Signs sg, double *X)
@@ -28,8 +24,8 @@ __global__ void stage64_kernel(const float *x, const float *y, const float *Mk, 
     }
 }
 
-static hipError_t launch_stage64(int d, const float *x, const float *y, const float *Mk, float M,
-                                 int64_t n, int64_t npad, const Signs &sg, double *X, hipStream_t s)
+hipError_t launch_stage64(int d, const float *x, const float *y, const float *Mk, float M,
+                          int64_t n, int64_t npad, const Signs &sg, double *X, hipStream_t s)
 {
     int64_t g = (npad + 255) / 256;
     if (g > 65536) g = 65536;
@@ -328,7 +324,7 @@ __global__ void slope_reduce_kernel(DsArgs A, int64_t *pair)
     }
 }
 
-static int64_t ds_npad(int64_t n) { return (n + kDsTile - 1) / kDsTile * kDsTile; }
+int64_t ds_npad(int64_t n) { return (n + kDsTile - 1) / kDsTile * kDsTile; }
 
 size_t data_side_ws_bytes(int64_t n, int d)
 {
@@ -352,7 +348,7 @@ static bool get_ds(const MetricInfo &mi, bool hasw, DsLaunchers *L)
     }
 }
 
-static bool fill_ds_metric(const MetricInfo &mi, bool use_mon, DsArgs *A, Signs *sg)
+bool fill_ds_metric(const MetricInfo &mi, bool use_mon, DsArgs *A, Signs *sg)
 {
     bool hasw = false;
     for (int i = 0; i < kMaxDim; ++i) {
@@ -368,7 +364,7 @@ static bool fill_ds_metric(const MetricInfo &mi, bool use_mon, DsArgs *A, Signs 
 
 // Column split: enough waves to fill the chip, chunks a multiple of the
 // partner tile, at most max_chunks of them.
-static void choose_chunks(int64_t n, int rows_per_wave, int max_chunks, DsArgs *A)
+void choose_chunks(int64_t n, int rows_per_wave, int max_chunks, DsArgs *A)
 {
     const int64_t row_waves = (n + rows_per_wave - 1) / rows_per_wave;
     int64_t nc = (kDsTargetWaves + row_waves - 1) / row_waves;
@@ -380,7 +376,7 @@ static void choose_chunks(int64_t n, int rows_per_wave, int max_chunks, DsArgs *
     A->n_chunks = (int)((n + cols - 1) / cols);
 }
 
-static unsigned grid_for_rows(int64_t n, int rows_per_wave, int n_chunks)
+unsigned grid_for_rows(int64_t n, int rows_per_wave, int n_chunks)
 {
     const int64_t waves = (n + rows_per_wave - 1) / rows_per_wave;
     return (unsigned)(((waves + 3) / 4) * n_chunks);

@@ -1112,6 +1112,18 @@ bool ds_table(int d, bool hasw, DsLaunchers *L)
     }
 }
 
+// Host helpers of data_side.hip shared with the step-function passes.
+// Per-coordinate signs of the FP64 staging (-1 for a decreasing coordinate).
+struct Signs {
+    float s[kMaxDim];
+};
+hipError_t launch_stage64(int d, const float *x, const float *y, const float *Mk, float M,
+                          int64_t n, int64_t npad, const Signs &sg, double *X, hipStream_t s);
+int64_t ds_npad(int64_t n);
+bool fill_ds_metric(const MetricInfo &mi, bool use_mon, DsArgs *A, Signs *sg);
+void choose_chunks(int64_t n, int rows_per_wave, int max_chunks, DsArgs *A);
+unsigned grid_for_rows(int64_t n, int rows_per_wave, int n_chunks);
+
 bool ds_table_l1(int d, bool hasw, DsLaunchers *L);
 bool ds_table_l2(int d, bool hasw, DsLaunchers *L);
 bool ds_table_linf(int d, bool hasw, DsLaunchers *L);

@@ -48,19 +48,34 @@ def check_bounds(p, gpu: dict, qidx=None, Mk=None, label=""):
     Returns a report dict (max errors, index mismatch counts)."""
     Mk = p.Mk if Mk is None else Mk
     qidx = np.arange(p.q) if qidx is None else np.asarray(qidx)
+    orc = oracle.bounds(p.x, p.y, p.xq[qidx], p.norm, M=p.M, Mk=Mk, mon=p.mon, w=p.w)
+    cand = lambda xq1: oracle.candidates(p.x, p.y, xq1, p.norm, M=p.M, Mk=Mk, mon=p.mon, w=p.w)
+    return _compare(p, gpu, qidx, orc, cand, tau_for(p, Mk), label)
+
+
+def check_bounds_steps(p, gpu: dict, knots, d1, V32, qidx=None, label=""):
+    """As check_bounds, for the step-function constants (tau from the largest
+    table entry)."""
+    qidx = np.arange(p.q) if qidx is None else np.asarray(qidx)
+    orc = oracle.bounds_step(p.x, p.y, p.xq[qidx], p.norm, knots, d1, V32, mon=p.mon, w=p.w)
+    cand = lambda xq1: oracle.candidates_step(p.x, p.y, xq1, p.norm, knots, d1, V32, mon=p.mon,
+                                              w=p.w)
+    return _compare(p, gpu, qidx, orc, cand, tau_for(p, np.asarray(V32).reshape(-1)), label)
+
+
+def _compare(p, gpu, qidx, orc, cand, tau, label):
+    hu, hl, g, au, al = orc
     xq = p.xq[qidx]
-    hu, hl, g, au, al = oracle.bounds(p.x, p.y, xq, p.norm, M=p.M, Mk=Mk, mon=p.mon, w=p.w)
     yscale = float(np.abs(p.y).max())
     rep = {"label": label, "queries": len(qidx)}
-    for name, orc in (("h_up", hu), ("h_lo", hl), ("g", g)):
+    for name, ov in (("h_up", hu), ("h_lo", hl), ("g", g)):
         if name not in gpu:
             continue
-        ok, err = value_ok(gpu[name][qidx], orc, yscale)
+        ok, err = value_ok(gpu[name][qidx], ov, yscale)
         rep[f"max_abs_err_{name}"] = float(err.max()) if err.size else 0.0
         bad = np.nonzero(~ok)[0]
         assert bad.size == 0, (f"{label}: {name} off at {bad.size} queries, e.g. q={qidx[bad[0]]} "
-                               f"gpu={gpu[name][qidx[bad[0]]]!r} oracle={orc[bad[0]]!r}")
-    tau = tau_for(p, Mk)
+                               f"gpu={gpu[name][qidx[bad[0]]]!r} oracle={ov[bad[0]]!r}")
     for name, orc_idx, orc_val, up in (("arg_up", au, hu, True), ("arg_lo", al, hl, False)):
         if name not in gpu:
             continue
@@ -68,7 +83,7 @@ def check_bounds(p, gpu: dict, qidx=None, Mk=None, label=""):
         assert np.all((gi >= 0) & (gi < p.n)), f"{label}: {name} out of range"
         mism = np.nonzero(gi != orc_idx)[0]
         for m in mism:
-            u, l = oracle.candidates(p.x, p.y, xq[m], p.norm, M=p.M, Mk=Mk, mon=p.mon, w=p.w)
+            u, l = cand(xq[m])
             if up:
                 assert u[gi[m]] <= orc_val[m] + tau, (
                     f"{label}: {name} q={qidx[m]} gpu picks {gi[m]} (u={u[gi[m]]!r}), oracle "

@@ -159,3 +159,55 @@ def test_python_binding_refuses_cpu_tensors():
     x = torch.zeros(4, 2)
     with pytest.raises(ValueError):
         lf.fit_eval(x, torch.zeros(4), torch.zeros(3, 2), lf.Metric(2, "l2"), M=1.0)
+
+
+def test_step_entry_points_validation(L):
+    lib = L.load()
+    m, keep = _metric(L)
+    P = ctypes.c_void_p
+    pairs = np.array([[0, 1], [2, 3]], np.int64)
+    bad_pairs = np.array([[0, 1], [2, 10]], np.int64)
+    probs = np.array([0.25, 0.75])
+    bad_probs = np.array([0.75, 0.25])
+    zero_prob = np.array([0.0, 0.5])
+    pp = lambda a: a.ctypes.data_as(P)
+
+    def knots(n=10, prs=pairs, pb=probs, K=2, ws=FAKE, ws_bytes=1 << 30, out=FAKE):
+        return lib.lip_local_knots(ctypes.byref(m), FAKE, n, pp(prs), prs.shape[0], pp(pb), K,
+                                   out, ws, ws_bytes, 0, None)
+    assert knots(n=0) == L.LIP_E_SHAPE
+    assert knots(K=9) == L.LIP_E_SHAPE
+    assert knots(prs=bad_pairs) == L.LIP_E_VALUE
+    assert knots(pb=bad_probs) == L.LIP_E_VALUE
+    assert knots(pb=zero_prob) == L.LIP_E_VALUE
+    assert knots(out=None) == L.LIP_E_ARG
+    assert knots(ws=None) == L.LIP_E_WORKSPACE
+    assert knots(ws_bytes=64) == L.LIP_E_WORKSPACE
+    assert knots(K=0) == L.LIP_OK  # nothing to compute, no device work
+
+    kn = np.array([0.5, 1.0])
+    kn_bad = np.array([1.0, 0.5])
+    kn_neg = np.array([-1.0, 0.5])
+
+    def steps(n=10, k=kn, K=2, d1=FAKE, ws=FAKE, ws_bytes=1 << 30):
+        return lib.lip_local_steps(ctypes.byref(m), FAKE, FAKE, n, pp(k), K, d1, None, None, ws,
+                                   ws_bytes, 0, None)
+    assert steps(n=0) == L.LIP_E_SHAPE
+    assert steps(K=9) == L.LIP_E_SHAPE
+    assert steps(k=kn_bad) == L.LIP_E_VALUE
+    assert steps(k=kn_neg) == L.LIP_E_VALUE
+    assert steps(d1=None) == L.LIP_E_ARG
+    assert steps(ws_bytes=16) == L.LIP_E_WORKSPACE
+
+    def ev(n=10, q=5, k=kn, K=2, V=FAKE, flags=0):
+        st = L.LipSteps(K, pp(k), FAKE, V)
+        return lib.lip_fit_eval_steps(ctypes.byref(m), FAKE, FAKE, n, ctypes.byref(st), FAKE, q,
+                                      FAKE, None, None, None, None, FAKE, 1 << 30, flags, None)
+    assert ev(n=0) == L.LIP_E_SHAPE
+    assert ev(K=-1) == L.LIP_E_SHAPE
+    assert ev(k=kn_bad) == L.LIP_E_VALUE
+    assert ev(V=None) == L.LIP_E_ARG
+    assert ev(flags=L.LIP_FLAG_BF16) == L.LIP_E_UNSUPPORTED
+    assert ev(q=0) == L.LIP_OK
+    assert lib.lip_fit_eval_steps(ctypes.byref(m), FAKE, FAKE, 10, None, FAKE, 5, FAKE, None,
+                                  None, None, None, FAKE, 1 << 30, 0, None) == L.LIP_E_ARG
