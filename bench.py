@@ -106,7 +106,7 @@ def parse():
                     help="queries per norm in the oracle's CPU-baseline sample")
     ap.add_argument("--norms", default="l1,l2,linf")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the BF16-vs-FP32 and batched-vs-per-set comparisons")
+                    help="skip the BF16-vs-FP32, batched-vs-per-set and step-function runs")
     return ap.parse_args()
 
 
@@ -178,6 +178,35 @@ def extra_batched(lf, W, torch, dev, reps=3):
     return {"workload": f"batched {len(probs)} sets, l2, sum N*Q = {pairs:.3e}",
             "plan_ms": t_plan, "per_set_ms": t_sets, "speedup": t_sets / t_plan,
             "plan_pair_evals_per_s": pairs / (t_plan * 1e-3)}
+
+
+def extra_steps(lf, W, torch, dev, base, x, y, xq, norms, scalar_fwd_ms, reps=3):
+    """Step-function local constants M_k(t) (Sec. 4.3) on the monotone local
+    workload (d = 4, N = 1e5, Q = 1e6): quantile knots from 65,536 sampled
+    pairs (K = 4), the FP64 all-pairs tables, and the bounds with M_k(dist),
+    against the scalar-M_k forward of the same norm."""
+    pairs = W.rng_for(300).integers(0, base.n, size=(65536, 2))
+    probs = [0.2, 0.4, 0.6, 0.8]
+    out = {"workload": f"monotone_local d={base.d} N={base.n} Q={base.q}, K=4 knots "
+                       f"(quantiles 0.2..0.8 of 65536 sampled pair distances)"}
+    for nm in norms:
+        sym = lf.Metric(base.d, nm)
+        mon = lf.Metric(base.d, nm, mon=base.mon)
+        kn = {}
+        t_knots = _time_ms(torch, lambda: kn.__setitem__(
+            "k", lf.local_knots(x, sym, pairs, probs)), reps)
+        knots = kn["k"].cpu().numpy()
+        tab = {}
+        t_tab = _time_ms(torch, lambda: tab.__setitem__("t", lf.local_steps(x, y, sym, knots)),
+                         reps)
+        d1, _, V32 = tab["t"]
+        t_fwd = _time_ms(torch, lambda: lf.fit_eval_steps(x, y, xq, mon, knots, d1, V32), reps)
+        pairs_fwd = float(base.n) * float(base.q)
+        out[nm] = {"knots_ms": t_knots, "table_ms": t_tab,
+                   "table_pairs_per_s": float(base.n) * float(base.n) / (t_tab * 1e-3),
+                   "fwd_ms": t_fwd, "fwd_pair_evals_per_s": pairs_fwd / (t_fwd * 1e-3),
+                   "fwd_time_vs_scalar_Mk": t_fwd / scalar_fwd_ms[nm]}
+    return out
 
 
 def main():
@@ -288,7 +317,10 @@ def main():
     extras = None
     if not a.no_extras:
         extras = {"bf16_vs_fp32": extra_bf16(lf, W, torch, dev),
-                  "batched_vs_per_set": extra_batched(lf, W, torch, dev)}
+                  "batched_vs_per_set": extra_batched(lf, W, torch, dev),
+                  "step_function_Mk": extra_steps(
+                      lf, W, torch, dev, base, x, y, xq, norms,
+                      {nm: stage_ms[nm]["forward"] for nm in norms})}
 
     rec = {
         "metric": METRIC, "value": value, "unit": "pair-evals/s", "n_gpus": 1,

@@ -1,0 +1,9 @@
+// Instantiation unit of the step-function bound kernel for one norm (all d
+// and monotone counts).
+#include "local_fwd.hpp"
+
+namespace lip {
+
+StepLaunch step_fwd_linf(int d, int dm) { return step_fwd_table<3>(d, dm); }
+
+}  // namespace lip

@@ -1,10 +1,11 @@
 // Host entry points of the step-function local constants of Sec. 4.3
 // (lip_local_knots, lip_local_steps, lip_fit_eval_steps) and their small
-// helper kernels; the pair kernels are in local_steps.hpp, instantiated per
-// norm in local_steps_{l1,l2,linf}.hip.
+// helper kernels; the pair kernels are in local_steps.hpp (tables) and
+// local_fwd.hpp (bounds), instantiated per norm in local_steps_*.hip and
+// local_fwd_*.hip.
 #include <math.h>
 
-#include "local_steps.hpp"
+#include "local_fwd.hpp"
 
 namespace lip {
 
@@ -128,19 +129,153 @@ __global__ void steps_combine_kernel(StepArgs A, int KB)
     }
 }
 
-// Forward staging: first-segment threshold per datum and the table in
-// segment-major order, the slots past the K-th knot repeating V_{K+1}.
-__global__ void steps_stage_kernel(const double *d1, const float *V, int K, int KB, int norm,
-                                   int64_t n, int64_t npad, double *T1, float *Vs)
+// Forward staging, part 1: first-segment threshold per datum and the table
+// in segment-major order (K + 2 rows).
+__global__ void steps_stage_kernel(const double *d1, const float *V, int K, int norm, int64_t n,
+                                   int64_t npad, double *T1, float *Vs)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < npad; k += stride) {
         const bool in = k < n;
         T1[k] = in ? (norm == 2 ? sq_threshold(d1[k]) : d1[k]) : 0.0;
-        for (int s = 0; s < KB + 2; ++s) {
-            const int src = s == 0 ? 0 : (s <= K ? s : K + 1);
-            Vs[(int64_t)s * npad + k] = in ? V[k * (K + 2) + src] : 0.0f;
+        for (int s = 0; s < K + 2; ++s) Vs[(int64_t)s * npad + k] = in ? V[k * (K + 2) + s] : 0.0f;
+    }
+}
+
+// Largest |x'_j| over the data and the queries (x' = the FP32 transform of
+// the bound path: weights, signs, free coordinates first), as float bits
+// (non-negative floats order like their bit patterns).
+__global__ void steps_amax_kernel(const float *x, int64_t n, const float *xq, int64_t q, int d,
+                                  Xform xf, unsigned int *amax)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t total = n + q;
+    for (int j = 0; j < d; ++j) {
+        float m = 0.0f;
+        for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += stride) {
+            const float v = k < n ? x[k * d + xf.perm[j]] : xq[(k - n) * d + xf.perm[j]];
+            m = fmaxf(m, fabsf(v * xf.scale[j]));
         }
+        for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+        if ((threadIdx.x & 63) == 0) atomicMax(amax + j, __float_as_uint(m));
+    }
+}
+
+__global__ void zero_u32_kernel(unsigned int *p, int n)
+{
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
+}
+
+// Forward staging, part 2: the FP32 records [x' | y | VL0 | VL1 | D1hi] of
+// local_fwd.hpp.  VL0 / VL1 are the smallest table entries overall and past
+// the first segment; D1hi = up(d1 (1 + rho) + alpha), alpha from amax.
+__global__ void steps_rec_kernel(const float *x, const float *y, const double *d1, const float *V,
+                                 int K, int d, int64_t n, int64_t npad, Xform xf,
+                                 const unsigned int *amax, float *rec)
+{
+    const int S = d + kStepRec;
+    double asum = 0.0;
+    for (int j = 0; j < d; ++j) asum += (double)__uint_as_float(amax[j]);
+    const double alpha = 0x1p-21 * asum + 0x1p-70;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < npad; k += stride) {
+        float *o = rec + k * S;
+        if (k >= n) {
+            for (int j = 0; j < S; ++j) o[j] = 0.0f;
+            continue;
+        }
+        for (int j = 0; j < d; ++j) o[j] = x[k * d + xf.perm[j]] * xf.scale[j];
+        o[d] = y[k];
+        float v0 = V[k * (K + 2)], v1 = V[k * (K + 2) + 1];
+        for (int s = 1; s < K + 2; ++s) {
+            const float v = V[k * (K + 2) + s];
+            v1 = v < v1 ? v : v1;
+        }
+        v0 = v1 < v0 ? v1 : v0;
+        o[d + 1] = v0;
+        o[d + 2] = v1;
+        const double t = d1[k] * (1.0 + (double)kStepRho) + alpha;
+        o[d + 3] = round_up_f32(t);
+    }
+}
+
+// Spatial order of the queries: Morton code of the coordinates quantised to
+// 32 / d bits (at least 1, at most 16) inside the queries' bounding box,
+// packed as (code << 32 | index); positions q..P-1 are padding (~0).
+__device__ inline unsigned int f32_key(float v)
+{
+    const unsigned int b = __float_as_uint(v);
+    return (b >> 31) ? ~b : (b | 0x80000000u);
+}
+
+__device__ inline float f32_unkey(unsigned int k)
+{
+    return __uint_as_float((k >> 31) ? (k & 0x7FFFFFFFu) : ~k);
+}
+
+__global__ void qbox_init_kernel(unsigned int *bb, int d)
+{
+    const int j = threadIdx.x;
+    if (j < d) {
+        bb[j] = ~0u;
+        bb[kMaxDim + j] = 0u;
+    }
+}
+
+__global__ void qbox_kernel(const float *xq, int64_t q, int d, unsigned int *bb)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int j = 0; j < d; ++j) {
+        unsigned int lo = ~0u, hi = 0u;
+        for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < q; k += stride) {
+            const unsigned int key = f32_key(xq[k * d + j]);
+            lo = key < lo ? key : lo;
+            hi = key > hi ? key : hi;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const unsigned int a = __shfl_xor(lo, off), b = __shfl_xor(hi, off);
+            lo = a < lo ? a : lo;
+            hi = b > hi ? b : hi;
+        }
+        if ((threadIdx.x & 63) == 0) {
+            atomicMin(bb + j, lo);
+            atomicMax(bb + kMaxDim + j, hi);
+        }
+    }
+}
+
+__global__ void qmorton_kernel(const float *xq, int64_t q, int d, int64_t P, const unsigned int *bb,
+                               unsigned long long *keys)
+{
+    const int bits = 32 / d > 0 ? (32 / d < 16 ? 32 / d : 16) : 1;
+    const float cells = (float)(1u << bits);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < P; k += stride) {
+        if (k >= q) {
+            keys[k] = ~0ull;
+            continue;
+        }
+        unsigned long long code = 0;
+        unsigned int c[kMaxDim];
+        for (int j = 0; j < d; ++j) {
+            const float lo = f32_unkey(bb[j]), hi = f32_unkey(bb[kMaxDim + j]);
+            float t = hi > lo ? (xq[k * d + j] - lo) / (hi - lo) * cells : 0.0f;
+            t = t < 0.0f ? 0.0f : (t > cells - 1.0f ? cells - 1.0f : t);  // NaN -> cells - 1
+            c[j] = (unsigned int)t;
+        }
+        for (int b = bits - 1; b >= 0; --b)
+            for (int j = 0; j < d; ++j) code = (code << 1) | ((c[j] >> b) & 1u);
+        keys[k] = (code << 32) | (unsigned int)k;
+    }
+}
+
+StepLaunch get_step_fwd(int norm, int d, int dm)
+{
+    switch (norm) {
+    case LIP_L1: return step_fwd_l1(d, dm);
+    case LIP_L2: return step_fwd_l2(d, dm);
+    case LIP_LINF: return step_fwd_linf(d, dm);
+    default: return nullptr;
     }
 }
 
@@ -184,7 +319,9 @@ size_t local_ws_bytes(int64_t n, int64_t q, int d)
     const int64_t npad = ds_npad(n);
     const size_t staged = align_up((size_t)npad * (size_t)(d + 2) * 8, 256) +
                           align_up((size_t)npad * 8, 256) +
-                          align_up((size_t)npad * (kMaxKnots + 2) * 4, 256);
+                          align_up((size_t)npad * (kMaxKnots + 2) * 4, 256) +
+                          align_up((size_t)npad * (size_t)(d + kStepRec) * 4, 256) + 256 +
+                          align_up((size_t)sort_len(q > 0 ? q : 1) * 8, 256) + 256;
     size_t part = builder_partial_bytes(n);
     const size_t fwd = partial_bytes(q);
     const size_t knots = align_up((size_t)sort_len(n) * 8, 256) + align_up((size_t)n * 16, 256);
@@ -281,7 +418,8 @@ extern "C" lip_status lip_local_steps(const lip_metric *metric, const float *x, 
     A.ds.X = X;
     char *p = (char *)ws + align_up((size_t)A.ds.npad * (size_t)(mi.d + 2) * 8, 256) +
               align_up((size_t)A.ds.npad * 8, 256) +
-              align_up((size_t)A.ds.npad * (kMaxKnots + 2) * 4, 256);
+              align_up((size_t)A.ds.npad * (kMaxKnots + 2) * 4, 256) +
+              align_up((size_t)A.ds.npad * (size_t)(mi.d + kStepRec) * 4, 256) + 256;
     choose_chunks(n, 64 * kDsRows, kStepMaxChunks, &A.ds);
     const size_t e = (size_t)A.ds.n_chunks * (size_t)n;
     A.p_d1 = (double *)p;
@@ -327,10 +465,9 @@ extern "C" lip_status lip_fit_eval_steps(const lip_metric *metric, const float *
     }
     StepArgs A{};
     Signs sg{};
-    const bool hasw = fill_ds_metric(mi, true, &A.ds, &sg);
-    const int KB = K <= 4 ? 4 : 8;
-    StepLaunchers L;
-    if (!get_steps(mi.norm, mi.d, hasw, KB, &L)) return LIP_E_UNSUPPORTED;
+    (void)fill_ds_metric(mi, true, &A.ds, &sg);
+    StepLaunch launch = get_step_fwd(mi.norm, mi.d, mi.dm);
+    if (!launch) return LIP_E_UNSUPPORTED;
     A.K = K;
     for (int j = 0; j < kMaxKnots; ++j) {
         const double kq = j < K ? steps->knots[j] : __builtin_inf();
@@ -338,6 +475,7 @@ extern "C" lip_status lip_fit_eval_steps(const lip_metric *metric, const float *
         A.knotS[j] = mi.norm == LIP_L2 ? sq_threshold(kq) : kq;
     }
     for (int j = 0; j < kMaxDim; ++j) A.qsign[j] = sg.s[j];
+    A.xf = mi.xf;
     A.ds.n = n;
     A.ds.npad = ds_npad(n);
     A.ds.norm = mi.norm;
@@ -347,9 +485,20 @@ extern "C" lip_status lip_fit_eval_steps(const lip_metric *metric, const float *
     p += align_up((size_t)A.ds.npad * 8, 256);
     float *Vs = (float *)p;
     p += align_up((size_t)A.ds.npad * (kMaxKnots + 2) * 4, 256);
+    float *rec = (float *)p;
+    p += align_up((size_t)A.ds.npad * (size_t)(mi.d + kStepRec) * 4, 256);
+    unsigned int *amax = (unsigned int *)p;
+    p += 256;
+    const int64_t PQ = sort_len(q);
+    unsigned long long *qorder = (unsigned long long *)p;
+    p += align_up((size_t)PQ * 8, 256);
+    unsigned int *qbb = (unsigned int *)p;
+    p += 256;
+    A.qorder = qorder;
     A.ds.X = X;
     A.T1 = T1;
     A.Vs = Vs;
+    A.rec = rec;
     A.xq = xq;
     A.q = q;
     A.g = g;
@@ -376,9 +525,24 @@ extern "C" lip_status lip_fit_eval_steps(const lip_metric *metric, const float *
     if (launch_stage64(mi.d, x, y, nullptr, 0.0f, n, A.ds.npad, sg, X, s) != hipSuccess)
         return LIP_E_DEVICE;
     hipLaunchKernelGGL(steps_stage_kernel, dim3(grid1d(A.ds.npad)), dim3(256), 0, s, steps->d1,
-                       steps->V, K, KB, mi.norm, n, A.ds.npad, T1, Vs);
+                       steps->V, K, mi.norm, n, A.ds.npad, T1, Vs);
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, amax, mi.d);
+    int64_t ga = (n + q + 255) / 256;
+    if (ga > 1024) ga = 1024;
+    hipLaunchKernelGGL(steps_amax_kernel, dim3((unsigned)ga), dim3(256), 0, s, x, n, xq, q, mi.d,
+                       mi.xf, amax);
+    hipLaunchKernelGGL(steps_rec_kernel, dim3(grid1d(A.ds.npad)), dim3(256), 0, s, x, y,
+                       steps->d1, steps->V, K, mi.d, n, A.ds.npad, mi.xf,
+                       (const unsigned int *)amax, rec);
+    hipLaunchKernelGGL(qbox_init_kernel, dim3(1), dim3(64), 0, s, qbb, mi.d);
+    int64_t gq = (q + 255) / 256;
+    if (gq > 1024) gq = 1024;
+    hipLaunchKernelGGL(qbox_kernel, dim3((unsigned)gq), dim3(256), 0, s, xq, q, mi.d, qbb);
+    hipLaunchKernelGGL(qmorton_kernel, dim3(grid1d(PQ)), dim3(256), 0, s, xq, q, mi.d, PQ,
+                       (const unsigned int *)qbb, qorder);
+    if (launch_sort_u64(qorder, PQ, s) != hipSuccess) return LIP_E_DEVICE;
     const unsigned grid = (unsigned)(((qwaves + 3) / 4) * A.ds.n_chunks);
-    (mi.dm > 0 ? L.fwd_mon : L.fwd)(A, dim3(grid), dim3(256), s);
+    launch(A, dim3(grid), dim3(256), s);
     if (hipGetLastError() != hipSuccess) return LIP_E_DEVICE;
     if (A.ds.n_chunks > 1) {
         CombineArgs c{};
