@@ -14,6 +14,7 @@ OpenMP over queries/rows), written from the paper's definitions:
   * subgradients:           chain rule through the selected data points
   * step-function M_k(t):   Sec. 4.3, quantile knots from sampled distances,
                             per-datum tables, bounds with M_k(dist)
+  * smoothing penalty:      Sec. 4.4, Eq. (7) and its gradient
 This module only marshals numpy arrays into that library.
 """
 from __future__ import annotations
@@ -77,6 +78,8 @@ def _load():
         lib.orc_bounds_step.restype = None
         lib.orc_candidates_step.argtypes = [i32, i32, P, P, P, P, i64, P, i32, P, P, P, P, P]
         lib.orc_candidates_step.restype = None
+        lib.orc_smooth.argtypes = [i32, i32, P, P, P, P, i64, f64, P, P, f64, P, P]
+        lib.orc_smooth.restype = None
         _lib = lib
     return _lib
 
@@ -245,6 +248,21 @@ def candidates_step(x, y, xq1, norm: int, knots_, d1, V32, mon=None, w=None):
     _load().orc_candidates_step(d, norm, _p(w), _p(mon), _p(x), _p(y), n, _p(kn), kn.shape[0],
                                 _p(d1), _p(V32), _p(q1), _p(u), _p(l))
     return u, l
+
+
+def smooth(x, y, eps, norm: int, M: float = 0.0, Mk=None, p: float = 1.0, mon=None, w=None):
+    """(F, grad[n]) float64: the penalty objective of Eq. (7) and its gradient at eps."""
+    d = int(np.shape(x)[1])
+    x, y, w, mon = _common(x, y, w, mon, d)
+    Mk = None if Mk is None else _f32(Mk)
+    e = np.ascontiguousarray(eps, np.float64)
+    n = x.shape[0]
+    assert e.shape == (n,)
+    F = np.zeros(1, np.float64)
+    g = np.empty(n, np.float64)
+    _load().orc_smooth(d, norm, _p(w), _p(mon), _p(x), _p(y), n, float(M), _p(Mk), _p(e),
+                       float(p), _p(F), _p(g))
+    return float(F[0]), g
 
 
 def round_up_f32(v) -> np.ndarray:

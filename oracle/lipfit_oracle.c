@@ -561,3 +561,50 @@ void orc_candidates_step(int d, int norm, const double *w, const signed char *mo
         l[k] = (double)y[k] - step_value(dl, d1[k], vk, knots, K) * dl;
     }
 }
+
+/* ---- penalty form of the smoothing problem (Sec. 4.4, Eq. 7) --------------
+ *
+ * With corrections eps (z = y + eps) the data must satisfy, for every ordered
+ * pair i != k, the two constraints of Eqs. (5)-(6); written with the
+ * directional distances (Sec. 4.1) and the datum k's constant, as in the
+ * consistency check:
+ *     a_ik = z_i - z_k - M_k dist_up(x^i, x^k) <= 0          (Eq. 5)
+ *     b_ik = z_k - z_i - M_k dist_lo(x^i, x^k) <= 0          (Eq. 6)
+ * Eq. (7) minimises
+ *     F(eps) = (1/p) ||eps||^2 + sum_{i != k} ( (a_ik)_+^2 + (b_ik)_+^2 ).
+ * This returns F and its gradient: d/d eps_i of (a_ik)_+^2 is 2 (a_ik)_+ and
+ * d/d eps_k is -2 (a_ik)_+; (b_ik)_+^2 gives the opposite signs.  Plain
+ * serial loops over all ordered pairs. */
+void orc_smooth(int d, int norm, const double *w, const signed char *mon, const float *x,
+                const float *y, long n, double M, const float *Mk, const double *eps, double p,
+                double *F, double *grad)
+{
+    double total = 0.0;
+    for (long i = 0; i < n; ++i) grad[i] = 0.0;
+    for (long i = 0; i < n; ++i) {
+        for (long k = 0; k < n; ++k) {
+            if (k == i) continue;
+            double du, dl;
+            dist_pair(d, norm, w, mon, x + i * (long)d, x + k * (long)d, &du, &dl, NULL, NULL);
+            double mk = m_of(Mk, M, k);
+            double zi = (double)y[i] + eps[i], zk = (double)y[k] + eps[k];
+            double a = zi - zk - mk * du;
+            double b = zk - zi - mk * dl;
+            if (a > 0.0) {
+                total += a * a;
+                grad[i] += 2.0 * a;
+                grad[k] -= 2.0 * a;
+            }
+            if (b > 0.0) {
+                total += b * b;
+                grad[k] += 2.0 * b;
+                grad[i] -= 2.0 * b;
+            }
+        }
+    }
+    for (long i = 0; i < n; ++i) {
+        total += eps[i] * eps[i] / p;
+        grad[i] += 2.0 * eps[i] / p;
+    }
+    *F = total;
+}
