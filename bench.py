@@ -106,7 +106,8 @@ def parse():
                     help="queries per norm in the oracle's CPU-baseline sample")
     ap.add_argument("--norms", default="l1,l2,linf")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the BF16-vs-FP32, batched-vs-per-set and step-function runs")
+                    help="skip the BF16-vs-FP32, batched-vs-per-set, step-function and "
+                         "smoothing runs")
     return ap.parse_args()
 
 
@@ -206,6 +207,20 @@ def extra_steps(lf, W, torch, dev, base, x, y, xq, norms, scalar_fwd_ms, reps=3)
                    "table_pairs_per_s": float(base.n) * float(base.n) / (t_tab * 1e-3),
                    "fwd_ms": t_fwd, "fwd_pair_evals_per_s": pairs_fwd / (t_fwd * 1e-3),
                    "fwd_time_vs_scalar_Mk": t_fwd / scalar_fwd_ms[nm]}
+    return out
+
+
+def extra_smooth(lf, W, torch, dev, base, x, y, norms, reps=3):
+    """Penalty objective of the smoothing problem (Sec. 4.4, Eq. 7) and its
+    gradient on the monotone local workload's data (N = 1e5, d = 4, global
+    M = 2, p = 1): one fused pass over the N^2 ordered pairs per evaluation."""
+    out = {"workload": f"monotone_local data d={base.d} N={base.n}, M=2, p=1, eps=0"}
+    eps = torch.zeros(base.n, device=dev)
+    for nm in norms:
+        met = lf.Metric(base.d, nm, mon=base.mon)
+        t = _time_ms(torch, lambda: lf.smooth_objective(x, y, eps, met, M=2.0, p=1.0), reps)
+        out[nm] = {"objective_and_gradient_ms": t,
+                   "pairs_per_s": float(base.n) * float(base.n) / (t * 1e-3)}
     return out
 
 
@@ -320,7 +335,8 @@ def main():
                   "batched_vs_per_set": extra_batched(lf, W, torch, dev),
                   "step_function_Mk": extra_steps(
                       lf, W, torch, dev, base, x, y, xq, norms,
-                      {nm: stage_ms[nm]["forward"] for nm in norms})}
+                      {nm: stage_ms[nm]["forward"] for nm in norms}),
+                  "smoothing_objective": extra_smooth(lf, W, torch, dev, base, x, y, norms)}
 
     rec = {
         "metric": METRIC, "value": value, "unit": "pair-evals/s", "n_gpus": 1,

@@ -81,9 +81,8 @@ typedef struct {
 
 typedef void *lip_stream; /* hipStream_t */
 
-/* Bytes of workspace that lip_bounds / lip_fit_eval / lip_consistency /
- * lip_estimate_M need for these sizes and flags (an upper bound; 0 is never
- * returned). */
+/* Bytes of workspace that the entry points taking `ws` need for these sizes
+ * and flags (an upper bound; 0 is never returned). */
 size_t lip_workspace_size(int64_t n, int64_t q, int32_t d, uint32_t flags);
 
 /* Eq. (2): the upper and lower Lipschitz bounds at q query points and the
@@ -241,6 +240,26 @@ lip_status lip_fit_eval_steps(const lip_metric *metric, const float *x, const fl
                               const lip_steps *steps, const float *xq, int64_t q, float *g,
                               float *h_up, float *h_lo, int32_t *arg_up, int32_t *arg_lo,
                               void *ws, size_t ws_bytes, uint32_t flags, lip_stream stream);
+
+/* ---- smoothing (Sec. 4.4) -------------------------------------------------
+ * Penalty form of the smoothing problem, Eq. (7): with corrections eps and
+ * z = y + eps, for every ordered pair i != k
+ *     a_ik = z_i - z_k - M_k dist_up(x^i, x^k)     (Eq. 5 as a penalty)
+ *     b_ik = z_k - z_i - M_k dist_lo(x^i, x^k)     (Eq. 6 as a penalty)
+ *     F(eps) = (1/p) ||eps||^2 + sum_{i != k} (a_ik)_+^2 + (b_ik)_+^2
+ * (M_k = M when Mk is NULL; directional distances on monotone coordinates as
+ * in lip_consistency).  One fused pass over all pairs, no distance matrix.
+ *   eps [n]      DEVICE FP32 corrections
+ *   p            penalty parameter > 0 (finite)
+ *   F [1]        DEVICE FP64 output, optional: the objective
+ *   grad [n]     DEVICE FP32 output, optional: dF / d eps
+ * Pair terms are FP32, sums FP64 in a fixed order (repeated calls give
+ * identical results).  Meant to be called by an unconstrained minimiser
+ * (L-BFGS); y + eps is then the smoothed data.  Needs ws. */
+lip_status lip_smooth_objective(const lip_metric *metric, const float *x, const float *y,
+                                int64_t n, float M, const float *Mk, const float *eps, double p,
+                                double *F, float *grad, void *ws, size_t ws_bytes,
+                                uint32_t flags, lip_stream stream);
 
 /* ---- many independent fits in one launch ------------------------------------
  * One entry per data set: its own metric, data, constants, queries and

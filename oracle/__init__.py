@@ -80,6 +80,8 @@ def _load():
         lib.orc_candidates_step.restype = None
         lib.orc_smooth.argtypes = [i32, i32, P, P, P, P, i64, f64, P, P, f64, P, P]
         lib.orc_smooth.restype = None
+        lib.orc_smooth_scale.argtypes = [i32, i32, P, P, P, P, i64, f64, P, P, f64, P, P, P]
+        lib.orc_smooth_scale.restype = None
         _lib = lib
     return _lib
 
@@ -263,6 +265,21 @@ def smooth(x, y, eps, norm: int, M: float = 0.0, Mk=None, p: float = 1.0, mon=No
     _load().orc_smooth(d, norm, _p(w), _p(mon), _p(x), _p(y), n, float(M), _p(Mk), _p(e),
                        float(p), _p(F), _p(g))
     return float(F[0]), g
+
+
+def smooth_scale(x, y, eps, norm: int, tau: float, M: float = 0.0, Mk=None, mon=None, w=None):
+    """(A, row_abs[n], row_cnt[n]): error scale of Eq. (7) for comparisons."""
+    d = int(np.shape(x)[1])
+    x, y, w, mon = _common(x, y, w, mon, d)
+    Mk = None if Mk is None else _f32(Mk)
+    e = np.ascontiguousarray(eps, np.float64)
+    n = x.shape[0]
+    A = np.zeros(1, np.float64)
+    ra = np.empty(n, np.float64)
+    rc = np.empty(n, np.int64)
+    _load().orc_smooth_scale(d, norm, _p(w), _p(mon), _p(x), _p(y), n, float(M), _p(Mk), _p(e),
+                             float(tau), _p(A), _p(ra), _p(rc))
+    return float(A[0]), ra, rc
 
 
 def round_up_f32(v) -> np.ndarray:

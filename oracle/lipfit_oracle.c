@@ -608,3 +608,40 @@ void orc_smooth(int d, int norm, const double *w, const signed char *mon, const 
     }
     *F = total;
 }
+
+/* Error scale of the penalty objective, for comparisons only: the sum A of
+ * the positive parts (a_ik)_+ + (b_ik)_+ over all ordered pairs, and per row
+ * i, over the four terms that move eps_i (a_ik, b_ik of the pairs (i, k) and
+ * a_ki, b_ki of the pairs (k, i)), the sum of their gradient magnitudes
+ * 2 (t)_+ (row_abs) and the number of them above -tau (row_cnt). */
+void orc_smooth_scale(int d, int norm, const double *w, const signed char *mon, const float *x,
+                      const float *y, long n, double M, const float *Mk, const double *eps,
+                      double tau, double *A, double *row_abs, long *row_cnt)
+{
+    double total = 0.0;
+    for (long i = 0; i < n; ++i) {
+        row_abs[i] = 0.0;
+        row_cnt[i] = 0;
+    }
+    for (long i = 0; i < n; ++i) {
+        for (long k = 0; k < n; ++k) {
+            if (k == i) continue;
+            double du, dl;
+            dist_pair(d, norm, w, mon, x + i * (long)d, x + k * (long)d, &du, &dl, NULL, NULL);
+            double mk = m_of(Mk, M, k);
+            double zi = (double)y[i] + eps[i], zk = (double)y[k] + eps[k];
+            double t[2] = {zi - zk - mk * du, zk - zi - mk * dl};
+            for (int j = 0; j < 2; ++j) {
+                double v = t[j] > 0.0 ? t[j] : 0.0;
+                total += v;
+                row_abs[i] += 2.0 * v;
+                row_abs[k] += 2.0 * v;
+                if (t[j] > -tau) {
+                    ++row_cnt[i];
+                    ++row_cnt[k];
+                }
+            }
+        }
+    }
+    *A = total;
+}

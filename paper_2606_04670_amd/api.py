@@ -11,6 +11,8 @@ runs in the library's kernels.  Functions mirror the C entry points:
     local_steps         -> lip_local_steps
     fit_eval_steps      -> lip_fit_eval_steps
     StepModel           -> the three above in sequence
+    smooth_objective    -> lip_smooth_objective           (Sec. 4.4, Eq. 7)
+    smooth_lipschitz    -> L-BFGS over smooth_objective   (Sec. 5, smooth_lipschitz)
     Plan                -> lip_plan_create / execute / destroy
     LipFitFn            -> torch.autograd.Function over fit_eval + backward
 """
@@ -303,6 +305,51 @@ class StepModel:
     def __call__(self, xq, want=("g", "h_up", "h_lo", "arg_up", "arg_lo")):
         return fit_eval_steps(self.x, self.y, xq, self.metric, self.knots, self.d1, self.V32,
                               want=want)
+
+
+# ---- smoothing (Sec. 4.4) ---------------------------------------------------------
+
+
+def smooth_objective(x, y, eps, metric: Metric, M=None, Mk=None, p: float = 1.0,
+                     want_F: bool = True, want_grad: bool = True):
+    """Eq. (7) at the corrections eps: (F float64 [1] tensor or None,
+    grad float32 [n] tensor or None)."""
+    x, y, M, Mk, dev = _prep(x, y, M, Mk)
+    eps = _f32(eps, "eps", dev)
+    n = x.shape[0]
+    F = torch.empty(1, dtype=torch.float64, device=dev) if want_F else None
+    g = torch.empty(n, dtype=torch.float32, device=dev) if want_grad else None
+    lib = L.load()
+    ws = workspace(dev, lib.lip_workspace_size(n, 0, metric.d, 0))
+    st = lib.lip_smooth_objective(metric.ref(), _ptr(x), _ptr(y), n, M, _ptr(Mk), _ptr(eps),
+                                  float(p), _ptr(F), _ptr(g), _ptr(ws), ws.numel(), 0,
+                                  _stream(dev))
+    L.check("lip_smooth_objective", st)
+    return F, g
+
+
+def smooth_lipschitz(x, y, metric: Metric, M=None, Mk=None, p: float = 1.0,
+                     max_iter: int = 200, tolerance_grad: float = 1e-7, history_size: int = 20):
+    """Smoothed data y + eps minimising Eq. (7) with torch's L-BFGS as the
+    unconstrained minimiser (the paper's choice); every objective and
+    gradient evaluation is one lip_smooth_objective call.  Returns
+    (y + eps, eps, final objective)."""
+    x = _f32(x, "x")
+    y = _f32(y, "y", x.device)
+    eps = torch.zeros_like(y, requires_grad=True)
+    opt = torch.optim.LBFGS([eps], max_iter=max_iter, tolerance_grad=tolerance_grad,
+                            tolerance_change=0.0, history_size=history_size,
+                            line_search_fn="strong_wolfe")
+
+    def closure():
+        F, g = smooth_objective(x, y, eps.detach(), metric, M=M, Mk=Mk, p=p)
+        eps.grad = g
+        return F.to(torch.float32).reshape(())
+
+    opt.step(closure)
+    F, _ = smooth_objective(x, y, eps.detach(), metric, M=M, Mk=Mk, p=p, want_grad=False)
+    e = eps.detach()
+    return y + e, e, F
 
 
 class LipFitFn(torch.autograd.Function):

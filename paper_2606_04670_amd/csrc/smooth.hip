@@ -1,0 +1,148 @@
+// Host entry point of the smoothing objective (lip_smooth_objective) and its
+// staging / reduction kernels; the pair kernel is in smooth.hpp,
+// instantiated per norm in smooth_{l1,l2,linf}.hip.
+#include "smooth.hpp"
+
+namespace lip {
+
+namespace {
+
+// Records [x' | z = y + eps | M_k] with the bound path's coordinate
+// transform; padded records are zero (never read as columns).
+__global__ void smooth_stage_kernel(const float *x, const float *y, const float *eps,
+                                    const float *Mk, float M, int d, int64_t n, int64_t npad,
+                                    Xform xf, float *rec)
+{
+    const int S = d + 2;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < npad; k += stride) {
+        float *o = rec + k * S;
+        if (k >= n) {
+            for (int j = 0; j < S; ++j) o[j] = 0.0f;
+            continue;
+        }
+        for (int j = 0; j < d; ++j) o[j] = x[k * d + xf.perm[j]] * xf.scale[j];
+        o[d] = y[k] + eps[k];
+        o[d + 1] = Mk ? Mk[k] : M;
+    }
+}
+
+// Per row: the chunk partials in chunk order plus the (1/p) eps^2 term and
+// its derivative.
+__global__ void smooth_rows_kernel(const double *pF, const double *pG, int n_chunks, int64_t n,
+                                   const float *eps, double p, double *rowF, float *grad)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double f = 0.0, g = 0.0;
+    for (int c = 0; c < n_chunks; ++c) {
+        f += pF[(int64_t)c * n + i];
+        g += pG[(int64_t)c * n + i];
+    }
+    const double e = (double)eps[i];
+    rowF[i] = f + e * e / p;
+    if (grad) grad[i] = (float)(g + 2.0 * e / p);
+}
+
+// F = sum of the row values in a fixed order: thread t adds rows t, t + 1024,
+// ... in turn, then a fixed tree over the 1024 partial sums.
+__global__ void __launch_bounds__(1024) smooth_reduce_kernel(const double *rowF, int64_t n,
+                                                             double *F)
+{
+    __shared__ double s[1024];
+    double a = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) a += rowF[i];
+    s[threadIdx.x] = a;
+    __syncthreads();
+    for (int h = 512; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) F[0] = s[0];
+}
+
+SmoothLaunch get_smooth(int norm, int d, int dm, bool local)
+{
+    switch (norm) {
+    case LIP_L1: return smooth_l1(d, dm, local);
+    case LIP_L2: return smooth_l2(d, dm, local);
+    case LIP_LINF: return smooth_linf(d, dm, local);
+    default: return nullptr;
+    }
+}
+
+int64_t smooth_npad(int64_t n) { return (n + kSmoothTile - 1) / kSmoothTile * kSmoothTile; }
+
+}  // namespace
+
+size_t smooth_ws_bytes(int64_t n, int d)
+{
+    const int64_t npad = smooth_npad(n);
+    return align_up((size_t)npad * (size_t)(d + 2) * 4, 256) +
+           2 * align_up((size_t)kSmoothMaxChunks * (size_t)n * 8, 256) +
+           align_up((size_t)n * 8, 256) + 256;
+}
+
+}  // namespace lip
+
+using namespace lip;
+
+extern "C" lip_status lip_smooth_objective(const lip_metric *metric, const float *x,
+                                           const float *y, int64_t n, float M, const float *Mk,
+                                           const float *eps, double p, double *F, float *grad,
+                                           void *ws, size_t ws_bytes, uint32_t flags,
+                                           lip_stream stream)
+{
+    MetricInfo mi;
+    lip_status st = parse_metric(metric, &mi);
+    if (st != LIP_OK) return st;
+    if (flags & ~LIP_FLAG_CHECK_FINITE) return LIP_E_ARG;
+    if (n <= 0 || n > kMaxIndex - kSmoothTile) return LIP_E_SHAPE;
+    if (!x || !y || !eps) return LIP_E_ARG;
+    if (!Mk && (!(M >= 0.0f) || !__builtin_isfinite(M))) return LIP_E_VALUE;
+    if (!(p > 0.0) || !__builtin_isfinite(p)) return LIP_E_VALUE;
+    if (!ws || ws_bytes < smooth_ws_bytes(n, mi.d)) return LIP_E_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    if (flags & LIP_FLAG_CHECK_FINITE) {
+        const float *arr[4] = {x, y, eps, Mk};
+        const int64_t cnt[4] = {n * mi.d, n, n, Mk ? n : 0};
+        st = check_finite(arr, cnt, 4, ws, s);
+        if (st != LIP_OK) return st;
+    }
+    SmoothLaunch launch = get_smooth(mi.norm, mi.d, mi.dm, Mk != nullptr);
+    if (!launch) return LIP_E_UNSUPPORTED;
+    SmoothArgs A{};
+    A.n = n;
+    A.npad = smooth_npad(n);
+    char *p0 = (char *)ws;
+    float *rec = (float *)p0;
+    p0 += align_up((size_t)A.npad * (size_t)(mi.d + 2) * 4, 256);
+    const int R = rows_for_dim(mi.d);
+    const int64_t row_waves = (n + 64 * R - 1) / (64 * R);
+    int64_t nc = (8192 + row_waves - 1) / row_waves;
+    if (nc > kSmoothMaxChunks) nc = kSmoothMaxChunks;
+    if (nc < 1) nc = 1;
+    int64_t cols = (n + nc - 1) / nc;
+    cols = (cols + kSmoothTile - 1) / kSmoothTile * kSmoothTile;
+    A.chunk_cols = cols;
+    A.n_chunks = (int)((n + cols - 1) / cols);
+    A.rec = rec;
+    A.pF = (double *)p0;
+    p0 += align_up((size_t)kSmoothMaxChunks * (size_t)n * 8, 256);
+    A.pG = (double *)p0;
+    p0 += align_up((size_t)kSmoothMaxChunks * (size_t)n * 8, 256);
+    double *rowF = (double *)p0;
+    int64_t gs = (A.npad + 255) / 256;
+    if (gs > 65536) gs = 65536;
+    hipLaunchKernelGGL(smooth_stage_kernel, dim3((unsigned)gs), dim3(256), 0, s, x, y, eps, Mk, M,
+                       mi.d, n, A.npad, mi.xf, rec);
+    const unsigned grid = (unsigned)(((row_waves + 3) / 4) * A.n_chunks);
+    launch(A, dim3(grid), dim3(256), s);
+    hipLaunchKernelGGL(smooth_rows_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       (const double *)A.pF, (const double *)A.pG, A.n_chunks, n, eps, p, rowF,
+                       grad);
+    if (F)
+        hipLaunchKernelGGL(smooth_reduce_kernel, dim3(1), dim3(1024), 0, s, (const double *)rowF,
+                           n, F);
+    return dev_status(hipGetLastError());
+}

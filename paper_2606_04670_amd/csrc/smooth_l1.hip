@@ -1,0 +1,9 @@
+// Instantiation unit of the smoothing-objective kernel for one norm (all d
+// and monotone counts, global and per-datum constants).
+#include "smooth.hpp"
+
+namespace lip {
+
+SmoothLaunch smooth_l1(int d, int dm, bool local) { return smooth_table<1>(d, dm, local); }
+
+}  // namespace lip

@@ -211,3 +211,19 @@ def test_step_entry_points_validation(L):
     assert ev(q=0) == L.LIP_OK
     assert lib.lip_fit_eval_steps(ctypes.byref(m), FAKE, FAKE, 10, None, FAKE, 5, FAKE, None,
                                   None, None, None, FAKE, 1 << 30, 0, None) == L.LIP_E_ARG
+
+
+def test_smooth_entry_point_validation(L):
+    lib = L.load()
+    m, keep = _metric(L)
+
+    def sm(n=10, M=1.0, eps=FAKE, p=1.0, ws=FAKE, ws_bytes=1 << 30, flags=0):
+        return lib.lip_smooth_objective(ctypes.byref(m), FAKE, FAKE, n, M, None, eps, p, FAKE,
+                                        FAKE, ws, ws_bytes, flags, None)
+    assert sm(n=0) == L.LIP_E_SHAPE
+    assert sm(M=-1.0) == L.LIP_E_VALUE
+    assert sm(p=0.0) == L.LIP_E_VALUE
+    assert sm(p=float("inf")) == L.LIP_E_VALUE
+    assert sm(eps=None) == L.LIP_E_ARG
+    assert sm(ws_bytes=16) == L.LIP_E_WORKSPACE
+    assert sm(flags=L.LIP_FLAG_BF16) == L.LIP_E_ARG
