@@ -15,6 +15,7 @@ OpenMP over queries/rows), written from the paper's definitions:
   * step-function M_k(t):   Sec. 4.3, quantile knots from sampled distances,
                             per-datum tables, bounds with M_k(dist)
   * smoothing penalty:      Sec. 4.4, Eq. (7) and its gradient
+  * k best bounds:          Sec. 5 (k > 1 with weights)
 This module only marshals numpy arrays into that library.
 """
 from __future__ import annotations
@@ -82,6 +83,8 @@ def _load():
         lib.orc_smooth.restype = None
         lib.orc_smooth_scale.argtypes = [i32, i32, P, P, P, P, i64, f64, P, P, f64, P, P, P]
         lib.orc_smooth_scale.restype = None
+        lib.orc_bounds_k.argtypes = [i32, i32, P, P, P, P, i64, f64, P, i32, P, P, i64, P, P, P]
+        lib.orc_bounds_k.restype = None
         _lib = lib
     return _lib
 
@@ -280,6 +283,21 @@ def smooth_scale(x, y, eps, norm: int, tau: float, M: float = 0.0, Mk=None, mon=
     _load().orc_smooth_scale(d, norm, _p(w), _p(mon), _p(x), _p(y), n, float(M), _p(Mk), _p(e),
                              float(tau), _p(A), _p(ra), _p(rc))
     return float(A[0]), ra, rc
+
+
+def bounds_k(x, y, xq, norm: int, wk, M: float = 0.0, Mk=None, mon=None, w=None):
+    """(H_up, H_lo, g) float64: weighted sums of the k best candidates (k = len(wk))."""
+    d = int(np.shape(x)[1])
+    x, y, w, mon = _common(x, y, w, mon, d)
+    xq = _f32(xq).reshape(-1, d)
+    Mk = None if Mk is None else _f32(Mk)
+    wk = np.ascontiguousarray(wk, np.float64)
+    assert 1 <= wk.shape[0] <= x.shape[0]
+    q = xq.shape[0]
+    hu, hl, g = (np.empty(q, np.float64) for _ in range(3))
+    _load().orc_bounds_k(d, norm, _p(w), _p(mon), _p(x), _p(y), x.shape[0], float(M), _p(Mk),
+                         wk.shape[0], _p(wk), _p(xq), q, _p(hu), _p(hl), _p(g))
+    return hu, hl, g
 
 
 def round_up_f32(v) -> np.ndarray:

@@ -645,3 +645,50 @@ void orc_smooth_scale(int d, int norm, const double *w, const signed char *mon, 
     }
     *A = total;
 }
+
+/* ---- k best bounds with weights (Sec. 5, k > 1) ------------------------------
+ *
+ * With k > 1 and weights wk[0..k-1], both bounds use the k best candidates
+ * of Eq. (2): u sorted ascending u_(1) <= u_(2) <= ..., l sorted descending
+ * l_[1] >= l_[2] >= ...;
+ *     H_up = sum_j wk[j] u_(j+1),   H_lo = sum_j wk[j] l_[j+1],   g = (H_up + H_lo) / 2.
+ * (The k values are a multiset: ties need no index rule.)  Requires k <= n. */
+static int cmp_double_desc(const void *pa, const void *pb)
+{
+    double a = *(const double *)pa, b = *(const double *)pb;
+    return (a < b) - (a > b);
+}
+
+void orc_bounds_k(int d, int norm, const double *w, const signed char *mon, const float *x,
+                  const float *y, long n, double M, const float *Mk, int K, const double *wk,
+                  const float *xq, long q, double *h_up, double *h_lo, double *g)
+{
+#pragma omp parallel
+    {
+        double *u = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+        double *l = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+#pragma omp for schedule(dynamic, 16)
+        for (long j = 0; j < q; ++j) {
+            const float *xj = xq + j * (long)d;
+            for (long k = 0; k < n; ++k) {
+                double du, dl;
+                dist_pair(d, norm, w, mon, xj, x + k * (long)d, &du, &dl, NULL, NULL);
+                double mk = m_of(Mk, M, k);
+                u[k] = (double)y[k] + mk * du;
+                l[k] = (double)y[k] - mk * dl;
+            }
+            qsort(u, (size_t)n, sizeof(double), cmp_double);
+            qsort(l, (size_t)n, sizeof(double), cmp_double_desc);
+            double su = 0.0, sl = 0.0;
+            for (int t = 0; t < K; ++t) {
+                su += wk[t] * u[t];
+                sl += wk[t] * l[t];
+            }
+            if (h_up) h_up[j] = su;
+            if (h_lo) h_lo[j] = sl;
+            if (g) g[j] = 0.5 * (su + sl);
+        }
+        free(u);
+        free(l);
+    }
+}
