@@ -106,8 +106,8 @@ def parse():
                     help="queries per norm in the oracle's CPU-baseline sample")
     ap.add_argument("--norms", default="l1,l2,linf")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the BF16-vs-FP32, batched-vs-per-set, step-function and "
-                         "smoothing runs")
+                    help="skip the BF16-vs-FP32, batched-vs-per-set, step-function, "
+                         "smoothing and k-best runs")
     return ap.parse_args()
 
 
@@ -207,6 +207,21 @@ def extra_steps(lf, W, torch, dev, base, x, y, xq, norms, scalar_fwd_ms, reps=3)
                    "table_pairs_per_s": float(base.n) * float(base.n) / (t_tab * 1e-3),
                    "fwd_ms": t_fwd, "fwd_pair_evals_per_s": pairs_fwd / (t_fwd * 1e-3),
                    "fwd_time_vs_scalar_Mk": t_fwd / scalar_fwd_ms[nm]}
+    return out
+
+
+def extra_topk(lf, W, torch, dev, base, x, y, xq, norms, scalar_fwd_ms, reps=3):
+    """The k best bounds with weights (Sec. 5, k = 3, w = (0.8, 0.1, 0.1)) on the
+    monotone local workload (per-datum M_k of the workload), against the
+    k = 1 forward of the same norm."""
+    mk = torch.from_numpy(base.Mk).to(dev)
+    out = {"workload": f"monotone_local d={base.d} N={base.n} Q={base.q}, k=3, w=(0.8,0.1,0.1)"}
+    for nm in norms:
+        met = lf.Metric(base.d, nm, mon=base.mon)
+        t = _time_ms(torch, lambda: lf.fit_eval_k(x, y, xq, met, [0.8, 0.1, 0.1], Mk=mk), reps)
+        out[nm] = {"fwd_ms": t,
+                   "fwd_pair_evals_per_s": float(base.n) * float(base.q) / (t * 1e-3),
+                   "fwd_time_vs_k1": t / scalar_fwd_ms[nm]}
     return out
 
 
@@ -336,7 +351,9 @@ def main():
                   "step_function_Mk": extra_steps(
                       lf, W, torch, dev, base, x, y, xq, norms,
                       {nm: stage_ms[nm]["forward"] for nm in norms}),
-                  "smoothing_objective": extra_smooth(lf, W, torch, dev, base, x, y, norms)}
+                  "smoothing_objective": extra_smooth(lf, W, torch, dev, base, x, y, norms),
+                  "k_best_bounds": extra_topk(lf, W, torch, dev, base, x, y, xq, norms,
+                                             {nm: stage_ms[nm]["forward"] for nm in norms})}
 
     rec = {
         "metric": METRIC, "value": value, "unit": "pair-evals/s", "n_gpus": 1,

@@ -173,6 +173,26 @@ lip_status lip_estimate_M(const lip_metric *metric, const float *x, const float 
                           int32_t mode, int32_t knn, double *M64, float *M32, int64_t *pair,
                           void *ws, size_t ws_bytes, uint32_t flags, lip_stream stream);
 
+/* ---- k best bounds with weights (Sec. 5, k > 1) ------------------------------
+ * Both bounds from the k best candidates of Eq. (2): with the upper
+ * candidates sorted ascending u_(1) <= u_(2) <= .. and the lower ones
+ * descending l_[1] >= l_[2] >= ..,
+ *     h_up = sum_j wk[j] u_(j+1),   h_lo = sum_j wk[j] l_[j+1],   g = (h_up + h_lo) / 2.
+ * The paper's weights add to 1 (not enforced); the result does not
+ * interpolate the data for k > 1.
+ *   k          1..LIP_MAX_K, and k <= n
+ *   wk [k]     HOST weights >= 0 (finite)
+ *   g, h_up, h_lo [q]   optional outputs (FP32)
+ * Other arguments and rules as in lip_fit_eval (LIP_FLAG_BF16 unsupported).
+ * Candidates are FP32 as in lip_fit_eval (k = 1 with wk = {1} gives its
+ * h_up / h_lo bit for bit); the k values are a multiset, so no index rule.
+ * Needs ws. */
+#define LIP_MAX_K 4
+lip_status lip_fit_eval_k(const lip_metric *metric, const float *x, const float *y, int64_t n,
+                          float M, const float *Mk, int32_t k, const float *wk, const float *xq,
+                          int64_t q, float *g, float *h_up, float *h_lo, void *ws,
+                          size_t ws_bytes, uint32_t flags, lip_stream stream);
+
 /* ---- step-function local constants (Sec. 4.3) ----------------------------
  * Each datum k gets a non-decreasing, piecewise constant M_k(t) of the
  * distance t, built from the data:

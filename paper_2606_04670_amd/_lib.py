@@ -21,7 +21,7 @@ LIP_FLAG_CHECK_FINITE = 1 << 0
 LIP_FLAG_BF16 = 1 << 1
 LIP_FLAG_DETERMINISTIC = 1 << 2
 LIP_M_GLOBAL, LIP_M_LOCAL_KNN = 0, 1
-LIP_MAX_DIM, LIP_MAX_KNN, LIP_MAX_KNOTS = 16, 32, 8
+LIP_MAX_DIM, LIP_MAX_KNN, LIP_MAX_KNOTS, LIP_MAX_K = 16, 32, 8, 4
 
 P = ctypes.c_void_p
 i32, i64, u32, f32, f64, sz = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_float,
@@ -57,6 +57,7 @@ _SIGS = {
     "lip_local_knots": (i32, [P, P, i64, P, i64, P, i32, P, P, sz, u32, P]),
     "lip_local_steps": (i32, [P, P, P, i64, P, i32, P, P, P, P, sz, u32, P]),
     "lip_fit_eval_steps": (i32, [P, P, P, i64, P, P, i64, P, P, P, P, P, P, sz, u32, P]),
+    "lip_fit_eval_k": (i32, [P, P, P, i64, f32, P, i32, P, P, i64, P, P, P, P, sz, u32, P]),
     "lip_smooth_objective": (i32, [P, P, P, i64, f32, P, P, f64, P, P, P, sz, u32, P]),
     "lip_plan_create": (i32, [P, P, i32, u32, P]),
     "lip_plan_execute": (i32, [P, P]),

@@ -11,6 +11,7 @@ runs in the library's kernels.  Functions mirror the C entry points:
     local_steps         -> lip_local_steps
     fit_eval_steps      -> lip_fit_eval_steps
     StepModel           -> the three above in sequence
+    fit_eval_k          -> lip_fit_eval_k                 (Sec. 5, k > 1 weighted bounds)
     smooth_objective    -> lip_smooth_objective           (Sec. 4.4, Eq. 7)
     smooth_lipschitz    -> L-BFGS over smooth_objective   (Sec. 5, smooth_lipschitz)
     Plan                -> lip_plan_create / execute / destroy
@@ -124,6 +125,24 @@ def fit_eval(x: torch.Tensor, y: torch.Tensor, xq: torch.Tensor, metric: Metric,
                           _ptr(out.get("arg_up")), _ptr(out.get("arg_lo")), _ptr(ws), ws.numel(),
                           flags, _stream(dev))
     L.check("lip_fit_eval", st)
+    return out
+
+
+def fit_eval_k(x, y, xq, metric: Metric, wk, M=None, Mk=None,
+               want=("g", "h_up", "h_lo")) -> Dict[str, torch.Tensor]:
+    """Weighted k-best bounds (k = len(wk)) and their midpoint."""
+    x, y, M, Mk, dev = _prep(x, y, M, Mk)
+    xq = _f32(xq, "xq", dev)
+    n, q = x.shape[0], xq.shape[0]
+    w = np.ascontiguousarray(np.asarray(wk, np.float32).reshape(-1))
+    out = {k: torch.empty(q, dtype=torch.float32, device=dev) for k in want}
+    lib = L.load()
+    ws = workspace(dev, lib.lip_workspace_size(n, q, metric.d, 0))
+    st = lib.lip_fit_eval_k(metric.ref(), _ptr(x), _ptr(y), n, M, _ptr(Mk), w.shape[0],
+                            w.ctypes.data_as(ctypes.c_void_p), _ptr(xq), q, _ptr(out.get("g")),
+                            _ptr(out.get("h_up")), _ptr(out.get("h_lo")), _ptr(ws), ws.numel(),
+                            0, _stream(dev))
+    L.check("lip_fit_eval_k", st)
     return out
 
 

@@ -1,0 +1,189 @@
+// The k best bounds with weights (Sec. 5, k > 1): for every query the k
+// smallest upper candidates u_(1) <= .. <= u_(k) and the k largest lower
+// candidates l_[1] >= .. >= l_[k] of Eq. (2), and
+//     H_up = sum_j w_j u_(j),   H_lo = sum_j w_j l_[j],   g = (H_up + H_lo) / 2.
+//
+// Same work decomposition and pair arithmetic as the fused bound kernel
+// (pair_bounds on the staged records, queries in VGPRs, records from SGPRs).
+// Each query keeps its kTopK best values per bound in registers, sorted.  A
+// candidate enters only if it beats the current kTopK-th value; the test is
+// one compare per bound and pair, and the insertion (a min into the last slot
+// and one compare-exchange pass) runs only when some lane of the wave needs
+// it.  The k values form a multiset, so no index rule is needed; records past
+// n (the staging's padding repeats the last datum) are masked, so every datum
+// counts once.  Split chunks write their sorted lists; a merge kernel takes
+// the kTopK smallest / largest of all of them.
+#pragma once
+
+#include "bounds_fwd.hpp"
+
+namespace lip {
+
+constexpr int kTopK = 4;
+
+struct TopkArgs {
+    FwdArgs f;            // staged records, n, queries, transform, outputs g / h_up / h_lo
+    int32_t k;
+    float wk[kTopK];      // weights, zero past k
+    int64_t chunk_recs;   // records per chunk (multiple of the group size)
+    float *part;          // [2][n_chunks][q][kTopK] sorted partial lists (n_chunks > 1)
+};
+
+// Ascending list: the new value replaces the last slot if smaller, then one
+// compare-exchange pass from the end restores the order.
+__device__ __forceinline__ void topk_insert_up(float (&s)[kTopK], float v)
+{
+    s[kTopK - 1] = fminf(s[kTopK - 1], v);
+#pragma unroll
+    for (int j = kTopK - 1; j > 0; --j) {
+        const float a = fminf(s[j - 1], s[j]), b = fmaxf(s[j - 1], s[j]);
+        s[j - 1] = a;
+        s[j] = b;
+    }
+}
+
+// Descending list, the mirror.
+__device__ __forceinline__ void topk_insert_lo(float (&s)[kTopK], float v)
+{
+    s[kTopK - 1] = fmaxf(s[kTopK - 1], v);
+#pragma unroll
+    for (int j = kTopK - 1; j > 0; --j) {
+        const float a = fmaxf(s[j - 1], s[j]), b = fminf(s[j - 1], s[j]);
+        s[j - 1] = a;
+        s[j] = b;
+    }
+}
+
+template <int D, int DM, int NORM>
+__global__ void __launch_bounds__(256) bounds_topk_kernel(TopkArgs A)
+{
+    constexpr int S = Rec<D>::S;
+    constexpr int R = rows_for_dim(D);
+    constexpr int G = group_for_dim(D);
+    const FwdArgs &a = A.f;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int chunk = blockIdx.x % a.n_chunks;
+    const int64_t qblock = (int64_t)(blockIdx.x / a.n_chunks) * (blockDim.x >> 6) + wave;
+    const int lane = threadIdx.x & 63;
+    const int64_t q0 = qblock * (64 * R);
+    if (q0 >= a.q) return;
+
+    const float big = opaque_inf();
+    float qv[R][D], qm[R], U[R][kTopK], L[R][kTopK];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        int64_t qi = q0 + r * 64 + lane;
+        qi = qi < a.q ? qi : a.q - 1;
+#pragma unroll
+        for (int j = 0; j < D; ++j) qv[r][j] = a.xq[qi * D + a.xf.perm[j]] * a.xf.scale[j];
+        qm[r] = query_mon_sum<D, DM>(qv[r]);
+#pragma unroll
+        for (int j = 0; j < kTopK; ++j) {
+            U[r][j] = __builtin_inff();
+            L[r][j] = -__builtin_inff();
+        }
+    }
+    const int64_t c0 = (int64_t)chunk * A.chunk_recs;
+    int64_t c1 = c0 + A.chunk_recs;
+    c1 = c1 < a.n ? c1 : a.n;
+    const cfloat_ptr base = as_const(a.data);
+#pragma unroll 1
+    for (int64_t g0 = c0; g0 < c1; g0 += G) {
+        float v[G * S];
+        load_group<D>(base + g0 * S, v);
+        float u[G][R], l[G][R];
+        bool need = false;
+#pragma unroll
+        for (int c = 0; c < G; ++c) {
+            float xk[D];
+#pragma unroll
+            for (int j = 0; j < D; ++j) xk[j] = v[c * S + j];
+            const bool in = g0 + c < c1;  // wave-uniform
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                pair_bounds<D, DM, NORM>(qv[r], qm[r], xk, v[c * S + Rec<D>::Y],
+                                         v[c * S + Rec<D>::M], v[c * S + Rec<D>::YU], big,
+                                         u[c][r], l[c][r]);
+                if (!in) {
+                    u[c][r] = __builtin_inff();
+                    l[c][r] = -__builtin_inff();
+                }
+                need = need || u[c][r] < U[r][kTopK - 1] || l[c][r] > L[r][kTopK - 1];
+            }
+        }
+        if (__builtin_amdgcn_ballot_w64(need) != 0) {
+#pragma unroll
+            for (int c = 0; c < G; ++c)
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    topk_insert_up(U[r], u[c][r]);
+                    topk_insert_lo(L[r], l[c][r]);
+                }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t qi = q0 + r * 64 + lane;
+        if (qi >= a.q) continue;
+        if (a.n_chunks == 1) {
+            float hu = 0.0f, hl = 0.0f;
+#pragma unroll
+            for (int j = 0; j < kTopK; ++j) {
+                if (j < A.k) {
+                    hu = fmaf(A.wk[j], U[r][j], hu);
+                    hl = fmaf(A.wk[j], L[r][j], hl);
+                }
+            }
+            if (a.g) a.g[qi] = 0.5f * (hu + hl);
+            if (a.h_up) a.h_up[qi] = hu;
+            if (a.h_lo) a.h_lo[qi] = hl;
+        } else {
+            float *pu = A.part + (((int64_t)chunk * a.q + qi) * kTopK);
+            float *pl = A.part + ((((int64_t)a.n_chunks + chunk) * a.q + qi) * kTopK);
+#pragma unroll
+            for (int j = 0; j < kTopK; ++j) {
+                pu[j] = U[r][j];
+                pl[j] = L[r][j];
+            }
+        }
+    }
+}
+
+typedef void (*TopkLaunch)(const TopkArgs &, dim3, dim3, hipStream_t);
+
+template <int NORM, int D, int DM>
+void launch_topk(const TopkArgs &a, dim3 g, dim3 b, hipStream_t s)
+{
+    hipLaunchKernelGGL((bounds_topk_kernel<D, DM, NORM>), g, b, 0, s, a);
+}
+
+template <int NORM, int D, int... DMs>
+constexpr std::array<TopkLaunch, D + 1> topk_row(std::integer_sequence<int, DMs...>)
+{
+    return {{&launch_topk<NORM, D, DMs>...}};
+}
+
+template <int NORM>
+TopkLaunch topk_table(int d, int dm)
+{
+    if (dm < 0 || dm > d) return nullptr;
+    switch (d) {
+#define LIP_TK_CASE(DD)                                                                    \
+    case DD: {                                                                             \
+        constexpr auto row = topk_row<NORM, DD>(std::make_integer_sequence<int, DD + 1>{}); \
+        return row[dm];                                                                    \
+    }
+        LIP_TK_CASE(1) LIP_TK_CASE(2) LIP_TK_CASE(3) LIP_TK_CASE(4)
+        LIP_TK_CASE(5) LIP_TK_CASE(6) LIP_TK_CASE(7) LIP_TK_CASE(8)
+        LIP_TK_CASE(9) LIP_TK_CASE(10) LIP_TK_CASE(11) LIP_TK_CASE(12)
+        LIP_TK_CASE(13) LIP_TK_CASE(14) LIP_TK_CASE(15) LIP_TK_CASE(16)
+#undef LIP_TK_CASE
+    default: return nullptr;
+    }
+}
+
+TopkLaunch topk_l1(int d, int dm);
+TopkLaunch topk_l2(int d, int dm);
+TopkLaunch topk_linf(int d, int dm);
+
+}  // namespace lip

@@ -1,0 +1,9 @@
+// Instantiation unit of the k-best bound kernel for one norm (all d and
+// monotone counts).
+#include "bounds_topk.hpp"
+
+namespace lip {
+
+TopkLaunch topk_l1(int d, int dm) { return topk_table<1>(d, dm); }
+
+}  // namespace lip

@@ -69,6 +69,7 @@ size_t data_side_ws_bytes(int64_t n, int d);
 size_t backward_ws_bytes(int64_t n);
 size_t local_ws_bytes(int64_t n, int64_t q, int d);
 size_t smooth_ws_bytes(int64_t n, int d);
+size_t topk_ws_bytes(int64_t n, int64_t q, int d);
 
 lip_status check_finite(const float *const *arrays, const int64_t *counts, int n_arrays,
                         void *ws, hipStream_t stream);

@@ -242,7 +242,9 @@ size_t lip_workspace_size(int64_t n, int64_t q, int32_t d, uint32_t flags)
     const size_t bwd = backward_ws_bytes(n);
     const size_t loc = local_ws_bytes(n, q, d);
     const size_t sm = smooth_ws_bytes(n, d);
+    const size_t tk = topk_ws_bytes(n, q, d);
     if (sm > m) m = sm;
+    if (tk > m) m = tk;
     if (ds > m) m = ds;
     if (bwd > m) m = bwd;
     if (loc > m) m = loc;

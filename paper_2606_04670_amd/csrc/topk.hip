@@ -1,0 +1,134 @@
+// Host entry point of the k-best weighted bounds (lip_fit_eval_k) and the
+// merge of split partial lists; the kernel is in bounds_topk.hpp,
+// instantiated per norm in bounds_topk_{l1,l2,linf}.hip.
+#include "bounds_topk.hpp"
+#include "host_common.hpp"
+
+namespace lip {
+
+namespace {
+
+// Merge of the chunks' sorted lists: the kTopK smallest upper and largest
+// lower values over all chunks, then the weighted sums.
+__global__ void topk_merge_kernel(TopkArgs A)
+{
+    const FwdArgs &a = A.f;
+    const int64_t qi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (qi >= a.q) return;
+    float U[kTopK], L[kTopK];
+    for (int j = 0; j < kTopK; ++j) {
+        U[j] = __builtin_inff();
+        L[j] = -__builtin_inff();
+    }
+    for (int c = 0; c < a.n_chunks; ++c) {
+        const float *pu = A.part + (((int64_t)c * a.q + qi) * kTopK);
+        const float *pl = A.part + ((((int64_t)a.n_chunks + c) * a.q + qi) * kTopK);
+        for (int j = 0; j < kTopK; ++j) {
+            topk_insert_up(U, pu[j]);
+            topk_insert_lo(L, pl[j]);
+        }
+    }
+    float hu = 0.0f, hl = 0.0f;
+    for (int j = 0; j < A.k; ++j) {
+        hu = fmaf(A.wk[j], U[j], hu);
+        hl = fmaf(A.wk[j], L[j], hl);
+    }
+    if (a.g) a.g[qi] = 0.5f * (hu + hl);
+    if (a.h_up) a.h_up[qi] = hu;
+    if (a.h_lo) a.h_lo[qi] = hl;
+}
+
+TopkLaunch get_topk(int norm, int d, int dm)
+{
+    switch (norm) {
+    case LIP_L1: return topk_l1(d, dm);
+    case LIP_L2: return topk_l2(d, dm);
+    case LIP_LINF: return topk_linf(d, dm);
+    default: return nullptr;
+    }
+}
+
+constexpr int kTopkMaxChunks = 16;
+
+}  // namespace
+
+size_t topk_ws_bytes(int64_t n, int64_t q, int d)
+{
+    return staged_bytes(n, d) + align_up((size_t)2 * kTopkMaxChunks * (size_t)q * kTopK * 4, 256) +
+           256;
+}
+
+}  // namespace lip
+
+using namespace lip;
+
+extern "C" lip_status lip_fit_eval_k(const lip_metric *metric, const float *x, const float *y,
+                                     int64_t n, float M, const float *Mk, int32_t k,
+                                     const float *wk, const float *xq, int64_t q, float *g,
+                                     float *h_up, float *h_lo, void *ws, size_t ws_bytes,
+                                     uint32_t flags, lip_stream stream)
+{
+    MetricInfo mi;
+    lip_status st = parse_metric(metric, &mi);
+    if (st != LIP_OK) return st;
+    if (flags & LIP_FLAG_BF16) return LIP_E_UNSUPPORTED;
+    if (flags & ~LIP_FLAG_CHECK_FINITE) return LIP_E_ARG;
+    if (n <= 0 || q < 0 || n > kMaxIndex - kMaxTile || q > kMaxIndex) return LIP_E_SHAPE;
+    if (k < 1 || k > kTopK || k > n) return LIP_E_SHAPE;
+    if (!x || !y || !wk || (q > 0 && !xq)) return LIP_E_ARG;
+    if (!Mk && (!(M >= 0.0f) || !__builtin_isfinite(M))) return LIP_E_VALUE;
+    for (int j = 0; j < k; ++j)
+        if (!(wk[j] >= 0.0f) || !__builtin_isfinite(wk[j])) return LIP_E_VALUE;
+    if (!ws || ws_bytes < topk_ws_bytes(n, q, mi.d)) return LIP_E_WORKSPACE;
+    if (q == 0) return LIP_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if (flags & LIP_FLAG_CHECK_FINITE) {
+        const float *arr[4] = {x, y, Mk, xq};
+        const int64_t cnt[4] = {n * mi.d, n, Mk ? n : 0, q * mi.d};
+        st = check_finite(arr, cnt, 4, ws, s);
+        if (st != LIP_OK) return st;
+    }
+    TopkLaunch launch = get_topk(mi.norm, mi.d, mi.dm);
+    if (!launch) return LIP_E_UNSUPPORTED;
+    const int64_t n_pad = (n + 7) / 8 * 8;
+    float *staged = (float *)ws;
+    StageArgs sa{};
+    sa.x = x;
+    sa.y = y;
+    sa.Mk = Mk;
+    sa.M = M;
+    sa.l1_mon = mi.norm == LIP_L1 ? mi.dm : 0;
+    sa.n = n;
+    sa.n_pad = n_pad;
+    sa.xf = mi.xf;
+    sa.out = staged;
+    if (launch_stage(mi.d, sa, s) != hipSuccess) return LIP_E_DEVICE;
+    TopkArgs A{};
+    A.f.data = staged;
+    A.f.n = n;
+    A.f.xq = xq;
+    A.f.q = q;
+    A.f.xf = mi.xf;
+    A.f.g = g;
+    A.f.h_up = h_up;
+    A.f.h_lo = h_lo;
+    A.k = k;
+    for (int j = 0; j < kTopK; ++j) A.wk[j] = j < k ? wk[j] : 0.0f;
+    // data split when the queries alone do not fill the chip
+    const int R = rows_for_dim(mi.d);
+    const int64_t qwaves = (q + 64 * R - 1) / (64 * R);
+    int nc = 1;
+    while (nc < kTopkMaxChunks && qwaves * nc < 16384 && n >= (int64_t)nc * 2 * 64) nc *= 2;
+    int64_t recs = (n + nc - 1) / nc;
+    recs = (recs + 7) / 8 * 8;
+    A.chunk_recs = recs;
+    A.f.n_chunks = (int)((n + recs - 1) / recs);
+    A.part = (float *)((char *)ws + staged_bytes(n, mi.d));
+    const unsigned grid = (unsigned)(((qwaves + 3) / 4) * A.f.n_chunks);
+    launch(A, dim3(grid), dim3(256), s);
+    if (hipGetLastError() != hipSuccess) return LIP_E_DEVICE;
+    if (A.f.n_chunks > 1)
+        hipLaunchKernelGGL(topk_merge_kernel, dim3((unsigned)((q + 255) / 256)), dim3(256), 0, s,
+                           A);
+    return dev_status(hipGetLastError());
+}

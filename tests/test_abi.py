@@ -227,3 +227,22 @@ def test_smooth_entry_point_validation(L):
     assert sm(eps=None) == L.LIP_E_ARG
     assert sm(ws_bytes=16) == L.LIP_E_WORKSPACE
     assert sm(flags=L.LIP_FLAG_BF16) == L.LIP_E_ARG
+
+
+def test_fit_eval_k_validation(L):
+    lib = L.load()
+    m, keep = _metric(L)
+    wk = np.array([0.5, 0.5], np.float32)
+    neg = np.array([0.5, -0.5], np.float32)
+    pp = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+
+    def ev(n=10, k=2, w=wk, q=5, flags=0, ws_bytes=1 << 30):
+        return lib.lip_fit_eval_k(ctypes.byref(m), FAKE, FAKE, n, 1.0, None, k, pp(w), FAKE, q,
+                                  FAKE, None, None, FAKE, ws_bytes, flags, None)
+    assert ev(k=0) == L.LIP_E_SHAPE
+    assert ev(k=5) == L.LIP_E_SHAPE
+    assert ev(n=1, k=2) == L.LIP_E_SHAPE
+    assert ev(w=neg) == L.LIP_E_VALUE
+    assert ev(flags=L.LIP_FLAG_BF16) == L.LIP_E_UNSUPPORTED
+    assert ev(ws_bytes=16) == L.LIP_E_WORKSPACE
+    assert ev(q=0) == L.LIP_OK
