@@ -16,6 +16,7 @@ OpenMP over queries/rows), written from the paper's definitions:
                             per-datum tables, bounds with M_k(dist)
   * smoothing penalty:      Sec. 4.4, Eq. (7) and its gradient
   * k best bounds:          Sec. 5 (k > 1 with weights)
+  * regional monotonicity:  Sec. 4.2 (cases I-IV on [a_i, b_i])
 This module only marshals numpy arrays into that library.
 """
 from __future__ import annotations
@@ -85,6 +86,11 @@ def _load():
         lib.orc_smooth_scale.restype = None
         lib.orc_bounds_k.argtypes = [i32, i32, P, P, P, P, i64, f64, P, i32, P, P, i64, P, P, P]
         lib.orc_bounds_k.restype = None
+        lib.orc_bounds_reg.argtypes = [i32, i32, P, P, P, P, P, P, i64, f64, P, P, i64, P, P, P,
+                                       P, P]
+        lib.orc_bounds_reg.restype = None
+        lib.orc_candidates_reg.argtypes = [i32, i32, P, P, P, P, P, P, i64, f64, P, P, P, P]
+        lib.orc_candidates_reg.restype = None
         _lib = lib
     return _lib
 
@@ -298,6 +304,43 @@ def bounds_k(x, y, xq, norm: int, wk, M: float = 0.0, Mk=None, mon=None, w=None)
     _load().orc_bounds_k(d, norm, _p(w), _p(mon), _p(x), _p(y), x.shape[0], float(M), _p(Mk),
                          wk.shape[0], _p(wk), _p(xq), q, _p(hu), _p(hl), _p(g))
     return hu, hl, g
+
+
+def _reg(kind, a, b, d):
+    kind = np.ascontiguousarray(kind, np.int8)
+    a = np.zeros(d) if a is None else np.ascontiguousarray(a, np.float64)
+    b = np.zeros(d) if b is None else np.ascontiguousarray(b, np.float64)
+    assert kind.shape == a.shape == b.shape == (d,)
+    return kind, a, b
+
+
+def bounds_reg(x, y, xq, norm: int, kind, a=None, b=None, M: float = 0.0, Mk=None, w=None):
+    """H_up, H_lo, g, arg_up, arg_lo with monotonicity on parts of the domain:
+    kind per coordinate 0 / +1 / -1 / 2..5 (cases I..IV on [a_i, b_i])."""
+    d = int(np.shape(x)[1])
+    x, y, w, _ = _common(x, y, w, None, d)
+    kind, a, b = _reg(kind, a, b, d)
+    xq = _f32(xq).reshape(-1, d)
+    Mk = None if Mk is None else _f32(Mk)
+    q = xq.shape[0]
+    hu, hl, g = (np.empty(q, np.float64) for _ in range(3))
+    au, al = np.empty(q, np.int64), np.empty(q, np.int64)
+    _load().orc_bounds_reg(d, norm, _p(w), _p(kind), _p(a), _p(b), _p(x), _p(y), x.shape[0],
+                           float(M), _p(Mk), _p(xq), q, _p(hu), _p(hl), _p(g), _p(au), _p(al))
+    return hu, hl, g, au, al
+
+
+def candidates_reg(x, y, xq1, norm: int, kind, a=None, b=None, M: float = 0.0, Mk=None, w=None):
+    d = int(np.shape(x)[1])
+    x, y, w, _ = _common(x, y, w, None, d)
+    kind, a, b = _reg(kind, a, b, d)
+    q1 = _f32(xq1).reshape(d)
+    Mk = None if Mk is None else _f32(Mk)
+    n = x.shape[0]
+    u, l = np.empty(n, np.float64), np.empty(n, np.float64)
+    _load().orc_candidates_reg(d, norm, _p(w), _p(kind), _p(a), _p(b), _p(x), _p(y), n,
+                               float(M), _p(Mk), _p(q1), _p(u), _p(l))
+    return u, l
 
 
 def round_up_f32(v) -> np.ndarray:

@@ -692,3 +692,131 @@ void orc_bounds_k(int d, int norm, const double *w, const signed char *mon, cons
         free(l);
     }
 }
+
+/* ---- monotonicity on parts of the domain (Sec. 4.2) -------------------------
+ *
+ * Per coordinate i a kind: 0 free, +1 / -1 increasing / decreasing everywhere,
+ * and on the partition A: x_i <= a_i, AB: a_i <= x_i <= b_i, B: x_i >= b_i
+ *   2 (case I)   increasing on A and B, unrestricted on AB,
+ *   3 (case II)  decreasing on A and B, unrestricted on AB,
+ *   4 (case III) decreasing on A, increasing on B, unrestricted on AB,
+ *   5 (case IV)  increasing on A, decreasing on B, unrestricted on AB.
+ * Reading (the section's formulas are not given): going from x^k to x along
+ * coordinate i, f can rise only where it is not decreasing (moving right) or
+ * not increasing (moving left), by at most M per unit length, and elsewhere
+ * it cannot rise.  So the component of the upper distance is the length of
+ * the part of the segment between x^k_i and x_i where f may rise in the
+ * direction of travel, and that of the lower distance the length where it
+ * may fall; with the regions "not decreasing" ND and "not increasing" NI:
+ *     x_i >= x^k_i:  c_up = |seg ∩ ND|,  c_lo = |seg ∩ NI|
+ *     x_i <  x^k_i:  c_up = |seg ∩ NI|,  c_lo = |seg ∩ ND|
+ * For +1 (ND = everything, NI = nothing) these are (x_i - x^k_i)_+ and
+ * (x^k_i - x_i)_+, Eq. (4) and its mirror.  The components are weighted and
+ * combined by the norm as before. */
+
+/* length of [lo, hi] ∩ [s, t] */
+static double overlap(double lo, double hi, double s, double t)
+{
+    double a = lo > s ? lo : s;
+    double b = hi < t ? hi : t;
+    return b > a ? b - a : 0.0;
+}
+
+static void regions(int kind, double a, double b, double *nd_s, double *nd_t, double *ni_s,
+                    double *ni_t)
+{
+    const double inf = INFINITY;
+    double s1 = -inf, t1 = inf, s2 = -inf, t2 = inf; /* ND, NI: everything */
+    switch (kind) {
+    case 1: s2 = inf; t2 = -inf; break;                 /* NI empty */
+    case -1: s1 = inf; t1 = -inf; break;                /* ND empty */
+    case 2: s2 = a; t2 = b; break;                      /* NI = AB */
+    case 3: s1 = a; t1 = b; break;                      /* ND = AB */
+    case 4: s1 = a; t1 = inf; s2 = -inf; t2 = b; break; /* ND = AB u B, NI = A u AB */
+    case 5: s1 = -inf; t1 = b; s2 = a; t2 = inf; break; /* ND = A u AB, NI = AB u B */
+    default: break;                                     /* free */
+    }
+    *nd_s = s1;
+    *nd_t = t1;
+    *ni_s = s2;
+    *ni_t = t2;
+}
+
+static void dist_pair_reg(int d, int norm, const double *w, const signed char *kind,
+                          const double *ra, const double *rb, const float *x, const float *xk,
+                          double *dup, double *dlo)
+{
+    double su = 0.0, sl = 0.0;
+    for (int i = 0; i < d; ++i) {
+        double xi = (double)x[i], ki = (double)xk[i];
+        double nds, ndt, nis, nit;
+        regions(kind ? kind[i] : 0, ra ? ra[i] : 0.0, rb ? rb[i] : 0.0, &nds, &ndt, &nis, &nit);
+        double cu, cl;
+        if (xi >= ki) {
+            cu = overlap(ki, xi, nds, ndt);
+            cl = overlap(ki, xi, nis, nit);
+        } else {
+            cu = overlap(xi, ki, nis, nit);
+            cl = overlap(xi, ki, nds, ndt);
+        }
+        cu = w[i] * cu;
+        cl = w[i] * cl;
+        if (norm == ORC_L1) {
+            su = su + cu;
+            sl = sl + cl;
+        } else if (norm == ORC_L2) {
+            su = su + cu * cu;
+            sl = sl + cl * cl;
+        } else {
+            if (cu > su) su = cu;
+            if (cl > sl) sl = cl;
+        }
+    }
+    if (norm == ORC_L2) {
+        su = sqrt(su);
+        sl = sqrt(sl);
+    }
+    *dup = su;
+    *dlo = sl;
+}
+
+/* Eq. (2)-(3) with the regional components above; lowest index on ties. */
+void orc_bounds_reg(int d, int norm, const double *w, const signed char *kind, const double *ra,
+                    const double *rb, const float *x, const float *y, long n, double M,
+                    const float *Mk, const float *xq, long q, double *h_up, double *h_lo,
+                    double *g, long *arg_up, long *arg_lo)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long j = 0; j < q; ++j) {
+        const float *xj = xq + j * (long)d;
+        double best_u = INFINITY, best_l = -INFINITY;
+        long au = -1, al = -1;
+        for (long k = 0; k < n; ++k) {
+            double du, dl;
+            dist_pair_reg(d, norm, w, kind, ra, rb, xj, x + k * (long)d, &du, &dl);
+            double mk = m_of(Mk, M, k);
+            double u = (double)y[k] + mk * du;
+            double l = (double)y[k] - mk * dl;
+            if (u < best_u) { best_u = u; au = k; }
+            if (l > best_l) { best_l = l; al = k; }
+        }
+        if (h_up) h_up[j] = best_u;
+        if (h_lo) h_lo[j] = best_l;
+        if (g) g[j] = 0.5 * (best_u + best_l);
+        if (arg_up) arg_up[j] = au;
+        if (arg_lo) arg_lo[j] = al;
+    }
+}
+
+void orc_candidates_reg(int d, int norm, const double *w, const signed char *kind,
+                        const double *ra, const double *rb, const float *x, const float *y, long n,
+                        double M, const float *Mk, const float *xq1, double *u, double *l)
+{
+    for (long k = 0; k < n; ++k) {
+        double du, dl;
+        dist_pair_reg(d, norm, w, kind, ra, rb, xq1, x + k * (long)d, &du, &dl);
+        double mk = m_of(Mk, M, k);
+        u[k] = (double)y[k] + mk * du;
+        l[k] = (double)y[k] - mk * dl;
+    }
+}
