@@ -48,7 +48,7 @@ typedef enum {
     LIP_OK = 0,
     LIP_E_ARG = 1,          /* NULL where required, bad enum, bad flag combination */
     LIP_E_SHAPE = 2,        /* n == 0, d outside 1..LIP_MAX_DIM, sizes too large */
-    LIP_E_VALUE = 3,        /* M < 0, weight <= 0, mon outside {-1,0,1}, tol < 0 */
+    LIP_E_VALUE = 3,        /* M < 0, weight <= 0, unknown mon kind, a_i > b_i, tol < 0 */
     LIP_E_NONFINITE = 4,    /* NaN/Inf found by LIP_FLAG_CHECK_FINITE */
     LIP_E_UNSUPPORTED = 5,  /* e.g. LIP_FLAG_BF16 with l1/linf or monotone coordinates */
     LIP_E_WORKSPACE = 6,    /* ws is NULL or smaller than lip_workspace_size() */
@@ -71,12 +71,36 @@ typedef enum { LIP_L1 = 1, LIP_L2 = 2, LIP_LINF = 3 } lip_norm;
  * calls give bitwise identical results. */
 #define LIP_FLAG_DETERMINISTIC (1u << 2)
 
-/* Distance definition (Sec. 3 "other distances", Sec. 4.1 monotonicity). */
+/* Monotonicity on parts of the domain (Sec. 4.2): with A: x_i <= a_i,
+ * AB: a_i <= x_i <= b_i, B: x_i >= b_i, a coordinate of kind
+ *   LIP_MON_CASE_I    is increasing on A and B, unrestricted on AB,
+ *   LIP_MON_CASE_II   is decreasing on A and B, unrestricted on AB,
+ *   LIP_MON_CASE_III  is decreasing on A, increasing on B, unrestricted on AB,
+ *   LIP_MON_CASE_IV   is increasing on A, decreasing on B, unrestricted on AB.
+ * Its distance components are the lengths of the part of the segment between
+ * x^k_i and x_i on which f may rise (upper distance) or fall (lower distance)
+ * in the direction of travel: moving towards larger x_i it may rise where it
+ * is not decreasing and fall where it is not increasing, and the reverse
+ * moving towards smaller x_i.  (Kinds +1 / -1 are the same rule with one
+ * region covering everything: Eq. 4 and its mirror.)  Only lip_bounds and
+ * lip_fit_eval accept these kinds; the other entry points return
+ * LIP_E_UNSUPPORTED for them. */
+#define LIP_MON_CASE_I   2
+#define LIP_MON_CASE_II  3
+#define LIP_MON_CASE_III 4
+#define LIP_MON_CASE_IV  5
+
+/* Distance definition (Sec. 3 "other distances", Sec. 4.1 monotonicity,
+ * Sec. 4.2 monotonicity on parts of the domain). */
 typedef struct {
     int32_t d;            /* dimension, 1..LIP_MAX_DIM */
     int32_t norm;         /* lip_norm */
     const float *w;       /* HOST [d] weights > 0, or NULL for all ones */
-    const int8_t *mon;    /* HOST [d] in {-1, 0, +1}, or NULL for no constraints */
+    const int8_t *mon;    /* HOST [d] in {-1, 0, +1} or LIP_MON_CASE_I..IV, or NULL for no
+                             constraints */
+    const float *a;       /* HOST [d] interval starts a_i (finite, used by the CASE kinds), or
+                             NULL when no coordinate has such a kind */
+    const float *b;       /* HOST [d] interval ends b_i >= a_i (finite), or NULL likewise */
 } lip_metric;
 
 typedef void *lip_stream; /* hipStream_t */

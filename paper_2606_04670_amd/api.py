@@ -40,21 +40,27 @@ def _stream(device: torch.device):
 
 
 class Metric:
-    """Distance definition: dimension, norm, weights and monotonicity (host)."""
+    """Distance definition: dimension, norm, weights and monotonicity (host).
+
+    mon per coordinate: 0 free, +1 / -1 increasing / decreasing (Sec. 4.1),
+    or 2..5 for cases I..IV of Sec. 4.2 on [a_i, b_i] (a, b given then)."""
 
     def __init__(self, d: int, norm="l2", mon: Optional[Sequence[int]] = None,
-                 w: Optional[Sequence[float]] = None):
+                 w: Optional[Sequence[float]] = None, a: Optional[Sequence[float]] = None,
+                 b: Optional[Sequence[float]] = None):
         self.d = int(d)
         self.norm = NORMS[norm]
         self.mon = None if mon is None else np.ascontiguousarray(np.asarray(mon, np.int8))
         self.w = None if w is None else np.ascontiguousarray(np.asarray(w, np.float32))
-        if self.mon is not None and self.mon.shape != (self.d,):
-            raise ValueError("mon must have d entries")
-        if self.w is not None and self.w.shape != (self.d,):
-            raise ValueError("w must have d entries")
-        self._c = L.LipMetric(self.d, self.norm,
-                              None if self.w is None else self.w.ctypes.data_as(ctypes.c_void_p),
-                              None if self.mon is None else self.mon.ctypes.data_as(ctypes.c_void_p))
+        self.a = None if a is None else np.ascontiguousarray(np.asarray(a, np.float32))
+        self.b = None if b is None else np.ascontiguousarray(np.asarray(b, np.float32))
+        for nm in ("mon", "w", "a", "b"):
+            v = getattr(self, nm)
+            if v is not None and v.shape != (self.d,):
+                raise ValueError(f"{nm} must have d entries")
+        ptr = lambda v: None if v is None else v.ctypes.data_as(ctypes.c_void_p)
+        self._c = L.LipMetric(self.d, self.norm, ptr(self.w), ptr(self.mon), ptr(self.a),
+                              ptr(self.b))
 
     @property
     def n_mon(self) -> int:

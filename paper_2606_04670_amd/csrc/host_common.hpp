@@ -27,9 +27,16 @@ struct MetricInfo {
     Xform xf{};          // free coordinates first, then monotone ones
     double w[kMaxDim];   // weights (for the FP64 passes)
     int8_t mon[kMaxDim]; // original monotonicity (for the FP64 passes)
+    // monotonicity on parts of the domain (some kind is a LIP_MON_CASE_*):
+    // per coordinate the intervals where f is not decreasing (nd) and not
+    // increasing (ni), [s, t] with infinite ends allowed, empty as [+inf, -inf]
+    bool regional = false;
+    float nd_s[kMaxDim], nd_t[kMaxDim], ni_s[kMaxDim], ni_t[kMaxDim];
 };
 
-lip_status parse_metric(const lip_metric *m, MetricInfo *out);
+// Validates the metric; the LIP_MON_CASE_* kinds are accepted only with
+// allow_regional (else LIP_E_UNSUPPORTED).
+lip_status parse_metric(const lip_metric *m, MetricInfo *out, bool allow_regional = false);
 
 // Resolved tiling for one bound-kernel launch.
 struct FwdPlan {
@@ -70,6 +77,13 @@ size_t backward_ws_bytes(int64_t n);
 size_t local_ws_bytes(int64_t n, int64_t q, int d);
 size_t smooth_ws_bytes(int64_t n, int d);
 size_t topk_ws_bytes(int64_t n, int64_t q, int d);
+size_t reg_ws_bytes(int64_t n, int64_t q, int d);
+
+// Bound path with monotonicity on parts of the domain (bounds_reg.hip).
+lip_status run_bounds_reg(const MetricInfo &mi, const float *x, const float *y, int64_t n,
+                          float M, const float *Mk, const float *xq, int64_t q, float *g,
+                          float *h_up, float *h_lo, int32_t *arg_up, int32_t *arg_lo, void *ws,
+                          size_t ws_bytes, hipStream_t stream);
 
 lip_status check_finite(const float *const *arrays, const int64_t *counts, int n_arrays,
                         void *ws, hipStream_t stream);

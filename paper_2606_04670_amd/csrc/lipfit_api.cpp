@@ -11,7 +11,7 @@
 
 namespace lip {
 
-lip_status parse_metric(const lip_metric *m, MetricInfo *out)
+lip_status parse_metric(const lip_metric *m, MetricInfo *out, bool allow_regional)
 {
     if (!m) return LIP_E_ARG;
     if (m->d < 1 || m->d > kMaxDim) return LIP_E_SHAPE;
@@ -19,13 +19,46 @@ lip_status parse_metric(const lip_metric *m, MetricInfo *out)
     MetricInfo mi;
     mi.d = m->d;
     mi.norm = m->norm;
+    const float inf = __builtin_inff();
     for (int i = 0; i < m->d; ++i) {
         const float w = m->w ? m->w[i] : 1.0f;
         if (!(w > 0.0f) || !__builtin_isfinite(w)) return LIP_E_VALUE;
         const int8_t mo = m->mon ? m->mon[i] : 0;
-        if (mo < -1 || mo > 1) return LIP_E_VALUE;
+        if (mo < -1 || mo > LIP_MON_CASE_IV) return LIP_E_VALUE;
         mi.w[i] = (double)w;
-        mi.mon[i] = mo;
+        // regions where f is not decreasing / not increasing
+        float nds = -inf, ndt = inf, nis = -inf, nit = inf;
+        if (mo == 1) {
+            nis = inf;
+            nit = -inf;
+        } else if (mo == -1) {
+            nds = inf;
+            ndt = -inf;
+        } else if (mo >= LIP_MON_CASE_I) {
+            if (!allow_regional) return LIP_E_UNSUPPORTED;
+            if (!m->a || !m->b) return LIP_E_ARG;
+            const float a = m->a[i], b = m->b[i];
+            if (!__builtin_isfinite(a) || !__builtin_isfinite(b) || !(a <= b)) return LIP_E_VALUE;
+            mi.regional = true;
+            if (mo == LIP_MON_CASE_I) {
+                nis = a;
+                nit = b;
+            } else if (mo == LIP_MON_CASE_II) {
+                nds = a;
+                ndt = b;
+            } else if (mo == LIP_MON_CASE_III) {
+                nds = a;
+                nit = b;
+            } else {
+                ndt = b;
+                nis = a;
+            }
+        }
+        mi.nd_s[i] = nds;
+        mi.nd_t[i] = ndt;
+        mi.ni_s[i] = nis;
+        mi.ni_t[i] = nit;
+        mi.mon[i] = mo >= LIP_MON_CASE_I ? 0 : mo;
     }
     int k = 0;
     for (int i = 0; i < m->d; ++i) {
@@ -212,9 +245,10 @@ static lip_status validate_bounds(const lip_metric *metric, const float *x, cons
                                   int64_t n, float M, const float *Mk, const float *xq, int64_t q,
                                   uint32_t flags, MetricInfo *mi)
 {
-    lip_status st = parse_metric(metric, mi);
+    lip_status st = parse_metric(metric, mi, true);
     if (st != LIP_OK) return st;
     if (flags & ~(LIP_FLAG_CHECK_FINITE | LIP_FLAG_BF16)) return LIP_E_ARG;
+    if ((flags & LIP_FLAG_BF16) && mi->regional) return LIP_E_UNSUPPORTED;
     if (n <= 0 || q < 0) return LIP_E_SHAPE;
     if (n > kMaxIndex - kMaxTile || q > kMaxIndex) return LIP_E_SHAPE;
     if (!x || !y || (q > 0 && !xq)) return LIP_E_ARG;
@@ -243,6 +277,8 @@ size_t lip_workspace_size(int64_t n, int64_t q, int32_t d, uint32_t flags)
     const size_t loc = local_ws_bytes(n, q, d);
     const size_t sm = smooth_ws_bytes(n, d);
     const size_t tk = topk_ws_bytes(n, q, d);
+    const size_t rg = reg_ws_bytes(n, q, d);
+    if (rg > m) m = rg;
     if (sm > m) m = sm;
     if (tk > m) m = tk;
     if (ds > m) m = ds;
@@ -268,6 +304,9 @@ lip_status lip_fit_eval(const lip_metric *metric, const float *x, const float *y
         st = check_finite(arr, cnt, 4, ws, s);
         if (st != LIP_OK) return st;
     }
+    if (mi.regional)
+        return run_bounds_reg(mi, x, y, n, M, Mk, xq, q, g, h_up, h_lo, arg_up, arg_lo, ws,
+                              ws_bytes, s);
     const lip_tile_cfg cfg = tune_lookup(mi.d, mi.dm, mi.norm, n, q);
     if (flags & LIP_FLAG_BF16) {
         return run_bounds_bf16(mi, x, y, n, M, Mk, xq, q, g, h_up, h_lo, arg_up, arg_lo, ws,

@@ -63,6 +63,15 @@ def check_bounds_steps(p, gpu: dict, knots, d1, V32, qidx=None, label=""):
     return _compare(p, gpu, qidx, orc, cand, tau_for(p, np.asarray(V32).reshape(-1)), label)
 
 
+def check_bounds_regional(p, gpu: dict, kind, a, b, qidx=None, label=""):
+    """As check_bounds, for monotonicity on parts of the domain."""
+    qidx = np.arange(p.q) if qidx is None else np.asarray(qidx)
+    orc = oracle.bounds_reg(p.x, p.y, p.xq[qidx], p.norm, kind, a, b, M=p.M, Mk=p.Mk, w=p.w)
+    cand = lambda xq1: oracle.candidates_reg(p.x, p.y, xq1, p.norm, kind, a, b, M=p.M, Mk=p.Mk,
+                                             w=p.w)
+    return _compare(p, gpu, qidx, orc, cand, tau_for(p, p.Mk), label)
+
+
 def _compare(p, gpu, qidx, orc, cand, tau, label):
     hu, hl, g, au, al = orc
     xq = p.xq[qidx]

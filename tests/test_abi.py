@@ -93,8 +93,10 @@ def test_fit_eval_validation(L):
     assert _eval(L, bad_norm) == L.LIP_E_ARG
     bad_w, k4 = _metric(L, w=[1.0, 0.0, 1.0])
     assert _eval(L, bad_w) == L.LIP_E_VALUE
-    bad_mon, k5 = _metric(L, mon=[0, 2, 0])
+    bad_mon, k5 = _metric(L, mon=[0, 7, 0])
     assert _eval(L, bad_mon) == L.LIP_E_VALUE
+    case_no_ab, k5b = _metric(L, mon=[0, 2, 0])  # a case of Sec. 4.2 needs a and b
+    assert _eval(L, case_no_ab) == L.LIP_E_ARG
     # BF16 path: l2 without monotone coordinates only
     l1, k6 = _metric(L, norm=1)
     assert _eval(L, l1, flags=L.LIP_FLAG_BF16) == L.LIP_E_UNSUPPORTED
@@ -246,3 +248,27 @@ def test_fit_eval_k_validation(L):
     assert ev(flags=L.LIP_FLAG_BF16) == L.LIP_E_UNSUPPORTED
     assert ev(ws_bytes=16) == L.LIP_E_WORKSPACE
     assert ev(q=0) == L.LIP_OK
+
+
+def test_regional_metric_validation(L):
+    lib = L.load()
+    kind = np.array([2, 0, 5], np.int8)
+    a = np.array([0.1, 0.0, 0.2], np.float32)
+    b = np.array([0.5, 0.0, 0.1], np.float32)   # b < a in coordinate 2
+    good_b = np.array([0.5, 0.0, 0.3], np.float32)
+    pp = lambda v: v.ctypes.data_as(ctypes.c_void_p)
+    m_bad = L.LipMetric(3, 2, None, pp(kind), pp(a), pp(b))
+    m_noab = L.LipMetric(3, 2, None, pp(kind), None, None)
+    m_ok = L.LipMetric(3, 2, None, pp(kind), pp(a), pp(good_b))
+
+    def ev(m, q=0):
+        return lib.lip_fit_eval(ctypes.byref(m), FAKE, FAKE, 10, 1.0, None, FAKE, q, FAKE, None,
+                                None, None, None, FAKE, 1 << 30, 0, None)
+    assert ev(m_bad) == L.LIP_E_VALUE
+    assert ev(m_noab) == L.LIP_E_ARG
+    assert ev(m_ok) == L.LIP_OK  # q = 0: validated, no device work
+    bad_kind = np.array([6, 0, 0], np.int8)
+    assert ev(L.LipMetric(3, 2, None, pp(bad_kind), pp(a), pp(good_b))) == L.LIP_E_VALUE
+    # the other entry points do not take the regional kinds
+    assert lib.lip_consistency(ctypes.byref(m_ok), FAKE, FAKE, 10, 1.0, None, 0.0, FAKE, None,
+                               None, None, None, FAKE, 1 << 30, 0, None) == L.LIP_E_UNSUPPORTED
