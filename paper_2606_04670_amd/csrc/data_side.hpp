@@ -264,9 +264,9 @@ template <int D, int NORM, bool HASW, bool MON, bool MASK, int FM>
 __device__ __forceinline__ void cons_group(const DsArgs &A, cdouble_ptr X, int64_t g0,
                                            const double (&xr)[kDsRows][D],
                                            const double (&yr)[kDsRows], const int (&ir)[kDsRows],
-                                           const bool (&valid)[kDsRows], double (&bu)[kDsRows],
-                                           double (&bl)[kDsRows], unsigned long long &cu,
-                                           unsigned long long &cl)
+                                           const unsigned long long (&vmask)[kDsRows],
+                                           double (&bu)[kDsRows], double (&bl)[kDsRows],
+                                           unsigned long long &cu, unsigned long long &cl)
 {
     double su[kDsGroup][kDsRows], sl[kDsGroup][kDsRows];
     ds_dist_group<D, NORM, HASW, MON, kDsRows, FM>(A, X, g0, xr, su, sl);
@@ -295,8 +295,10 @@ __device__ __forceinline__ void cons_group(const DsArgs &A, cdouble_ptr X, int64
             }
             bu[r] = fmin(bu[r], tu);
             bl[r] = fmin(bl[r], tl);
-            cu += __popcll(__ballot(valid[r] && tu < -A.tol));
-            cl += __popcll(__ballot(valid[r] && tl < -A.tol));
+            // lanes past the last row are removed with the wave-uniform mask
+            // (scalar work) instead of a per-pair vector condition
+            cu += __popcll(__ballot(tu < -A.tol) & vmask[r]);
+            cl += __popcll(__ballot(tl < -A.tol) & vmask[r]);
         }
 }
 
@@ -321,10 +323,12 @@ __global__ void __launch_bounds__(256) consistency_kernel(DsArgs A)
     double xr[kDsRows][D], yr[kDsRows], bu[kDsRows], bl[kDsRows];
     int ir[kDsRows], tu_t[kDsRows], tl_t[kDsRows];
     bool valid[kDsRows];
+    unsigned long long vmask[kDsRows];
 #pragma unroll
     for (int r = 0; r < kDsRows; ++r) {
         int64_t i = w.r0 + r * 64 + lane;
         valid[r] = i < A.n;
+        vmask[r] = __ballot(valid[r]);
         i = i < A.n ? i : A.n - 1;
         ir[r] = (int)i;
 #pragma unroll
@@ -349,9 +353,9 @@ __global__ void __launch_bounds__(256) consistency_kernel(DsArgs A)
         for (int64_t g0 = tb; g0 < te; g0 += kDsGroup) {
             const bool masked = (g0 + kDsGroup > A.n) || (g0 < w.r1 && g0 + kDsGroup > w.r0);
             if (masked)
-                cons_group<D, NORM, HASW, MON, true, FM>(A, X, g0, xr, yr, ir, valid, bu, bl, cu, cl);
+                cons_group<D, NORM, HASW, MON, true, FM>(A, X, g0, xr, yr, ir, vmask, bu, bl, cu, cl);
             else
-                cons_group<D, NORM, HASW, MON, false, FM>(A, X, g0, xr, yr, ir, valid, bu, bl, cu, cl);
+                cons_group<D, NORM, HASW, MON, false, FM>(A, X, g0, xr, yr, ir, vmask, bu, bl, cu, cl);
         }
 #pragma unroll
         for (int r = 0; r < kDsRows; ++r) {
@@ -899,10 +903,12 @@ __global__ void __launch_bounds__(256) consistency32_kernel(DsArgs A)
     double xd[R][D], yd[R], bu[R], bl[R];
     int ir[R], pu[R], pl[R];
     bool valid[R];
+    unsigned long long vmask[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         int64_t i = w.r0 + r * 64 + lane;
         valid[r] = i < A.n;
+        vmask[r] = __ballot(valid[r]);
         i = valid[r] ? i : A.n - 1;
         ir[r] = (int)i;
 #pragma unroll
@@ -942,8 +948,14 @@ __global__ void __launch_bounds__(256) consistency32_kernel(DsArgs A)
                 if (MASK) okm = (g + c) < A.n && (int)(g + c) != ir[r];
                 eu[c][r] = au[c][r] || (okm && !(tu > umin[r]));
                 el[c][r] = al[c][r] || (okm && !(tl > lmin[r]));
-                cu += __popcll(__ballot(ok && su));
-                cl += __popcll(__ballot(ok && sl));
+                if (MASK) {
+                    cu += __popcll(__ballot(ok && su));
+                    cl += __popcll(__ballot(ok && sl));
+                } else {
+                    // valid rows through the wave-uniform mask (scalar work)
+                    cu += __popcll(__ballot(su) & vmask[r]);
+                    cl += __popcll(__ballot(sl) & vmask[r]);
+                }
                 any = any || eu[c][r] || el[c][r];
             }
         }
