@@ -31,7 +31,6 @@ METRIC = ("query×data pair-evals/s (d=4, N=1e5, Q=1e6) fwd and fwd+bwd; % VALU 
 # second (one slot = one lane-operation at the base issue rate).
 VALU_PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 FP32_DATASHEET_TFLOPS = 157.3
-FP64_VALU_PEAK_SLOTS = VALU_PEAK_SLOTS
 
 # Issue cost of one instruction in slots, from the measured single-kind
 # rates on this chip (profiles/valu_issue_rates_gfx950.txt): v_add/v_sub_f32
@@ -54,13 +53,16 @@ INSTR_PER_PAIR = {nm: sum(mix.values()) for nm, mix in MIX.items()}
 # Conventional FLOP per pair (each add/sub/min/max/abs-accumulate 1, FMA 2,
 # sqrt 1) used for the datasheet comparison.
 FLOP_PER_PAIR = {"l1": 16, "l2": 24, "linf": 16}
-# FP64 instructions per ordered data pair of the consistency kernel with
-# monotone coordinates (d = 4): 4 differences; per coordinate 2 positive
-# parts + 2 selector FMAs; 3 + 3 accumulations (l2: products and sums,
-# 6 + 6) and 2 square roots (l2, ~10 instructions each); 2 x (mul, add, add)
-# for the bounds; 2 minima; 2 compares.
-FP64_OPS_PER_PAIR = {"l1": 4 + 16 + 6 + 6 + 2 + 2, "linf": 4 + 16 + 6 + 6 + 2 + 2,
-                     "l2": 4 + 16 + 12 + 20 + 6 + 2 + 2}
+# Minimal instructions per ordered data pair of the consistency kernels at
+# d = 4 with the monotone pattern known at compile time.  l1 / linf (FP64
+# kernel, one slot each): 4 differences, 4 positive parts (the monotone
+# coordinates), 3 + 3 accumulations, 2 x 3 for the bounds (mul, add, sub in
+# the definition's order), 2 minima, 2 violation compares = 24.  l2 (FP32
+# filter kernel, slots): 4 differences (2), 4 positive parts (4), 2 x (mul
+# + 3 FMA) squares (8), 2 v_sqrt_f32 (4), 2 x (FMA + sub) bounds (3), 6
+# compares (certain violation, tolerance band, running-minimum candidate for
+# each bound) = 27; the rare FP64 re-evaluations come on top.
+CONS_SLOTS_PER_PAIR = {"l1": 24, "linf": 24, "l2": 27}
 
 
 # HBM traffic of the forward kernel, from rocprofv3 FETCH_SIZE / WRITE_SIZE
@@ -332,8 +334,8 @@ def main():
             # fraction of the VALU issue peak spent on the minimal instruction mix
             "valu_frac": SLOTS_PER_PAIR[nm] * rate / VALU_PEAK_SLOTS,
             "datasheet_fp32_frac": FLOP_PER_PAIR[nm] * rate / 1e12 / FP32_DATASHEET_TFLOPS,
-            "consistency_fp64_valu_frac": FP64_OPS_PER_PAIR[nm] * float(N) * float(N)
-            / (stage_ms[nm]["consistency"] * 1e-3) / FP64_VALU_PEAK_SLOTS,
+            "consistency_valu_frac": CONS_SLOTS_PER_PAIR[nm] * float(N) * float(N)
+            / (stage_ms[nm]["consistency"] * 1e-3) / VALU_PEAK_SLOTS,
         }
     # dominant kernel: the forward bound kernel of the slowest norm
     dom = max(norms, key=lambda nm: stage_ms[nm]["forward"])
