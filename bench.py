@@ -109,7 +109,7 @@ def parse():
     ap.add_argument("--norms", default="l1,l2,linf")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the BF16-vs-FP32, batched-vs-per-set, step-function, "
-                         "smoothing, k-best and regional-monotonicity runs")
+                         "smoothing, k-best, regional-monotonicity and other-workload runs")
     return ap.parse_args()
 
 
@@ -244,6 +244,49 @@ def extra_regional(lf, W, torch, dev, base, x, y, xq, norms, scalar_fwd_ms, reps
     return out
 
 
+def extra_other_configs(lf, W, torch, dev, base, x, y, norms, reps=3):
+    """The remaining workloads, each on its own inputs: the plain fit (d = 2,
+    N = 1e3, Q = 1e4, l2, M = 4; launch-bound), the differentiable one (d = 8,
+    N = 2e5, Q = 262,144, l2, M = 2: forward and backward through the saved
+    indices), the global constant of the monotone local data (N^2 / 2 pairs
+    per norm, FP64), and the FP64 consistency check on the first 2e5 points
+    of the mixed-precision workload (d = 16, l2, M = 1)."""
+    out = {}
+    p = W.plain_l2()
+    px, py, pq = (torch.from_numpy(a).to(dev) for a in (p.x, p.y, p.xq))
+    met = lf.Metric(p.d, "l2")
+    t = _time_ms(torch, lambda: lf.fit_eval(px, py, pq, met, M=p.M), 20)
+    out["plain_l2"] = {"workload": f"plain_l2 d={p.d} N={p.n} Q={p.q} M={p.M} l2",
+                       "fwd_ms": t, "fwd_pair_evals_per_s": float(p.n) * p.q / (t * 1e-3)}
+    p = W.diff_l2()
+    dx, dy_, dq, dgr = (torch.from_numpy(a).to(dev) for a in (p.x, p.y, p.xq, p.dg))
+    met = lf.Metric(p.d, "l2")
+    res = {}
+    tf = _time_ms(torch, lambda: res.__setitem__("o", lf.fit_eval(dx, dy_, dq, met, M=p.M)), reps)
+    o = res["o"]
+    tb = _time_ms(torch, lambda: lf.backward(dx, dy_, dq, met, o["arg_up"], o["arg_lo"],
+                                             dg=dgr, M=p.M), reps)
+    pairs = float(p.n) * p.q
+    out["diff_l2"] = {"workload": f"diff_l2 d={p.d} N={p.n} Q={p.q} M={p.M} l2",
+                      "fwd_ms": tf, "bwd_ms": tb,
+                      "fwd_pair_evals_per_s": pairs / (tf * 1e-3),
+                      "fwd_bwd_pair_evals_per_s": pairs / ((tf + tb) * 1e-3)}
+    gm = {}
+    for nm in norms:
+        met = lf.Metric(base.d, nm)
+        t = _time_ms(torch, lambda: lf.estimate_M(x, y, met, mode="global"), reps)
+        gm[nm] = {"ms": t, "pairs_per_s": float(base.n) * (base.n - 1) / 2 / (t * 1e-3)}
+    out["global_M_monotone_local"] = gm
+    p = W.mixed_l2(q=1)
+    mx, my = (torch.from_numpy(a[:200_000].copy()).to(dev) for a in (p.x, p.y))
+    met = lf.Metric(p.d, "l2")
+    t = _time_ms(torch, lambda: lf.consistency(mx, my, met, M=p.M, per_row=False), reps)
+    nc = 200_000
+    out["consistency_mixed_l2_200k"] = {"workload": "mixed_l2 first 2e5 points, d=16, l2, M=1",
+                                        "ms": t, "pairs_per_s": float(nc) * (nc - 1) / (t * 1e-3)}
+    return out
+
+
 def extra_smooth(lf, W, torch, dev, base, x, y, norms, reps=3):
     """Penalty objective of the smoothing problem (Sec. 4.4, Eq. 7) and its
     gradient on the monotone local workload's data (N = 1e5, d = 4, global
@@ -375,7 +418,8 @@ def main():
                                              {nm: stage_ms[nm]["forward"] for nm in norms}),
                   "regional_monotonicity": extra_regional(
                       lf, W, torch, dev, base, x, y, xq, norms,
-                      {nm: stage_ms[nm]["forward"] for nm in norms})}
+                      {nm: stage_ms[nm]["forward"] for nm in norms}),
+                  "other_configs": extra_other_configs(lf, W, torch, dev, base, x, y, norms)}
 
     rec = {
         "metric": METRIC, "value": value, "unit": "pair-evals/s", "n_gpus": 1,
