@@ -804,7 +804,10 @@ __global__ void __launch_bounds__(256) knn_select_kernel(DsArgs A)
 //                            the lowest index, as the partner requires).
 // Pairs that need FP64 are evaluated with cons_pair (the FP64 kernel's own
 // operation sequence).  A NaN t32 or an infinite E sends the pair to FP64.
-constexpr int kC32Rows = 4;
+// Rows per lane of the FP32-filtered kernel: 4 up to d = 4, fewer above so
+// that the row coordinates and the per-pair state keep several waves per
+// SIMD.
+constexpr int c32_rows(int D) { return D <= 4 ? 4 : (D <= 8 ? 2 : 1); }
 
 constexpr int c32_group(int D) { return D <= 4 ? 2 : 1; }
 
@@ -891,7 +894,7 @@ __device__ __forceinline__ void c32_dist(const DsArgs &A, const float (&xr)[D], 
 template <int D, int NORM, bool HASW, bool MON, int FM = -1>
 __global__ void __launch_bounds__(256) consistency32_kernel(DsArgs A)
 {
-    constexpr int R = kC32Rows;
+    constexpr int R = c32_rows(D);
     constexpr int S = D + 2;
     constexpr int G = c32_group(D);
     WaveRange w;
@@ -900,7 +903,7 @@ __global__ void __launch_bounds__(256) consistency32_kernel(DsArgs A)
     const double E = A.cE[0];
     const float vlo = f32_down(-A.tol - E), vhi = f32_up(-A.tol + E);
     float xr[R][D], yr[R], umin[R], lmin[R];
-    double xd[R][D], yd[R], bu[R], bl[R];
+    double bu[R], bl[R];
     int ir[R], pu[R], pl[R];
     bool valid[R];
     unsigned long long vmask[R];
@@ -912,12 +915,8 @@ __global__ void __launch_bounds__(256) consistency32_kernel(DsArgs A)
         i = valid[r] ? i : A.n - 1;
         ir[r] = (int)i;
 #pragma unroll
-        for (int j = 0; j < D; ++j) {
-            xr[r][j] = A.c32[i * S + j];
-            xd[r][j] = (double)xr[r][j];
-        }
+        for (int j = 0; j < D; ++j) xr[r][j] = A.c32[i * S + j];
         yr[r] = A.c32[i * S + D];
-        yd[r] = (double)yr[r];
         bu[r] = bl[r] = __builtin_inf();
         umin[r] = lmin[r] = __builtin_inff();
         pu[r] = pl[r] = -1;
@@ -966,8 +965,13 @@ __global__ void __launch_bounds__(256) consistency32_kernel(DsArgs A)
             for (int r = 0; r < R; ++r) {
                 if (!(eu[c][r] || el[c][r])) continue;
                 const int64_t k = g + c;
+                // the FP64 row values are the FP32 inputs widened (exact),
+                // formed here instead of being held for the whole scan
+                double xd[D];
+#pragma unroll
+                for (int j = 0; j < D; ++j) xd[j] = (double)xr[r][j];
                 double tu, tl;
-                cons_pair<D, NORM, HASW, MON>(A, xd[r], yd[r], k, tu, tl);
+                cons_pair<D, NORM, HASW, MON>(A, xd, (double)yr[r], k, tu, tl);
                 if (au[c][r] && tu < -A.tol) ++xu;
                 if (al[c][r] && tl < -A.tol) ++xl;
                 if (eu[c][r] && tu < bu[r]) {

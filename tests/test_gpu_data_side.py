@@ -265,3 +265,22 @@ def test_consistency_l2_tiny_values(lf):
     for key in ("slack_up", "slack_lo", "partner_up", "partner_lo"):
         np.testing.assert_array_equal(g[key], o[key])
     assert g["counts"].tolist() == [o["viol_up"].sum(), o["viol_lo"].sum()]
+
+
+@pytest.mark.parametrize("d", [5, 8, 12, 16])
+@pytest.mark.parametrize("norm", [1, 2, 3])
+def test_consistency_exact_higher_dims(lf, d, norm):
+    """Dimensions above 4 (the l2 filter kernel holds fewer rows per lane
+    there): slacks, partners and counts bit-exact, with and without monotone
+    coordinates, per-datum constants and weights, ragged n over several
+    column chunks."""
+    for k, n in enumerate((130, 1537)):
+        mon = np.zeros(d, np.int8) if k == 0 else np.array([1, 0, -1] * 6, np.int8)[:d]
+        p = W.random_problem(900 + d + n, n=n, q=1, d=d, norm=norm, mon=mon,
+                             local=(k == 1), weighted=(d % 2 == 0))
+        M32 = float(np.float32(1.2))
+        g = _consistency(lf, p, M32, p.Mk)
+        o = oracle.consistency(p.x, p.y, norm, M=M32, Mk=p.Mk, mon=p.mon, w=p.w)
+        for key in ("slack_up", "slack_lo", "partner_up", "partner_lo"):
+            np.testing.assert_array_equal(g[key], o[key], err_msg=f"d={d} n={n} {key}")
+        assert g["counts"].tolist() == [o["viol_up"].sum(), o["viol_lo"].sum()]
