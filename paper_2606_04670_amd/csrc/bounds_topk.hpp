@@ -21,6 +21,10 @@ namespace lip {
 
 constexpr int kTopK = 4;
 
+// Queries per lane: half of the fused kernel's, since each query also holds
+// its two sorted lists of kTopK values.
+constexpr int topk_rows(int D) { return rows_for_dim(D) / 2 > 0 ? rows_for_dim(D) / 2 : 1; }
+
 struct TopkArgs {
     FwdArgs f;            // staged records, n, queries, transform, outputs g / h_up / h_lo
     int32_t k;
@@ -58,7 +62,7 @@ template <int D, int DM, int NORM>
 __global__ void __launch_bounds__(256) bounds_topk_kernel(TopkArgs A)
 {
     constexpr int S = Rec<D>::S;
-    constexpr int R = rows_for_dim(D);
+    constexpr int R = topk_rows(D);
     constexpr int G = group_for_dim(D);
     const FwdArgs &a = A.f;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);

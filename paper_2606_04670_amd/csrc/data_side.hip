@@ -418,8 +418,8 @@ extern "C" lip_status lip_consistency(const lip_metric *metric, const float *x, 
     A.X = (const double *)ws;
     A.tol = tol;
     // l2 runs the FP32-filtered kernel (c32_rows(d) rows per lane), l1 / linf
-    // the FP64 kernel (kDsRows)
-    const int rows = 64 * (mi.norm == LIP_L2 ? c32_rows(mi.d) : kDsRows);
+    // the FP64 kernel (ds_cons_rows(d))
+    const int rows = 64 * (mi.norm == LIP_L2 ? c32_rows(mi.d) : ds_cons_rows(mi.d));
     choose_chunks(n, rows, kDsMaxChunks, &A);
     char *p = (char *)ws + align_up((size_t)A.npad * (size_t)(mi.d + 2) * 8, 256);
     const size_t e = (size_t)A.n_chunks * (size_t)n;

@@ -44,7 +44,10 @@
 
 namespace lip {
 
-constexpr int kDsRows = 2;        // rows per lane (consistency, slope)
+constexpr int kDsRows = 2;        // rows per lane (slope)
+// Rows per lane of the FP64 consistency kernel: 2, and 1 above d = 12 where
+// two rows of FP64 coordinates would leave one wave per SIMD.
+constexpr int ds_cons_rows(int D) { return D <= 12 ? 2 : 1; }
 constexpr int kDsTile = 64;       // columns per partner tile
 constexpr int kDsGroup = 4;       // columns per scalar-load group
 constexpr int kDsMaxChunks = 16;  // column chunks (consistency, slope)
@@ -260,16 +263,16 @@ __device__ __forceinline__ bool wave_range(const DsArgs &A, int rows_per_wave, W
 
 // ---- consistency -------------------------------------------------------------
 
-template <int D, int NORM, bool HASW, bool MON, bool MASK, int FM>
+template <int D, int NORM, bool HASW, bool MON, bool MASK, int FM, int R>
 __device__ __forceinline__ void cons_group(const DsArgs &A, cdouble_ptr X, int64_t g0,
-                                           const double (&xr)[kDsRows][D],
-                                           const double (&yr)[kDsRows], const int (&ir)[kDsRows],
-                                           const unsigned long long (&vmask)[kDsRows],
-                                           double (&bu)[kDsRows], double (&bl)[kDsRows],
+                                           const double (&xr)[R][D],
+                                           const double (&yr)[R], const int (&ir)[R],
+                                           const unsigned long long (&vmask)[R],
+                                           double (&bu)[R], double (&bl)[R],
                                            unsigned long long &cu, unsigned long long &cl)
 {
-    double su[kDsGroup][kDsRows], sl[kDsGroup][kDsRows];
-    ds_dist_group<D, NORM, HASW, MON, kDsRows, FM>(A, X, g0, xr, su, sl);
+    double su[kDsGroup][R], sl[kDsGroup][R];
+    ds_dist_group<D, NORM, HASW, MON, R, FM>(A, X, g0, xr, su, sl);
     double yk[kDsGroup], mk[kDsGroup];
 #pragma unroll
     for (int c = 0; c < kDsGroup; ++c) {
@@ -279,7 +282,7 @@ __device__ __forceinline__ void cons_group(const DsArgs &A, cdouble_ptr X, int64
 #pragma unroll
     for (int c = 0; c < kDsGroup; ++c)
 #pragma unroll
-        for (int r = 0; r < kDsRows; ++r) {
+        for (int r = 0; r < R; ++r) {
             double du = su[c][r], dl = MON ? sl[c][r] : su[c][r];
             if (NORM == 2) {
                 du = sqrt(du);
@@ -316,16 +319,17 @@ __device__ __forceinline__ void cons_pair(const DsArgs &A, const double (&xr)[D]
 template <int D, int NORM, bool HASW, bool MON, int FM = -1>
 __global__ void __launch_bounds__(256) consistency_kernel(DsArgs A)
 {
-    constexpr int RW = 64 * kDsRows;
+    constexpr int R = ds_cons_rows(D);
+    constexpr int RW = 64 * R;
     WaveRange w;
     if (!wave_range(A, RW, w)) return;
     const int lane = threadIdx.x & 63;
-    double xr[kDsRows][D], yr[kDsRows], bu[kDsRows], bl[kDsRows];
-    int ir[kDsRows], tu_t[kDsRows], tl_t[kDsRows];
-    bool valid[kDsRows];
-    unsigned long long vmask[kDsRows];
+    double xr[R][D], yr[R], bu[R], bl[R];
+    int ir[R], tu_t[R], tl_t[R];
+    bool valid[R];
+    unsigned long long vmask[R];
 #pragma unroll
-    for (int r = 0; r < kDsRows; ++r) {
+    for (int r = 0; r < R; ++r) {
         int64_t i = w.r0 + r * 64 + lane;
         valid[r] = i < A.n;
         vmask[r] = __ballot(valid[r]);
@@ -343,9 +347,9 @@ __global__ void __launch_bounds__(256) consistency_kernel(DsArgs A)
     int t = 0;
     for (int64_t tb = w.c0; tb < w.c1; tb += kDsTile, ++t) {
         const int64_t te = tb + kDsTile < w.c1 ? tb + kDsTile : w.c1;
-        double pu[kDsRows], pl[kDsRows];
+        double pu[R], pl[R];
 #pragma unroll
-        for (int r = 0; r < kDsRows; ++r) {
+        for (int r = 0; r < R; ++r) {
             pu[r] = bu[r];
             pl[r] = bl[r];
         }
@@ -353,19 +357,19 @@ __global__ void __launch_bounds__(256) consistency_kernel(DsArgs A)
         for (int64_t g0 = tb; g0 < te; g0 += kDsGroup) {
             const bool masked = (g0 + kDsGroup > A.n) || (g0 < w.r1 && g0 + kDsGroup > w.r0);
             if (masked)
-                cons_group<D, NORM, HASW, MON, true, FM>(A, X, g0, xr, yr, ir, vmask, bu, bl, cu, cl);
+                cons_group<D, NORM, HASW, MON, true, FM, R>(A, X, g0, xr, yr, ir, vmask, bu, bl, cu, cl);
             else
-                cons_group<D, NORM, HASW, MON, false, FM>(A, X, g0, xr, yr, ir, vmask, bu, bl, cu, cl);
+                cons_group<D, NORM, HASW, MON, false, FM, R>(A, X, g0, xr, yr, ir, vmask, bu, bl, cu, cl);
         }
 #pragma unroll
-        for (int r = 0; r < kDsRows; ++r) {
+        for (int r = 0; r < R; ++r) {
             tu_t[r] = bu[r] < pu[r] ? t : tu_t[r];
             tl_t[r] = bl[r] < pl[r] ? t : tl_t[r];
         }
     }
     // partners: first column of the last improving tile attaining the minimum
 #pragma unroll
-    for (int r = 0; r < kDsRows; ++r) {
+    for (int r = 0; r < R; ++r) {
         int pu_i = -1, pl_i = -1;
         const int64_t bu0 = w.c0 + (int64_t)(tu_t[r] < 0 ? 0 : tu_t[r]) * kDsTile;
         const int64_t bl0 = w.c0 + (int64_t)(tl_t[r] < 0 ? 0 : tl_t[r]) * kDsTile;

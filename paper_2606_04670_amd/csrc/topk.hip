@@ -115,7 +115,7 @@ extern "C" lip_status lip_fit_eval_k(const lip_metric *metric, const float *x, c
     A.k = k;
     for (int j = 0; j < kTopK; ++j) A.wk[j] = j < k ? wk[j] : 0.0f;
     // data split when the queries alone do not fill the chip
-    const int R = rows_for_dim(mi.d);
+    const int R = topk_rows(mi.d);
     const int64_t qwaves = (q + 64 * R - 1) / (64 * R);
     int nc = 1;
     while (nc < kTopkMaxChunks && qwaves * nc < 16384 && n >= (int64_t)nc * 2 * 64) nc *= 2;
