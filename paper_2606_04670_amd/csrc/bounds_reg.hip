@@ -3,16 +3,20 @@
 //
 // Every coordinate carries the two intervals where f is not decreasing (ND)
 // and not increasing (NI) (kinds 0 / +1 / -1 are the cases where these are
-// everything or nothing).  For a pair, with lo / hi the smaller / larger of
-// the two coordinates, the travelled length inside an interval [s, t] is
-// max(min(hi, t) - max(lo, s), 0); moving towards larger values (query >=
-// datum) the upper component is the length inside ND and the lower one the
-// length inside NI, moving towards smaller values the reverse.  Components
-// are weighted and combined by the norm in FP32.  A lane owns R queries, a
-// wave 64 R queries and one data chunk; records [x | y | M_k] (the caller's
-// coordinates) come four at a time through scalar loads; the first index of
-// the running min / max is kept per pair (strict comparisons, data in
-// ascending order), chunk partials go through the bound path's combine.
+// everything or nothing; an empty interval is stored as [0, 0]).  With
+// c(v) = w clamp(v, s, t) the clamped, weighted coordinate, the travelled
+// length inside [s, t] is |c(q) - c(x)|, and the difference a = c_ND(q) -
+// c_ND(x) is positive when moving towards larger values, negative otherwise
+// (likewise b for NI).  So the upper component (length where f may rise in
+// the direction of travel: inside ND moving up, inside NI moving down) is
+// max(a, -b), and the lower one max(b, -a).  The clamped data coordinates are
+// staged per datum and the clamped query coordinates formed once per query,
+// so a pair costs two subtractions and two maxima per coordinate, then the
+// norm, as in the fused kernel.  A lane owns R queries, a wave 64 R queries
+// and one data chunk; records [c_ND(x_0), c_NI(x_0), .. | y | M_k] come four
+// at a time through scalar loads; the first index of the running min / max is
+// kept per pair (strict comparisons, data in ascending order), chunk
+// partials go through the bound path's combine.
 #include "host_common.hpp"
 #include "lip_device.hpp"
 
@@ -21,7 +25,7 @@ namespace lip {
 namespace {
 
 struct RegArgs {
-    const float *rec;  // [npad][D + 2]
+    const float *rec;  // [npad][2 D + 2]
     int64_t n, npad;
     int32_t n_chunks;
     int32_t pad0;
@@ -37,28 +41,31 @@ struct RegArgs {
 
 constexpr int reg_rows(int D) { return rows_for_dim(D) / 2 > 0 ? rows_for_dim(D) / 2 : 1; }
 
+// w clamp(v, s, t) (s <= t; the median of three needs no canonicalisation)
+__device__ __forceinline__ float reg_clamp(float v, float s, float t, float w)
+{
+    return w * __builtin_amdgcn_fmed3f(v, s, t);
+}
+
 template <int D, int NORM>
-__device__ __forceinline__ void reg_dist(const RegArgs &A, const float (&q)[D], const float *xk,
-                                         float &tu, float &tl)
+__device__ __forceinline__ void reg_dist(const float (&q)[2 * D], const float *xk, float &tu,
+                                         float &tl)
 {
     float su = 0.0f, sl = 0.0f;
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-        const float lo = fminf(q[i], xk[i]), hi = fmaxf(q[i], xk[i]);
-        const float lnd = fmaxf(fminf(hi, A.nd_t[i]) - fmaxf(lo, A.nd_s[i]), 0.0f);
-        const float lni = fmaxf(fminf(hi, A.ni_t[i]) - fmaxf(lo, A.ni_s[i]), 0.0f);
-        const bool right = q[i] >= xk[i];
-        const float cu = (right ? lnd : lni) * A.w[i];
-        const float cl = (right ? lni : lnd) * A.w[i];
+        const float a = q[2 * i] - xk[2 * i];          // signed length inside ND
+        const float b = q[2 * i + 1] - xk[2 * i + 1];  // signed length inside NI
+        const float cu = fmaxf(a, -b), cl = fmaxf(b, -a);
         if (NORM == kNormL1) {
-            su = su + cu;
-            sl = sl + cl;
+            su = i == 0 ? cu : su + cu;
+            sl = i == 0 ? cl : sl + cl;
         } else if (NORM == kNormL2) {
-            su = fmaf(cu, cu, su);
-            sl = fmaf(cl, cl, sl);
+            su = i == 0 ? cu * cu : fmaf(cu, cu, su);
+            sl = i == 0 ? cl * cl : fmaf(cl, cl, sl);
         } else {
-            su = fmaxf(su, cu);
-            sl = fmaxf(sl, cl);
+            su = i == 0 ? cu : fmaxf(su, cu);
+            sl = i == 0 ? cl : fmaxf(sl, cl);
         }
     }
     if (NORM == kNormL2) {
@@ -73,7 +80,7 @@ template <int D, int NORM>
 __global__ void __launch_bounds__(256) bounds_reg_kernel(RegArgs A)
 {
     constexpr int R = reg_rows(D);
-    constexpr int S = D + 2;
+    constexpr int S = 2 * D + 2;
     constexpr int G = 4;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int chunk = blockIdx.x % A.n_chunks;
@@ -81,14 +88,18 @@ __global__ void __launch_bounds__(256) bounds_reg_kernel(RegArgs A)
     const int64_t q0 = qb * 64 * R;
     if (q0 >= A.q) return;
     const int lane = threadIdx.x & 63;
-    float qv[R][D], hu[R], hl[R];
+    float qv[R][2 * D], hu[R], hl[R];
     int au[R], al[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         int64_t j = q0 + r * 64 + lane;
         j = j < A.q ? j : A.q - 1;
 #pragma unroll
-        for (int i = 0; i < D; ++i) qv[r][i] = A.xq[j * D + i];
+        for (int i = 0; i < D; ++i) {
+            const float v = A.xq[j * D + i];
+            qv[r][2 * i] = reg_clamp(v, A.nd_s[i], A.nd_t[i], A.w[i]);
+            qv[r][2 * i + 1] = reg_clamp(v, A.ni_s[i], A.ni_t[i], A.w[i]);
+        }
         hu[r] = __builtin_inff();
         hl[r] = -__builtin_inff();
         au[r] = -1;
@@ -108,11 +119,11 @@ __global__ void __launch_bounds__(256) bounds_reg_kernel(RegArgs A)
             const int64_t k = g0 + c;
             if (k >= c1) break;  // wave-uniform
             const float *xk = v + c * S;
-            const float yk = xk[D], mk = xk[D + 1];
+            const float yk = xk[2 * D], mk = xk[2 * D + 1];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 float tu, tl;
-                reg_dist<D, NORM>(A, qv[r], xk, tu, tl);
+                reg_dist<D, NORM>(qv[r], xk, tu, tl);
                 const float u = fmaf(mk, tu, yk), l = fmaf(-mk, tl, yk);
                 if (u < hu[r]) {
                     hu[r] = u;
@@ -146,16 +157,20 @@ __global__ void __launch_bounds__(256) bounds_reg_kernel(RegArgs A)
 }
 
 __global__ void reg_stage_kernel(const float *x, const float *y, const float *Mk, float M, int d,
-                                 int64_t n, int64_t npad, float *rec)
+                                 int64_t n, int64_t npad, RegArgs A, float *rec)
 {
-    const int S = d + 2;
+    const int S = 2 * d + 2;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < npad; k += stride) {
         float *o = rec + k * S;
         const bool in = k < n;
-        for (int j = 0; j < d; ++j) o[j] = in ? x[k * d + j] : 0.0f;
-        o[d] = in ? y[k] : 0.0f;
-        o[d + 1] = in ? (Mk ? Mk[k] : M) : 0.0f;
+        for (int j = 0; j < d; ++j) {
+            const float v = in ? x[k * d + j] : 0.0f;
+            o[2 * j] = reg_clamp(v, A.nd_s[j], A.nd_t[j], A.w[j]);
+            o[2 * j + 1] = reg_clamp(v, A.ni_s[j], A.ni_t[j], A.w[j]);
+        }
+        o[2 * d] = in ? y[k] : 0.0f;
+        o[2 * d + 1] = in ? (Mk ? Mk[k] : M) : 0.0f;
     }
 }
 
@@ -190,7 +205,7 @@ int64_t reg_npad(int64_t n) { return (n + 63) / 64 * 64; }
 
 size_t reg_ws_bytes(int64_t n, int64_t q, int d)
 {
-    return align_up((size_t)reg_npad(n) * (size_t)(d + 2) * 4, 256) + partial_bytes(q) + 256;
+    return align_up((size_t)reg_npad(n) * (size_t)(2 * d + 2) * 4, 256) + partial_bytes(q) + 256;
 }
 
 lip_status run_bounds_reg(const MetricInfo &mi, const float *x, const float *y, int64_t n,
@@ -208,14 +223,19 @@ lip_status run_bounds_reg(const MetricInfo &mi, const float *x, const float *y, 
     A.npad = reg_npad(n);
     for (int i = 0; i < kMaxDim; ++i) {
         const bool in = i < mi.d;
-        A.nd_s[i] = in ? mi.nd_s[i] : 0.0f;
-        A.nd_t[i] = in ? mi.nd_t[i] : 0.0f;
-        A.ni_s[i] = in ? mi.ni_s[i] : 0.0f;
-        A.ni_t[i] = in ? mi.ni_t[i] : 0.0f;
+        float nds = in ? mi.nd_s[i] : 0.0f, ndt = in ? mi.nd_t[i] : 0.0f;
+        float nis = in ? mi.ni_s[i] : 0.0f, nit = in ? mi.ni_t[i] : 0.0f;
+        // an empty region clamps everything to one point: zero length
+        if (!(nds <= ndt)) nds = ndt = 0.0f;
+        if (!(nis <= nit)) nis = nit = 0.0f;
+        A.nd_s[i] = nds;
+        A.nd_t[i] = ndt;
+        A.ni_s[i] = nis;
+        A.ni_t[i] = nit;
         A.w[i] = in ? (float)mi.w[i] : 1.0f;
     }
     float *rec = (float *)ws;
-    char *p = (char *)ws + align_up((size_t)A.npad * (size_t)(mi.d + 2) * 4, 256);
+    char *p = (char *)ws + align_up((size_t)A.npad * (size_t)(2 * mi.d + 2) * 4, 256);
     A.rec = rec;
     A.xq = xq;
     A.q = q;
@@ -242,7 +262,7 @@ lip_status run_bounds_reg(const MetricInfo &mi, const float *x, const float *y, 
     int64_t gs = (A.npad + 255) / 256;
     if (gs > 65536) gs = 65536;
     hipLaunchKernelGGL(reg_stage_kernel, dim3((unsigned)gs), dim3(256), 0, s, x, y, Mk, M, mi.d,
-                       n, A.npad, rec);
+                       n, A.npad, A, rec);
     const unsigned grid = (unsigned)(((qwaves + 3) / 4) * A.n_chunks);
     launch(A, dim3(grid), dim3(256), s);
     if (hipGetLastError() != hipSuccess) return LIP_E_DEVICE;
