@@ -80,9 +80,9 @@ def _load():
         lib.orc_bounds_step.restype = None
         lib.orc_candidates_step.argtypes = [i32, i32, P, P, P, P, i64, P, i32, P, P, P, P, P]
         lib.orc_candidates_step.restype = None
-        lib.orc_smooth.argtypes = [i32, i32, P, P, P, P, i64, f64, P, P, f64, P, P]
+        lib.orc_smooth.argtypes = [i32, i32, P, P, P, P, i64, f64, P, P, f64, f64, P, P]
         lib.orc_smooth.restype = None
-        lib.orc_smooth_scale.argtypes = [i32, i32, P, P, P, P, i64, f64, P, P, f64, P, P, P]
+        lib.orc_smooth_scale.argtypes = [i32, i32, P, P, P, P, i64, f64, P, P, f64, f64, P, P, P]
         lib.orc_smooth_scale.restype = None
         lib.orc_bounds_k.argtypes = [i32, i32, P, P, P, P, i64, f64, P, i32, P, P, i64, P, P, P]
         lib.orc_bounds_k.restype = None
@@ -261,8 +261,10 @@ def candidates_step(x, y, xq1, norm: int, knots_, d1, V32, mon=None, w=None):
     return u, l
 
 
-def smooth(x, y, eps, norm: int, M: float = 0.0, Mk=None, p: float = 1.0, mon=None, w=None):
-    """(F, grad[n]) float64: the penalty objective of Eq. (7) and its gradient at eps."""
+def smooth(x, y, eps, norm: int, M: float = 0.0, Mk=None, p: float = 1.0, mon=None, w=None,
+           prune: float = 0.0):
+    """(F, grad[n]) float64: the penalty objective of Eq. (7) and its gradient at eps;
+    prune > 0 drops the pairs of the Sec. 5 pre-screening with that fraction."""
     d = int(np.shape(x)[1])
     x, y, w, mon = _common(x, y, w, mon, d)
     Mk = None if Mk is None else _f32(Mk)
@@ -272,11 +274,12 @@ def smooth(x, y, eps, norm: int, M: float = 0.0, Mk=None, p: float = 1.0, mon=No
     F = np.zeros(1, np.float64)
     g = np.empty(n, np.float64)
     _load().orc_smooth(d, norm, _p(w), _p(mon), _p(x), _p(y), n, float(M), _p(Mk), _p(e),
-                       float(p), _p(F), _p(g))
+                       float(p), float(prune), _p(F), _p(g))
     return float(F[0]), g
 
 
-def smooth_scale(x, y, eps, norm: int, tau: float, M: float = 0.0, Mk=None, mon=None, w=None):
+def smooth_scale(x, y, eps, norm: int, tau: float, M: float = 0.0, Mk=None, mon=None, w=None,
+                 prune: float = 0.0):
     """(A, row_abs[n], row_cnt[n]): error scale of Eq. (7) for comparisons."""
     d = int(np.shape(x)[1])
     x, y, w, mon = _common(x, y, w, mon, d)
@@ -287,7 +290,7 @@ def smooth_scale(x, y, eps, norm: int, tau: float, M: float = 0.0, Mk=None, mon=
     ra = np.empty(n, np.float64)
     rc = np.empty(n, np.int64)
     _load().orc_smooth_scale(d, norm, _p(w), _p(mon), _p(x), _p(y), n, float(M), _p(Mk), _p(e),
-                             float(tau), _p(A), _p(ra), _p(rc))
+                             float(prune), float(tau), _p(A), _p(ra), _p(rc))
     return float(A[0]), ra, rc
 
 

@@ -574,10 +574,22 @@ void orc_candidates_step(int d, int norm, const double *w, const signed char *mo
  *     F(eps) = (1/p) ||eps||^2 + sum_{i != k} ( (a_ik)_+^2 + (b_ik)_+^2 ).
  * This returns F and its gradient: d/d eps_i of (a_ik)_+^2 is 2 (a_ik)_+ and
  * d/d eps_k is -2 (a_ik)_+; (b_ik)_+^2 gives the opposite signs.  Plain
- * serial loops over all ordered pairs. */
+ * serial loops over all ordered pairs.
+ *
+ * Pre-screening of Sec. 5 (c > 0): a pair whose data already satisfy both
+ * constraints with a third of the allowance (c = 1/3 in the paper) is taken
+ * out of the sums before the minimisation.  Here the ordered pair (i, k) is
+ * dropped when, on the given y (not on z),
+ *     y_i - y_k <= c M_k dist_up(x^i, x^k)  and  y_k - y_i <= c M_k dist_lo(x^i, x^k)
+ * (products evaluated left to right); c = 0 keeps every pair. */
+static int pruned(double c, double yi, double yk, double mk, double du, double dl)
+{
+    return c > 0.0 && yi - yk <= c * mk * du && yk - yi <= c * mk * dl;
+}
+
 void orc_smooth(int d, int norm, const double *w, const signed char *mon, const float *x,
                 const float *y, long n, double M, const float *Mk, const double *eps, double p,
-                double *F, double *grad)
+                double c, double *F, double *grad)
 {
     double total = 0.0;
     for (long i = 0; i < n; ++i) grad[i] = 0.0;
@@ -587,6 +599,7 @@ void orc_smooth(int d, int norm, const double *w, const signed char *mon, const 
             double du, dl;
             dist_pair(d, norm, w, mon, x + i * (long)d, x + k * (long)d, &du, &dl, NULL, NULL);
             double mk = m_of(Mk, M, k);
+            if (pruned(c, (double)y[i], (double)y[k], mk, du, dl)) continue;
             double zi = (double)y[i] + eps[i], zk = (double)y[k] + eps[k];
             double a = zi - zk - mk * du;
             double b = zk - zi - mk * dl;
@@ -610,13 +623,14 @@ void orc_smooth(int d, int norm, const double *w, const signed char *mon, const 
 }
 
 /* Error scale of the penalty objective, for comparisons only: the sum A of
- * the positive parts (a_ik)_+ + (b_ik)_+ over all ordered pairs, and per row
+ * the positive parts (a_ik)_+ + (b_ik)_+ over all ordered pairs that the
+ * pre-screening keeps, and per row
  * i, over the four terms that move eps_i (a_ik, b_ik of the pairs (i, k) and
  * a_ki, b_ki of the pairs (k, i)), the sum of their gradient magnitudes
  * 2 (t)_+ (row_abs) and the number of them above -tau (row_cnt). */
 void orc_smooth_scale(int d, int norm, const double *w, const signed char *mon, const float *x,
                       const float *y, long n, double M, const float *Mk, const double *eps,
-                      double tau, double *A, double *row_abs, long *row_cnt)
+                      double c, double tau, double *A, double *row_abs, long *row_cnt)
 {
     double total = 0.0;
     for (long i = 0; i < n; ++i) {
@@ -629,6 +643,7 @@ void orc_smooth_scale(int d, int norm, const double *w, const signed char *mon, 
             double du, dl;
             dist_pair(d, norm, w, mon, x + i * (long)d, x + k * (long)d, &du, &dl, NULL, NULL);
             double mk = m_of(Mk, M, k);
+            if (pruned(c, (double)y[i], (double)y[k], mk, du, dl)) continue;
             double zi = (double)y[i] + eps[i], zk = (double)y[k] + eps[k];
             double t[2] = {zi - zk - mk * du, zk - zi - mk * dl};
             for (int j = 0; j < 2; ++j) {

@@ -106,3 +106,107 @@ def test_large_constant_leaves_the_ridge_term():
     F, g = oracle.smooth(x, y, eps, oracle.L2, M=1e6, p=0.5)
     assert F == pytest.approx(np.sum(eps ** 2) / 0.5, rel=1e-14)
     np.testing.assert_allclose(g, 2 * eps / 0.5, rtol=1e-14)
+
+
+# ---- pre-screening of Sec. 5 ------------------------------------------------------
+# An ordered pair (i, k) leaves the sums when y_i - y_k <= c M_k dist_up and
+# y_k - y_i <= c M_k dist_lo on the given data y.  The cases below are worked by
+# hand; every value is exact in binary floating point.
+
+
+@pytest.mark.parametrize("norm", NORMS)
+def test_prune_three_points_by_hand(norm):
+    # x = 0, 1, 3; y = 0, 0.25, 2; M = 1, p = 1; eps = (2, 0, -4) -> z = (2, 0.25, -2).
+    # c = 0.25: c M d = 0.25, 0.75, 0.5 for the pairs {0,1}, {0,2}, {1,2} against
+    # |dy| = 0.25, 2, 1.75: only {0,1} is dropped (a tie, kept out by <=), although
+    # its z values violate the constraint (a_01 = 1.75 - 1 = 0.75).
+    # kept: {0,2}: a_02 = b_20 = 4 - 3 = 1; {1,2}: a_12 = b_21 = 2.25 - 2 = 0.25.
+    #   F = (4 + 16) + 2 (1 + 0.0625) = 22.125;  g = (4 + 4, 1, -8 - 4 - 1) = (8, 1, -13)
+    # c = 0.24 (or 0) keeps {0,1}: F = 22.125 + 2 * 0.5625 = 23.25, g = (11, -2, -13)
+    x = np.array([[0.0], [1.0], [3.0]], np.float32)
+    y = np.array([0.0, 0.25, 2.0], np.float32)
+    eps = [2.0, 0.0, -4.0]
+    F, g = oracle.smooth(x, y, eps, norm, M=1.0, p=1.0, prune=0.25)
+    assert F == 22.125
+    np.testing.assert_array_equal(g, [8.0, 1.0, -13.0])
+    for c in (0.24, 0.0):
+        F, g = oracle.smooth(x, y, eps, norm, M=1.0, p=1.0, prune=c)
+        assert F == 23.25
+        np.testing.assert_array_equal(g, [11.0, -2.0, -13.0])
+
+
+@pytest.mark.parametrize("norm", NORMS)
+def test_prune_directional_distances_by_hand(norm):
+    # One increasing coordinate, x = 0, 1, M = 1, p = 1, c = 0.25.
+    # (i, k) = (0, 1): dist_up = 0, dist_lo = 1;  (1, 0): dist_up = 1, dist_lo = 0.
+    x = np.array([[0.0], [1.0]], np.float32)
+    mon = np.array([1], np.int8)
+    # y = (0.25, 0) decreases: (0, 1) needs 0.25 <= 0, (1, 0) needs 0.25 <= 0: both
+    # kept (|dy| <= c M |dx| would drop them).  eps = 0: a_01 = 0.25 and
+    # b_10 = z_0 - z_1 - 0 = 0.25:  F = 2 * 0.0625 = 0.125,  g = (1, -1)
+    F, g = oracle.smooth(x, [0.25, 0.0], [0.0, 0.0], norm, M=1.0, p=1.0, mon=mon, prune=0.25)
+    assert F == 0.125
+    np.testing.assert_array_equal(g, [1.0, -1.0])
+    # y = (0, 0.25) increases: (0, 1): -0.25 <= 0 and 0.25 <= 0.25; (1, 0): 0.25 <= 0.25
+    # and -0.25 <= 0: both dropped.  eps = (1, -1): F = 2, g = (2, -2); without the
+    # pre-screening a_01 = b_10 = 1.75 add 2 * 3.0625: F = 8.125, g = (9, -9)
+    F, g = oracle.smooth(x, [0.0, 0.25], [1.0, -1.0], norm, M=1.0, p=1.0, mon=mon, prune=0.25)
+    assert F == 2.0
+    np.testing.assert_array_equal(g, [2.0, -2.0])
+    F, g = oracle.smooth(x, [0.0, 0.25], [1.0, -1.0], norm, M=1.0, p=1.0, mon=mon)
+    assert F == 8.125
+    np.testing.assert_array_equal(g, [9.0, -9.0])
+
+
+@pytest.mark.parametrize("norm", NORMS)
+def test_prune_uses_the_datums_constant_by_hand(norm):
+    # x = 0, 1; y = (0, 0.25); M_k = (1, 0.5); c = 0.25; eps = (1, -1) -> z = (1, -0.75).
+    # (0, 1) with M_1: 0.25 <= 0.125 fails -> kept: a_01 = 1.75 - 0.5 = 1.25;
+    # (1, 0) with M_0: 0.25 <= 0.25 and -0.25 <= 0.25 -> dropped.
+    #   F = 2 + 1.5625 = 3.5625,  g = (2 + 2.5, -2 - 2.5)
+    # (With the row's constant M_i instead, (1, 0) would stay: b_10 = 1.75 - 1.)
+    x = np.array([[0.0], [1.0]], np.float32)
+    F, g = oracle.smooth(x, [0.0, 0.25], [1.0, -1.0], norm, Mk=[1.0, 0.5], p=1.0, prune=0.25)
+    assert F == 3.5625
+    np.testing.assert_array_equal(g, [4.5, -4.5])
+
+
+@pytest.mark.parametrize("norm", NORMS)
+@pytest.mark.parametrize("local", [False, True])
+def test_prune_nested_in_c_and_large_c_limit(norm, local):
+    # the dropped sets grow with c (M_k dist >= 0), so F cannot grow; a c beyond every
+    # |dy| / (M_k dist) drops all pairs of distinct points (the data here are distinct)
+    x, y, rng = _data(20 + norm, 60, 3)
+    mon = np.array([1, 0, -1], np.int8)
+    Mk = (0.5 + rng.random(60)).astype(np.float32) if local else None
+    eps = 0.5 * rng.standard_normal(60)
+    Fs = [oracle.smooth(x, y, eps, norm, M=0.3, Mk=Mk, p=2.0, mon=mon, prune=c)[0]
+          for c in (0.0, 0.05, 0.2, 1 / 3, 1.0, 4.0)]
+    assert all(a >= b for a, b in zip(Fs, Fs[1:]))
+    assert Fs[0] > Fs[-2]
+    # with monotone coordinates some distances are 0 while dy != 0: only a c beyond
+    # every ratio drops everything, so use the free coordinate alone there
+    Ff, gf = oracle.smooth(x, y, eps, norm, M=0.3, Mk=Mk, p=2.0, prune=1e9)
+    assert Ff == pytest.approx(float(np.sum(eps ** 2)) / 2.0, rel=1e-14)
+    np.testing.assert_allclose(gf, eps, rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("norm", NORMS)
+def test_prune_gradient_matches_finite_differences(norm):
+    # the dropped set depends on y only, so F stays piecewise quadratic in eps
+    x, y, rng = _data(30 + norm, 40, 3)
+    mon = np.array([0, 1, 0], np.int8)
+    Mk = (0.2 + rng.random(40)).astype(np.float32)
+    eps = 0.3 * rng.standard_normal(40)
+    F, g = oracle.smooth(x, y, eps, norm, Mk=Mk, p=1.5, mon=mon, prune=1 / 3)
+    F0, _ = oracle.smooth(x, y, eps, norm, Mk=Mk, p=1.5, mon=mon)
+    assert F < F0
+    h = 1e-6
+    fd = np.empty(40)
+    for i in range(40):
+        ep, em = eps.copy(), eps.copy()
+        ep[i] += h
+        em[i] -= h
+        fd[i] = (oracle.smooth(x, y, ep, norm, Mk=Mk, p=1.5, mon=mon, prune=1 / 3)[0]
+                 - oracle.smooth(x, y, em, norm, Mk=Mk, p=1.5, mon=mon, prune=1 / 3)[0]) / (2 * h)
+    np.testing.assert_allclose(g, fd, rtol=1e-5, atol=1e-6)
