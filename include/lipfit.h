@@ -295,6 +295,13 @@ lip_status lip_fit_eval_steps(const lip_metric *metric, const float *x, const fl
  * in lip_consistency).  One fused pass over all pairs, no distance matrix.
  *   eps [n]      DEVICE FP32 corrections
  *   p            penalty parameter > 0 (finite)
+ *   prune        pre-screening of Sec. 5: 0 keeps every pair; c > 0 drops the
+ *                ordered pair (i, k) from both sums when, on the given y,
+ *                y_i - y_k <= c M_k dist_up(x^i, x^k) and
+ *                y_k - y_i <= c M_k dist_lo(x^i, x^k)  (the paper uses c = 1/3).
+ *                Decided as in FP64 with the consistency check's distances
+ *                and (c M_k) dist, so the dropped set is exact.  Negative or
+ *                non-finite: LIP_E_VALUE.
  *   F [1]        DEVICE FP64 output, optional: the objective
  *   grad [n]     DEVICE FP32 output, optional: dF / d eps
  * Pair terms are FP32, sums FP64 in a fixed order (repeated calls give
@@ -302,7 +309,7 @@ lip_status lip_fit_eval_steps(const lip_metric *metric, const float *x, const fl
  * (L-BFGS); y + eps is then the smoothed data.  Needs ws. */
 lip_status lip_smooth_objective(const lip_metric *metric, const float *x, const float *y,
                                 int64_t n, float M, const float *Mk, const float *eps, double p,
-                                double *F, float *grad, void *ws, size_t ws_bytes,
+                                double prune, double *F, float *grad, void *ws, size_t ws_bytes,
                                 uint32_t flags, lip_stream stream);
 
 /* ---- many independent fits in one launch ------------------------------------

@@ -59,7 +59,7 @@ _SIGS = {
     "lip_local_steps": (i32, [P, P, P, i64, P, i32, P, P, P, P, sz, u32, P]),
     "lip_fit_eval_steps": (i32, [P, P, P, i64, P, P, i64, P, P, P, P, P, P, sz, u32, P]),
     "lip_fit_eval_k": (i32, [P, P, P, i64, f32, P, i32, P, P, i64, P, P, P, P, sz, u32, P]),
-    "lip_smooth_objective": (i32, [P, P, P, i64, f32, P, P, f64, P, P, P, sz, u32, P]),
+    "lip_smooth_objective": (i32, [P, P, P, i64, f32, P, P, f64, f64, P, P, P, sz, u32, P]),
     "lip_plan_create": (i32, [P, P, i32, u32, P]),
     "lip_plan_execute": (i32, [P, P]),
     "lip_plan_destroy": (i32, [P]),

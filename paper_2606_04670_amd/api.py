@@ -336,9 +336,11 @@ class StepModel:
 
 
 def smooth_objective(x, y, eps, metric: Metric, M=None, Mk=None, p: float = 1.0,
-                     want_F: bool = True, want_grad: bool = True):
+                     prune: float = 0.0, want_F: bool = True, want_grad: bool = True):
     """Eq. (7) at the corrections eps: (F float64 [1] tensor or None,
-    grad float32 [n] tensor or None)."""
+    grad float32 [n] tensor or None).  prune = c > 0 leaves out the pairs of
+    the Sec. 5 pre-screening (data within c times their Lipschitz allowance;
+    the paper's c is 1/3)."""
     x, y, M, Mk, dev = _prep(x, y, M, Mk)
     eps = _f32(eps, "eps", dev)
     n = x.shape[0]
@@ -347,13 +349,14 @@ def smooth_objective(x, y, eps, metric: Metric, M=None, Mk=None, p: float = 1.0,
     lib = L.load()
     ws = workspace(dev, lib.lip_workspace_size(n, 0, metric.d, 0))
     st = lib.lip_smooth_objective(metric.ref(), _ptr(x), _ptr(y), n, M, _ptr(Mk), _ptr(eps),
-                                  float(p), _ptr(F), _ptr(g), _ptr(ws), ws.numel(), 0,
+                                  float(p), float(prune), _ptr(F), _ptr(g), _ptr(ws),
+                                  ws.numel(), 0,
                                   _stream(dev))
     L.check("lip_smooth_objective", st)
     return F, g
 
 
-def smooth_lipschitz(x, y, metric: Metric, M=None, Mk=None, p: float = 1.0,
+def smooth_lipschitz(x, y, metric: Metric, M=None, Mk=None, p: float = 1.0, prune: float = 0.0,
                      max_iter: int = 200, tolerance_grad: float = 1e-7, history_size: int = 20):
     """Smoothed data y + eps minimising Eq. (7) with torch's L-BFGS as the
     unconstrained minimiser (the paper's choice); every objective and
@@ -367,12 +370,13 @@ def smooth_lipschitz(x, y, metric: Metric, M=None, Mk=None, p: float = 1.0,
                             line_search_fn="strong_wolfe")
 
     def closure():
-        F, g = smooth_objective(x, y, eps.detach(), metric, M=M, Mk=Mk, p=p)
+        F, g = smooth_objective(x, y, eps.detach(), metric, M=M, Mk=Mk, p=p, prune=prune)
         eps.grad = g
         return F.to(torch.float32).reshape(())
 
     opt.step(closure)
-    F, _ = smooth_objective(x, y, eps.detach(), metric, M=M, Mk=Mk, p=p, want_grad=False)
+    F, _ = smooth_objective(x, y, eps.detach(), metric, M=M, Mk=Mk, p=p, prune=prune,
+                            want_grad=False)
     e = eps.detach()
     return y + e, e, F
 

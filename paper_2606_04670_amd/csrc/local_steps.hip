@@ -83,13 +83,6 @@ __global__ void knot_pick_kernel(const unsigned long long *keys, Ranks rk, int K
     if (j < K) knots[j] = from_bits(keys[rk.r[j]]);
 }
 
-__device__ inline float round_up_f32(double v)
-{
-    float f = (float)v;
-    if ((double)f < v) f = nextafterf(f, __builtin_inff());
-    return f;
-}
-
 // Merge of the builder's chunk partials: nearest distance (min), its slope
 // (max over the chunks that attain the min), the knot maxima (max); then the
 // table: V_0, V_s = max(v_s, V_0) (a knot below d1 adds nothing beyond the

@@ -18,6 +18,14 @@ namespace lip {
 constexpr int kMaxKnots = 8;
 constexpr int kStepMaxChunks = 8;
 
+// The smallest float >= v.
+__device__ inline float round_up_f32(double v)
+{
+    float f = (float)v;
+    if ((double)f < v) f = nextafterf(f, __builtin_inff());
+    return f;
+}
+
 struct StepArgs {
     DsArgs ds;                 // staged data (X, n, npad), weights, free/monotone selectors, chunks
     int32_t K;                 // number of knots

@@ -219,13 +219,16 @@ def test_smooth_entry_point_validation(L):
     lib = L.load()
     m, keep = _metric(L)
 
-    def sm(n=10, M=1.0, eps=FAKE, p=1.0, ws=FAKE, ws_bytes=1 << 30, flags=0):
-        return lib.lip_smooth_objective(ctypes.byref(m), FAKE, FAKE, n, M, None, eps, p, FAKE,
-                                        FAKE, ws, ws_bytes, flags, None)
+    def sm(n=10, M=1.0, eps=FAKE, p=1.0, prune=0.0, ws=FAKE, ws_bytes=1 << 30, flags=0):
+        return lib.lip_smooth_objective(ctypes.byref(m), FAKE, FAKE, n, M, None, eps, p, prune,
+                                        FAKE, FAKE, ws, ws_bytes, flags, None)
     assert sm(n=0) == L.LIP_E_SHAPE
     assert sm(M=-1.0) == L.LIP_E_VALUE
     assert sm(p=0.0) == L.LIP_E_VALUE
     assert sm(p=float("inf")) == L.LIP_E_VALUE
+    assert sm(prune=-0.5) == L.LIP_E_VALUE
+    assert sm(prune=float("nan")) == L.LIP_E_VALUE
+    assert sm(prune=float("inf")) == L.LIP_E_VALUE
     assert sm(eps=None) == L.LIP_E_ARG
     assert sm(ws_bytes=16) == L.LIP_E_WORKSPACE
     assert sm(flags=L.LIP_FLAG_BF16) == L.LIP_E_ARG

@@ -11,6 +11,11 @@ so the tolerances are
     |grad_gpu_i - grad_orc_i| <= 2 delta c_i + 2^-17 (|grad_i| + row_abs_i)
 with c_i the terms moving eps_i that are above -delta and row_abs_i the sum
 of their gradient magnitudes (oracle.smooth_scale).
+
+With the pre-screening of Sec. 5 the dropped pairs are a yes / no answer and
+must be the oracle's exactly: a wrong one moves F by a whole pair term.  The
+cases use corrections large enough that many dropped pairs would be active,
+and data on a grid where many pairs sit exactly on the threshold.
 """
 import numpy as np
 import pytest
@@ -35,8 +40,8 @@ def _t(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
 
 
-def _check(p, eps, F_gpu, g_gpu, M, Mk, pen, label):
-    F, g = oracle.smooth(p.x, p.y, eps, p.norm, M=M, Mk=Mk, p=pen, mon=p.mon, w=p.w)
+def _check(p, eps, F_gpu, g_gpu, M, Mk, pen, label, prune=0.0):
+    F, g = oracle.smooth(p.x, p.y, eps, p.norm, M=M, Mk=Mk, p=pen, mon=p.mon, w=p.w, prune=prune)
     z = np.abs(p.y.astype(np.float64) + eps).max()
     span = (p.x.max(0) - p.x.min(0)).astype(np.float64) * p.w
     dmax = {1: span.sum(), 2: np.sqrt((span ** 2).sum()), 3: span.max()}[p.norm]
@@ -44,7 +49,7 @@ def _check(p, eps, F_gpu, g_gpu, M, Mk, pen, label):
     S = z + mmax * dmax
     delta = (p.d + 12) * 2.0 ** -24 * S
     A, row_abs, row_cnt = oracle.smooth_scale(p.x, p.y, eps, p.norm, delta, M=M, Mk=Mk,
-                                              mon=p.mon, w=p.w)
+                                              mon=p.mon, w=p.w, prune=prune)
     tolF = 2 * delta * A + row_cnt.sum() / 2 * delta ** 2 + 2.0 ** -17 * F
     assert abs(F_gpu - F) <= tolF, f"{label}: F gpu={F_gpu!r} oracle={F!r} tol={tolF:g}"
     tolg = 2 * delta * row_cnt + 2.0 ** -17 * (np.abs(g) + row_abs)
@@ -140,3 +145,110 @@ def test_monotone_local_full_size_objective(lf):
     q.x, q.y, q.norm, q.mon, q.w, q.d = xs, ys, 1, p.mon, np.ones(4), 4
     _check(q, np.zeros(2000), Fs.item(), gs.cpu().numpy().astype(np.float64), 2.0, None, 1.0,
            "monotone_local subset")
+
+
+# ---- pre-screening (Sec. 5) -----------------------------------------------------
+
+
+@pytest.mark.parametrize("norm", [1, 2, 3])
+@pytest.mark.parametrize("seed,n,d,mon,local,weighted", CASES)
+def test_smooth_objective_pruned_parity(lf, norm, seed, n, d, mon, local, weighted):
+    p = W.random_problem(700 + seed, n=n, q=1, d=d, norm=norm, mon=np.array(mon, np.int8),
+                         local=local, weighted=weighted, M=0.8)
+    rng = W.rng_for(701, seed)
+    eps = (0.3 * rng.standard_normal(n)).astype(np.float32).astype(np.float64)
+    pen, c = 0.7, 1.0 / 3.0
+    M = np.float32(p.M)
+    met = lf.Metric(d, norm, mon=p.mon, w=p.w)
+    mk = None if p.Mk is None else _t(p.Mk)
+    F, g = lf.smooth_objective(_t(p.x), _t(p.y), _t(eps.astype(np.float32)), met,
+                               M=None if mk is not None else p.M, Mk=mk, p=pen, prune=c)
+    torch.cuda.synchronize()
+    Fo = _check(p, eps, F.item(), g.cpu().numpy().astype(np.float64), M, p.Mk, pen,
+                f"pruned n={n} d={d} norm={norm}", prune=c)
+    if n > 100:
+        # the pre-screening dropped pairs that would have counted
+        F_all, _ = oracle.smooth(p.x, p.y, eps, norm, M=M, Mk=p.Mk, p=pen, mon=p.mon, w=p.w)
+        assert Fo < F_all
+
+
+def _grid_problem(seed, n, d, norm, mon):
+    """Integer coordinates in [0, 4]^d and values on a grid of 1/4: with M = 1
+    and c = 1/4, c M dist and |y_i - y_k| are exact multiples of 1/4 (l1, linf;
+    l2 where the distance is an integer), so many pairs sit on the threshold."""
+    rng = W.rng_for(seed)
+
+    class _P:
+        pass
+    p = _P()
+    p.x = rng.integers(0, 5, size=(n, d)).astype(np.float32)
+    p.y = (0.25 * rng.integers(-8, 9, size=n)).astype(np.float32)
+    p.norm, p.d, p.mon, p.w = norm, d, np.array(mon, np.int8), np.ones(d)
+    return p
+
+
+@pytest.mark.parametrize("norm", [1, 2, 3])
+@pytest.mark.parametrize("d,mon,local", [(1, [0], False), (2, [0, 0], False), (2, [1, 0], True),
+                                         (3, [0, -1, 1], False)])
+def test_smooth_pruned_ties_on_a_grid(lf, norm, d, mon, local):
+    n = 900
+    p = _grid_problem(710 + d, n, d, norm, mon)
+    rng = W.rng_for(711, d)
+    eps = (0.25 * rng.integers(-6, 7, size=n)).astype(np.float64)
+    Mk = (0.25 * rng.integers(2, 7, size=n)).astype(np.float32) if local else None
+    c, pen = 0.25, 1.0
+    # ties at the threshold are common here (y_i - y_k = c M_k dist exactly)
+    x64, y64 = p.x.astype(np.float64), p.y.astype(np.float64)
+    i, k = rng.integers(0, n, 4000), rng.integers(0, n, 4000)
+    dist = {1: np.abs(x64[i] - x64[k]).sum(1), 2: np.sqrt(((x64[i] - x64[k]) ** 2).sum(1)),
+            3: np.abs(x64[i] - x64[k]).max(1)}[norm]
+    mk = 1.0 if Mk is None else Mk[k].astype(np.float64)
+    assert np.sum(np.abs(y64[i] - y64[k]) == c * mk * dist) > 20
+    met = lf.Metric(d, norm, mon=p.mon)
+    F, g = lf.smooth_objective(_t(p.x), _t(p.y), _t(eps.astype(np.float32)), met,
+                               M=None if Mk is not None else 1.0,
+                               Mk=None if Mk is None else _t(Mk), p=pen, prune=c)
+    torch.cuda.synchronize()
+    _check(p, eps, F.item(), g.cpu().numpy().astype(np.float64), 1.0, Mk, pen,
+           f"grid ties d={d} norm={norm}", prune=c)
+
+
+def test_smooth_pruned_repeatable_and_zero_is_all_pairs(lf):
+    p = W.random_problem(720, n=3000, q=1, d=4, norm=2, mon=np.array([1, 0, 1, 0], np.int8),
+                         M=0.5)
+    met = lf.Metric(4, 2, mon=p.mon)
+    eps = _t((0.2 * W.rng_for(721).standard_normal(3000)).astype(np.float32))
+    F1, g1 = lf.smooth_objective(_t(p.x), _t(p.y), eps, met, M=p.M, p=1.0, prune=0.3)
+    F2, g2 = lf.smooth_objective(_t(p.x), _t(p.y), eps, met, M=p.M, p=1.0, prune=0.3)
+    assert F1.item() == F2.item() and torch.equal(g1, g2)
+    F3, g3 = lf.smooth_objective(_t(p.x), _t(p.y), eps, met, M=p.M, p=1.0, prune=0.0)
+    F4, g4 = lf.smooth_objective(_t(p.x), _t(p.y), eps, met, M=p.M, p=1.0)
+    assert F3.item() == F4.item() and torch.equal(g3, g4)
+    assert F1.item() < F3.item()
+
+
+def test_monotone_local_full_size_pruned(lf):
+    """d = 4, N = 1e5 with the paper's c = 1/3 and per-datum constants: the
+    full-size call, then a 2000-datum subset end to end against the oracle."""
+    p = W.monotone_local(norm=2)
+    met = lf.Metric(4, 2, mon=p.mon)
+    eps = _t((0.2 * W.rng_for(730).standard_normal(p.n)).astype(np.float32))
+    mk = _t(p.Mk)
+    F, g = lf.smooth_objective(_t(p.x), _t(p.y), eps, met, Mk=mk, p=1.0, prune=1 / 3)
+    F0, _ = lf.smooth_objective(_t(p.x), _t(p.y), eps, met, Mk=mk, p=1.0)
+    torch.cuda.synchronize()
+    assert np.isfinite(F.item()) and 0 < F.item() < F0.item()
+    assert torch.isfinite(g).all()
+    sub = W.rng_for(731).choice(p.n, 2000, replace=False)
+    xs, ys, ms = p.x[sub], p.y[sub], p.Mk[sub]
+    es = (0.2 * W.rng_for(732).standard_normal(2000)).astype(np.float32).astype(np.float64)
+    Fs, gs = lf.smooth_objective(_t(xs), _t(ys), _t(es.astype(np.float32)), met, Mk=_t(ms),
+                                 p=1.0, prune=1 / 3)
+    torch.cuda.synchronize()
+
+    class _P:
+        pass
+    q = _P()
+    q.x, q.y, q.norm, q.mon, q.w, q.d = xs, ys, 2, p.mon, np.ones(4), 4
+    _check(q, es, Fs.item(), gs.cpu().numpy().astype(np.float64), 0.0, ms, 1.0,
+           "monotone_local subset, pruned", prune=1 / 3)
