@@ -307,6 +307,11 @@ def extra_smooth(lf, W, torch, dev, base, x, y, norms, reps=3):
     return out
 
 
+def progress(msg):
+    """One line per finished stage on stderr (stdout carries only the JSON line)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -352,6 +357,7 @@ def main():
     for _ in range(a.warmup):
         one_step()
     torch.cuda.synchronize()
+    progress(f"{a.warmup} warm-up steps done")
 
     # timed region: K whole steps; HIP events on the launch stream bracket
     # every stage of every step
@@ -364,6 +370,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / a.steps
+    progress(f"{a.steps} timed steps done: {ms_step:.1f} ms per step")
     stage_ms = {nm: {s: float(np.mean([evs[k][nm][s][0].elapsed_time(evs[k][nm][s][1])
                                         for k in range(a.steps)])) for s in stages}
                 for nm in norms}
@@ -411,21 +418,27 @@ def main():
                "cores": oracle.num_threads(), "kind": "oracle",
                "sample": f"forward bounds (FP64) of {qs} seeded queries x all {N} data, "
                          f"norms {'/'.join(norms)}, {tc1 - tc0:.1f} s"}
+        progress(f"CPU baseline done ({tc1 - tc0:.1f} s)")
 
     extras = None
     if not a.no_extras:
-        extras = {"bf16_vs_fp32": extra_bf16(lf, W, torch, dev),
-                  "batched_vs_per_set": extra_batched(lf, W, torch, dev),
-                  "step_function_Mk": extra_steps(
-                      lf, W, torch, dev, base, x, y, xq, norms,
-                      {nm: stage_ms[nm]["forward"] for nm in norms}),
-                  "smoothing_objective": extra_smooth(lf, W, torch, dev, base, x, y, norms),
-                  "k_best_bounds": extra_topk(lf, W, torch, dev, base, x, y, xq, norms,
-                                             {nm: stage_ms[nm]["forward"] for nm in norms}),
-                  "regional_monotonicity": extra_regional(
-                      lf, W, torch, dev, base, x, y, xq, norms,
-                      {nm: stage_ms[nm]["forward"] for nm in norms}),
-                  "other_configs": extra_other_configs(lf, W, torch, dev, base, x, y, norms)}
+        fwd = {nm: stage_ms[nm]["forward"] for nm in norms}
+        runs = [("bf16_vs_fp32", lambda: extra_bf16(lf, W, torch, dev)),
+                ("batched_vs_per_set", lambda: extra_batched(lf, W, torch, dev)),
+                ("step_function_Mk",
+                 lambda: extra_steps(lf, W, torch, dev, base, x, y, xq, norms, fwd)),
+                ("smoothing_objective",
+                 lambda: extra_smooth(lf, W, torch, dev, base, x, y, norms)),
+                ("k_best_bounds",
+                 lambda: extra_topk(lf, W, torch, dev, base, x, y, xq, norms, fwd)),
+                ("regional_monotonicity",
+                 lambda: extra_regional(lf, W, torch, dev, base, x, y, xq, norms, fwd)),
+                ("other_configs",
+                 lambda: extra_other_configs(lf, W, torch, dev, base, x, y, norms))]
+        extras = {}
+        for name, run in runs:
+            extras[name] = run()
+            progress(f"extra {name} done")
 
     rec = {
         "metric": METRIC, "value": value, "unit": "pair-evals/s", "n_gpus": 1,
