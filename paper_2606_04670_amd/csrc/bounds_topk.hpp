@@ -8,8 +8,9 @@
 // Each query keeps its kTopK best values per bound in registers, sorted.  A
 // candidate enters only if it beats the current kTopK-th value; the test is
 // one compare per bound and pair, and the insertion (a min into the last slot
-// and one compare-exchange pass) runs only when some lane of the wave needs
-// it.  The k values form a multiset, so no index rule is needed; records past
+// and one compare-exchange pass) runs per candidate only when some lane of
+// the wave needs it (a wave-uniform branch: after the first data, few
+// candidates improve any list).  The k values form a multiset, so no index rule is needed; records past
 // n (the staging's padding repeats the last datum) are masked, so every datum
 // counts once.  Split chunks write their sorted lists; a merge kernel takes
 // the kTopK smallest / largest of all of them.
@@ -95,34 +96,23 @@ __global__ void __launch_bounds__(256) bounds_topk_kernel(TopkArgs A)
     for (int64_t g0 = c0; g0 < c1; g0 += G) {
         float v[G * S];
         load_group<D>(base + g0 * S, v);
-        float u[G][R], l[G][R];
-        bool need = false;
 #pragma unroll
         for (int c = 0; c < G; ++c) {
             float xk[D];
 #pragma unroll
             for (int j = 0; j < D; ++j) xk[j] = v[c * S + j];
-            const bool in = g0 + c < c1;  // wave-uniform
+            if (g0 + c >= c1) break;  // wave-uniform
 #pragma unroll
             for (int r = 0; r < R; ++r) {
+                float u, l;
                 pair_bounds<D, DM, NORM>(qv[r], qm[r], xk, v[c * S + Rec<D>::Y],
-                                         v[c * S + Rec<D>::M], v[c * S + Rec<D>::YU], big,
-                                         u[c][r], l[c][r]);
-                if (!in) {
-                    u[c][r] = __builtin_inff();
-                    l[c][r] = -__builtin_inff();
-                }
-                need = need || u[c][r] < U[r][kTopK - 1] || l[c][r] > L[r][kTopK - 1];
+                                         v[c * S + Rec<D>::M], v[c * S + Rec<D>::YU], big, u, l);
+                // insert only where some lane of the wave improves its list
+                if (__builtin_amdgcn_ballot_w64(u < U[r][kTopK - 1]) != 0)
+                    topk_insert_up(U[r], u);
+                if (__builtin_amdgcn_ballot_w64(l > L[r][kTopK - 1]) != 0)
+                    topk_insert_lo(L[r], l);
             }
-        }
-        if (__builtin_amdgcn_ballot_w64(need) != 0) {
-#pragma unroll
-            for (int c = 0; c < G; ++c)
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    topk_insert_up(U[r], u[c][r]);
-                    topk_insert_lo(L[r], l[c][r]);
-                }
         }
     }
 #pragma unroll
