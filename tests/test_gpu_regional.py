@@ -31,6 +31,9 @@ CASES = [
     (4, 5, 100, [5, 2, 0], False, False),
     (5, 800, 129, [2, 3, 4, 5, 0, 1, -1, 2], True, True),
     (6, 513, 64, [2, 3, 4, 5] * 4, False, False),
+    # free coordinates first in the kernel's order, shared by both distances
+    (7, 900, 333, [4, 0, 5, 0], True, False),
+    (8, 700, 200, [0, 2, 0, 0, 3, 0, 1, 0, 0, 0, 5, 0, 0, -1, 0, 4], False, True),
 ]
 
 
