@@ -95,7 +95,7 @@ lip_status run_bounds_reg(const MetricInfo &mi, const float *x, const float *y, 
            (int64_t)nc * 2 * q <= kMaxPartials)
         nc *= 2;
     int64_t cols = (n + nc - 1) / nc;
-    cols = (cols + 63) / 64 * 64;
+    cols = (cols + kRegTile - 1) / kRegTile * kRegTile;
     A.chunk_cols = cols;
     A.n_chunks = (int)((n + cols - 1) / cols);
     if (A.n_chunks > 1) {

@@ -19,8 +19,11 @@
 //
 // A lane owns R queries, a wave 64 R queries and one data chunk; records
 // [w x_free.. | c_ND, c_NI per restricted coordinate | y | M_k] come four at
-// a time through scalar loads; the first index of the running min / max is
-// kept per pair (strict comparisons, data in ascending order), chunk
+// a time through scalar loads.  The inner loop keeps only the running min /
+// max; at the end of every tile of kRegTile records a query notes the tile if
+// its value strictly improved there, and afterwards re-scans that one tile
+// with the same arithmetic for the first index that attains the final value
+// (so ties resolve to the lowest index, as in the definition).  Chunk
 // partials go through the bound path's combine.
 #pragma once
 
@@ -45,6 +48,8 @@ struct RegArgs {
     float *part_v;
     int32_t *part_i;
 };
+
+constexpr int kRegTile = 64;  // records per tile; chunks are whole tiles
 
 constexpr int reg_rows(int D) { return rows_for_dim(D) / 2 > 0 ? rows_for_dim(D) / 2 : 1; }
 
@@ -108,8 +113,11 @@ __global__ void __launch_bounds__(256) bounds_reg_kernel(RegArgs A)
     const int64_t q0 = qb * 64 * R;
     if (q0 >= A.q) return;
     const int lane = threadIdx.x & 63;
-    float qv[R][E], hu[R], hl[R];
-    int au[R], al[R];
+    float qv[R][E], hu[R], hl[R], pu[R], pl[R];
+    int tu[R], tl[R];
+    const int64_t c0 = (int64_t)chunk * A.chunk_cols;
+    int64_t c1 = c0 + A.chunk_cols;
+    c1 = c1 < A.n ? c1 : A.n;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         int64_t j = q0 + r * 64 + lane;
@@ -124,13 +132,18 @@ __global__ void __launch_bounds__(256) bounds_reg_kernel(RegArgs A)
         }
         hu[r] = __builtin_inff();
         hl[r] = -__builtin_inff();
-        au[r] = -1;
-        al[r] = -1;
+        pu[r] = hu[r];
+        pl[r] = hl[r];
+        tu[r] = (int)(c0 / kRegTile);
+        tl[r] = tu[r];
     }
-    const int64_t c0 = (int64_t)chunk * A.chunk_cols;
-    int64_t c1 = c0 + A.chunk_cols;
-    c1 = c1 < A.n ? c1 : A.n;
     const cfloat_ptr rec = as_const(A.rec);
+    // min / max as medians with an opaque infinity: no re-quieting of the
+    // running values each pair
+    const float big = opaque_inf(), nbig = -big;
+    constexpr int gpt = kRegTile / G;  // groups per tile
+    int left = gpt;
+    int t = (int)(c0 / kRegTile);
 #pragma unroll 1
     for (int64_t g0 = c0; g0 < c1; g0 += G) {
         float v[G * S];
@@ -138,25 +151,53 @@ __global__ void __launch_bounds__(256) bounds_reg_kernel(RegArgs A)
         for (int e = 0; e < G * S; ++e) v[e] = rec[g0 * S + e];
 #pragma unroll
         for (int c = 0; c < G; ++c) {
-            const int64_t k = g0 + c;
-            if (k >= c1) break;  // wave-uniform
+            if (g0 + c >= c1) break;  // wave-uniform
             const float *xk = v + c * S;
             const float yk = xk[E], mk = xk[E + 1];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                float tu, tl;
-                reg_dist<D, DF, NORM>(qv[r], xk, tu, tl);
-                const float u = fmaf(mk, tu, yk), l = fmaf(-mk, tl, yk);
-                if (u < hu[r]) {
-                    hu[r] = u;
-                    au[r] = (int)k;
-                }
-                if (l > hl[r]) {
-                    hl[r] = l;
-                    al[r] = (int)k;
-                }
+                float du, dl;
+                reg_dist<D, DF, NORM>(qv[r], xk, du, dl);
+                hu[r] = __builtin_amdgcn_fmed3f(hu[r], fmaf(mk, du, yk), nbig);
+                hl[r] = __builtin_amdgcn_fmed3f(hl[r], fmaf(-mk, dl, yk), big);
             }
         }
+        if (--left == 0 || g0 + G >= c1) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                tu[r] = hu[r] < pu[r] ? t : tu[r];
+                tl[r] = hl[r] > pl[r] ? t : tl[r];
+                pu[r] = hu[r];
+                pl[r] = hl[r];
+            }
+            left = gpt;
+            ++t;
+        }
+    }
+    // first attaining index: descending re-scan of the last improving tile
+    int au[R], al[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t bu = (int64_t)tu[r] * kRegTile, bl = (int64_t)tl[r] * kRegTile;
+        const int64_t eu = bu + kRegTile < c1 ? bu + kRegTile : c1;
+        const int64_t el = bl + kRegTile < c1 ? bl + kRegTile : c1;
+        int iu = -1, il = -1;
+#pragma unroll 1
+        for (int64_t k = eu - 1; k >= bu; --k) {
+            const float *xk = A.rec + k * S;
+            float du, dl;
+            reg_dist<D, DF, NORM>(qv[r], xk, du, dl);
+            iu = fmaf(xk[E + 1], du, xk[E]) == hu[r] ? (int)k : iu;
+        }
+#pragma unroll 1
+        for (int64_t k = el - 1; k >= bl; --k) {
+            const float *xk = A.rec + k * S;
+            float du, dl;
+            reg_dist<D, DF, NORM>(qv[r], xk, du, dl);
+            il = fmaf(-xk[E + 1], dl, xk[E]) == hl[r] ? (int)k : il;
+        }
+        au[r] = iu;
+        al[r] = il;
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
