@@ -104,7 +104,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-queries", type=int, default=8192,
+    ap.add_argument("--cpu-queries", type=int, default=65536,
                     help="queries per norm in the oracle's CPU-baseline sample")
     ap.add_argument("--norms", default="l1,l2,linf")
     ap.add_argument("--no-extras", action="store_true",
