@@ -62,3 +62,42 @@ def test_regional_kinds_rejected_elsewhere(lf):
         lf.consistency(_t(p.x), _t(p.y), met, M=1.0)
     with pytest.raises(lf.LipError):
         lf.fit_eval(_t(p.x), _t(p.y), _t(p.xq), met, M=1.0, bf16=True)
+
+
+@pytest.mark.parametrize("norm", [1, 2, 3])
+def test_monotone_local_full_size_sampled(lf, norm):
+    """d = 4, N = 1e5, Q = 1e6, per-datum M_k, coordinates 1 / 3 as cases III / IV
+    on [0.3, 0.6] (the configuration the benchmark times): every query on the GPU,
+    a seeded sample of 512 plus the first and last against the oracle, and the same
+    outputs on a second call."""
+    p = W.monotone_local(norm=norm)
+    kind = np.array([4, 0, 5, 0], np.int8)
+    a = np.full(4, 0.3, np.float32)
+    b = np.full(4, 0.6, np.float32)
+    met = lf.Metric(4, norm, mon=kind, a=a, b=b)
+    args = (_t(p.x), _t(p.y), _t(p.xq), met)
+    out = lf.fit_eval(*args, Mk=_t(p.Mk))
+    torch.cuda.synchronize()
+    gpu = {k: v.cpu().numpy() for k, v in out.items()}
+    qidx = np.sort(W.rng_for(870, norm).choice(p.q, 512, replace=False))
+    qidx = np.concatenate([[0, p.q - 1], qidx])
+    print(check_bounds_regional(p, gpu, kind, a.astype(np.float64), b.astype(np.float64),
+                                qidx=qidx, label=f"regional monotone_local norm={norm}"))
+    out2 = lf.fit_eval(*args, Mk=_t(p.Mk))
+    for k in out:
+        assert torch.equal(out[k], out2[k]), k
+
+
+@pytest.mark.parametrize("norm", [1, 2, 3])
+def test_regional_single_datum(lf, norm):
+    p = W.random_problem(880 + norm, n=1, q=300, d=3, norm=norm)
+    kind = np.array([2, 0, 5], np.int8)
+    a = np.array([0.2, 0.0, 0.4], np.float32)
+    b = np.array([0.7, 0.0, 0.5], np.float32)
+    met = lf.Metric(3, norm, mon=kind, a=a, b=b)
+    out = lf.fit_eval(_t(p.x), _t(p.y), _t(p.xq), met, M=p.M)
+    torch.cuda.synchronize()
+    gpu = {k: v.cpu().numpy() for k, v in out.items()}
+    assert (gpu["arg_up"] == 0).all() and (gpu["arg_lo"] == 0).all()
+    print(check_bounds_regional(p, gpu, kind, a.astype(np.float64), b.astype(np.float64),
+                                label=f"regional n=1 norm={norm}"))
