@@ -29,11 +29,15 @@
 // index order (the consistency check's arithmetic), products left to right.
 // The FP32 pass decides all but a sliver of the pairs: with
 //     m = max(fma(-cM_k, du32, dy32), fma(-cM_k, dl32, -dy32))
-// the exact quantity max(DY - cM du, -DY - cM dl) differs from m by at most
-//     tol = cM (2^-16 max(du32, dl32) + 2 alpha) + 2^-16 |dy32|
-// (FP32 distance error rho t + alpha with rho = 2^-18 and alpha as in the
-// step-function forward, one rounding each of dy, cM and the fma, with a
-// factor 2 of margin).  A pair with |m| <= tol is deferred: if some lane of
+// each of e_u = DY - cM du and e_l = -DY - cM dl is within
+//     2^-17 (|DY| + cM t) + cM alpha
+// of its FP32 value (FP32 distance error rho t + alpha with rho = 2^-18 and
+// alpha as in the step-function forward; one rounding each of dy, cM and the
+// fma).  With cM t = DY - e_u that is at most 2^-16 |dy| + 2^-17 |e| + cM
+// alpha, so |e| > tol = 2^-14 |dy32| + 2 cM alpha fixes the sign of e, and
+// |m| > tol fixes the sign of m (if m > tol, the larger one is certainly
+// positive; if m < -tol, both are certainly negative).  A pair with
+// |m| <= tol is deferred: if some lane of
 // the wave has one, the wave decides those pairs in FP64 and adds the kept
 // ones right after the column, so every row's sum keeps its column order.
 // (The diagonal, m = 0, is always deferred and dropped: its terms are zero.)
@@ -109,13 +113,15 @@ __device__ __forceinline__ void smooth_column(const SmoothArgs &A, const float *
                                               int64_t r0, int lane, const float (&xr)[R][D],
                                               const float (&zr)[R], const float (&mr)[R],
                                               const float (&yr)[R], const float (&cr)[R],
-                                              float s_alpha2, float (&f32)[R], float (&g32)[R])
+                                              const float (&kr)[R], float s_alpha2,
+                                              float (&f32)[R], float (&g32)[R])
 {
     const float zk = xk[D], mk = xk[D + 1];
-    float yk = 0.0f, ck = 0.0f;
+    float yk = 0.0f, ck = 0.0f, ka = 0.0f;
     if constexpr (PRUNE) {
         yk = xk[D + 2];
         ck = xk[D + 3];
+        ka = ck * s_alpha2;  // the absolute part of the datum's tolerance
     }
     unsigned defer = 0u;
 #pragma unroll
@@ -132,16 +138,13 @@ __device__ __forceinline__ void smooth_column(const SmoothArgs &A, const float *
         }
         if constexpr (PRUNE) {
             const float dy = yr[r] - yk;
-            const float dmax = DM == 0 ? du : fmaxf(du, dl);
-            const float sd = fmaf(0x1p-16f, dmax, s_alpha2);
-            const float ty = fabsf(dy) * 0x1p-16f;
             const float m1 = fmaxf(fmaf(-ck, du, dy), fmaf(-ck, dl, -dy));
-            bool u = fabsf(m1) <= fmaf(ck, sd, ty);
+            bool u = fabsf(m1) <= fmaf(0x1p-14f, fabsf(dy), ka);
             bool keep1 = m1 > 0.0f;
             bool keep2 = true;
             if constexpr (LOCAL) {
                 const float m2 = fmaxf(fmaf(-cr[r], dl, -dy), fmaf(-cr[r], du, dy));
-                u = u || fabsf(m2) <= fmaf(cr[r], sd, ty);
+                u = u || fabsf(m2) <= fmaf(0x1p-14f, fabsf(dy), kr[r]);
                 keep2 = m2 > 0.0f;
             }
             if (u) defer |= 1u << r;
@@ -205,7 +208,7 @@ __global__ void __launch_bounds__(256) smooth_kernel(SmoothArgs A)
     const int64_t r0 = rb * 64 * R;
     if (r0 >= A.n) return;
     const int lane = threadIdx.x & 63;
-    float xr[R][D], zr[R], mr[R], yr[R], cr[R], f32[R], g32[R];
+    float xr[R][D], zr[R], mr[R], yr[R], cr[R], kr[R], f32[R], g32[R];
     double f64[R], g64[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -223,6 +226,8 @@ __global__ void __launch_bounds__(256) smooth_kernel(SmoothArgs A)
         g64[r] = 0.0;
     }
     const float s_alpha2 = PRUNE ? 2.0f * A.alpha[0] : 0.0f;
+#pragma unroll
+    for (int r = 0; r < R; ++r) kr[r] = cr[r] * s_alpha2;
     const int64_t c0 = (int64_t)chunk * A.chunk_cols;
     int64_t c1 = c0 + A.chunk_cols;
     c1 = c1 < A.n ? c1 : A.n;
@@ -239,7 +244,7 @@ __global__ void __launch_bounds__(256) smooth_kernel(SmoothArgs A)
             for (int c = 0; c < G; ++c) {
                 if (g0 + c >= t1) break;  // wave-uniform
                 smooth_column<D, DM, NORM, LOCAL, PRUNE, R>(A, v + c * S, g0 + c, r0, lane, xr, zr,
-                                                            mr, yr, cr, s_alpha2, f32, g32);
+                                                            mr, yr, cr, kr, s_alpha2, f32, g32);
             }
         }
         // one tile of 64 columns in FP32, then into the FP64 row sums
