@@ -20,7 +20,7 @@
 // lane of the wave has fma(M_lb, t32, y) < H_up or the mirror test for H_lo
 // on a datum, the datum is skipped: its candidates cannot win.  Otherwise the
 // wave evaluates that datum exactly (FP64 distance, segment, FP32 bound) for
-// all of its queries.  The skip changes no result, ties included (a skipped
+// the queries of every row (one query per lane) in which some lane passed.  The skip changes no result, ties included (a skipped
 // candidate is >= the running minimum, and minima are strict).
 //
 // D1hi.  |t32 - t64| <= rho t64 + alpha with rho = 2^-18 (the FP32
@@ -50,10 +50,11 @@ constexpr float kStepRho = 0x1p-18f;
 template <int D>
 constexpr int step_rec_stride() { return D + kStepRec; }
 
-// Queries per lane: half of the scalar-M path's, so that a wave's queries
-// cover a smaller region (fewer data pass the lower-bound test) and the
-// exact step's FP64 registers fit.
-constexpr int step_rows(int D) { return rows_for_dim(D) / 4 > 0 ? rows_for_dim(D) / 4 : 1; }
+// Queries per lane: half of the scalar-M path's, so that the exact step's
+// FP64 registers fit.  Each row of a wave is a run of 64 consecutive queries
+// in spatial order and is voted on separately, so a row whose queries cannot
+// take a datum skips its exact evaluation.
+constexpr int step_rows(int D) { return rows_for_dim(D) / 2 > 0 ? rows_for_dim(D) / 2 : 1; }
 
 // FP32 directional distances of one pair: D coordinates, the last DM
 // monotone (increasing after the staging's sign flip), Eq. (4) for the upper
@@ -118,9 +119,11 @@ __device__ __forceinline__ float step_M_exact(const StepArgs &A, double t, doubl
     return A.Vs[(int64_t)s * A.ds.npad + k];
 }
 
-// Exact evaluation of datum k for all R queries of the lane.
+// Exact evaluation of datum k for the queries of the lane in the rows set in
+// `rows` (wave-uniform: the rows where some lane's lower-bound test passed;
+// in the others the candidate cannot win).
 template <int D, int NORM, bool MON, int R>
-__device__ __forceinline__ void step_exact(const StepArgs &A, int64_t k, float yk,
+__device__ __forceinline__ void step_exact(const StepArgs &A, int64_t k, float yk, unsigned rows,
                                            const int (&qi)[R], const float (&tu)[R],
                                            const float (&tl)[R], float (&hu)[R], float (&hl)[R],
                                            int (&au)[R], int (&al)[R])
@@ -131,6 +134,7 @@ __device__ __forceinline__ void step_exact(const StepArgs &A, int64_t k, float y
     for (int i = 0; i < D; ++i) xc[i] = A.ds.X[(int64_t)i * A.ds.npad + k];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
+        if (!((rows >> r) & 1u)) continue;
         const int64_t j = qi[r];
         double su = 0.0, sl = 0.0;
 #pragma unroll
@@ -199,16 +203,17 @@ __global__ void __launch_bounds__(256) steps_fwd32_kernel(StepArgs A)
             const float *xk = v + c * S;
             const float yk = xk[D], vl0 = xk[D + 1], vl1 = xk[D + 2], d1hi = xk[D + 3];
             float tu[R], tl[R];
-            bool any = false;
+            unsigned rows = 0u;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 step_dist32<D, DM, NORM>(qv[r], xk, tu[r], tl[r]);
                 const float mu = tu[r] > d1hi ? vl1 : vl0;
                 const float ml = tl[r] > d1hi ? vl1 : vl0;
-                any = any || fmaf(mu, tu[r], yk) < hu[r] || fmaf(-ml, tl[r], yk) > hl[r];
+                const bool need = fmaf(mu, tu[r], yk) < hu[r] || fmaf(-ml, tl[r], yk) > hl[r];
+                if (__builtin_amdgcn_ballot_w64(need) != 0) rows |= 1u << r;
             }
-            if (__builtin_amdgcn_ballot_w64(any) != 0)
-                step_exact<D, NORM, MON, R>(A, k, yk, qi, tu, tl, hu, hl, au, al);
+            if (rows != 0u)
+                step_exact<D, NORM, MON, R>(A, k, yk, rows, qi, tu, tl, hu, hl, au, al);
         }
     }
 #pragma unroll
