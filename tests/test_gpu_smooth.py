@@ -252,3 +252,29 @@ def test_monotone_local_full_size_pruned(lf):
     q.x, q.y, q.norm, q.mon, q.w, q.d = xs, ys, 2, p.mon, np.ones(4), 4
     _check(q, es, Fs.item(), gs.cpu().numpy().astype(np.float64), 0.0, ms, 1.0,
            "monotone_local subset, pruned", prune=1 / 3)
+
+
+@pytest.mark.parametrize("norm", [1, 2, 3])
+def test_smooth_pruned_degenerate_pairs(lf, norm):
+    """Zero constants (c M_k = 0: only pairs with equal values are dropped),
+    duplicated points (zero distances) and repeated values, where the filter
+    value sits exactly at the threshold and the FP64 decision takes over."""
+    n, d = 700, 3
+    rng = W.rng_for(740, norm)
+    base_x = rng.random((n // 2, d)).astype(np.float32)
+    x = np.concatenate([base_x, base_x[: n - n // 2]])            # every point twice
+    y = (0.125 * rng.integers(-4, 5, size=n)).astype(np.float32)  # many equal values
+    Mk = rng.random(n).astype(np.float32)
+    Mk[rng.random(n) < 0.3] = 0.0
+    eps = (0.25 * rng.standard_normal(n)).astype(np.float32).astype(np.float64)
+
+    class _P:
+        pass
+    p = _P()
+    p.x, p.y, p.norm, p.d, p.mon, p.w = x, y, norm, d, np.array([0, 1, 0], np.int8), np.ones(d)
+    met = lf.Metric(d, norm, mon=p.mon)
+    F, g = lf.smooth_objective(_t(x), _t(y), _t(eps.astype(np.float32)), met, Mk=_t(Mk), p=0.5,
+                               prune=0.5)
+    torch.cuda.synchronize()
+    _check(p, eps, F.item(), g.cpu().numpy().astype(np.float64), 0.0, Mk, 0.5,
+           f"pruned degenerate norm={norm}", prune=0.5)
