@@ -808,10 +808,12 @@ __global__ void __launch_bounds__(256) knn_select_kernel(DsArgs A)
 //                            the lowest index, as the partner requires).
 // Pairs that need FP64 are evaluated with cons_pair (the FP64 kernel's own
 // operation sequence).  A NaN t32 or an infinite E sends the pair to FP64.
-// Rows per lane of the FP32-filtered kernel: 4 up to d = 4, fewer above so
-// that the row coordinates and the per-pair state keep several waves per
-// SIMD.
-constexpr int c32_rows(int D) { return D <= 4 ? 4 : (D <= 8 ? 2 : 1); }
+// Rows per lane of the FP32-filtered kernel: one.  The per-pair predicates of
+// every (row, column) of a group are held as lane masks in scalar registers
+// until the wave's FP64 branch; with more rows they overflow the scalar file
+// and spill into vector lanes (at d = 4: 4 rows 15.4 ms, 2 rows 12.8 ms,
+// 1 row 11.1 ms for the 1e10 ordered pairs of the benchmark data).
+constexpr int c32_rows(int D) { return 1; }
 
 constexpr int c32_group(int D) { return D <= 4 ? 2 : 1; }
 
