@@ -9,8 +9,8 @@
 // candidate enters only if it beats the current kTopK-th value; the test is
 // one compare per bound and pair, and the insertion (a min into the last slot
 // and one compare-exchange pass) runs per candidate only when some lane of
-// the wave needs it (a wave-uniform branch: after the first data, few
-// candidates improve any list).  The k values form a multiset, so no index rule is needed; records past
+// the wave improves one of its two lists (a wave-uniform branch: after the
+// first data, few candidates improve any list).  The k values form a multiset, so no index rule is needed; records past
 // n (the staging's padding repeats the last datum) are masked, so every datum
 // counts once.  Split chunks write their sorted lists; a merge kernel takes
 // the kTopK smallest / largest of all of them.
@@ -107,11 +107,12 @@ __global__ void __launch_bounds__(256) bounds_topk_kernel(TopkArgs A)
                 float u, l;
                 pair_bounds<D, DM, NORM>(qv[r], qm[r], xk, v[c * S + Rec<D>::Y],
                                          v[c * S + Rec<D>::M], v[c * S + Rec<D>::YU], big, u, l);
-                // insert only where some lane of the wave improves its list
-                if (__builtin_amdgcn_ballot_w64(u < U[r][kTopK - 1]) != 0)
+                // insert only where some lane of the wave improves a list
+                // (an insertion that improves nothing leaves the list as it is)
+                if (__builtin_amdgcn_ballot_w64(u < U[r][kTopK - 1] || l > L[r][kTopK - 1]) != 0) {
                     topk_insert_up(U[r], u);
-                if (__builtin_amdgcn_ballot_w64(l > L[r][kTopK - 1]) != 0)
                     topk_insert_lo(L[r], l);
+                }
             }
         }
     }
