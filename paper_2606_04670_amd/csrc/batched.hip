@@ -22,6 +22,9 @@
 namespace lip {
 
 // Staging of many sets in one launch: workgroup g handles sets g, g + G, ...
+// Each set first gets its coordinate origin (the mid-range per coordinate,
+// the same value launch_origin computes: minima and maxima are exact in any
+// order), written to `origin` for the class kernels' query loads.
 struct BatchStage {
     const float *x, *y, *Mk;
     float M;
@@ -30,13 +33,40 @@ struct BatchStage {
     int32_t pad0;
     int64_t n, n_pad;
     Xform xf;
+    float *origin;  // [kMaxDim], the array xf.origin points to
     float *out;
 };
 
-__global__ void batched_stage_kernel(const BatchStage *st, int n_sets)
+__global__ void __launch_bounds__(256) batched_stage_kernel(const BatchStage *st, int n_sets)
 {
+    __shared__ float smin[256], smax[256], org[kMaxDim];
     for (int s = blockIdx.x; s < n_sets; s += gridDim.x) {
         const BatchStage a = st[s];
+        for (int j = 0; j < a.d; ++j) {
+            float mn = __builtin_inff(), mx = -__builtin_inff();
+            for (int64_t k = threadIdx.x; k < a.n; k += blockDim.x) {
+                const float v = a.x[k * a.d + a.xf.perm[j]];
+                mn = fminf(mn, v);
+                mx = fmaxf(mx, v);
+            }
+            smin[threadIdx.x] = mn;
+            smax[threadIdx.x] = mx;
+            __syncthreads();
+            for (int h = 128; h > 0; h >>= 1) {
+                if ((int)threadIdx.x < h) {
+                    smin[threadIdx.x] = fminf(smin[threadIdx.x], smin[threadIdx.x + h]);
+                    smax[threadIdx.x] = fmaxf(smax[threadIdx.x], smax[threadIdx.x + h]);
+                }
+                __syncthreads();
+            }
+            if (threadIdx.x == 0) {
+                const float o = origin_of_range(smin[0], smax[0]);
+                org[j] = o;
+                a.origin[j] = o;
+            }
+            __syncthreads();
+        }
+        if ((int)threadIdx.x >= a.d && threadIdx.x < kMaxDim) a.origin[threadIdx.x] = 0.0f;
         const int S = a.d + 3;
         for (int64_t k = threadIdx.x; k < a.n_pad; k += blockDim.x) {
             const int64_t src = k < a.n ? k : a.n - 1;
@@ -46,7 +76,8 @@ __global__ void batched_stage_kernel(const BatchStage *st, int n_sets)
             const float m = a.Mk ? a.Mk[src] : a.M;
             float xm = 0.0f;
             for (int j = 0; j < a.d; ++j) {
-                const float v = xs[a.xf.perm[j]] * a.xf.scale[j];
+                // xf_coord with the origin from LDS (same operations, same value)
+                const float v = (xs[a.xf.perm[j]] - org[j]) * a.xf.scale[j];
                 o[j] = v;
                 if (j >= a.d - a.l1_mon) xm = (j == a.d - a.l1_mon) ? v : xm + v;
             }
@@ -54,6 +85,7 @@ __global__ void batched_stage_kernel(const BatchStage *st, int n_sets)
             o[a.d + 1] = m;
             o[a.d + 2] = a.l1_mon > 0 ? fmaf(-m, xm, y) : y;
         }
+        __syncthreads();  // org and the reduction arrays are reused by the next set
     }
 }
 
@@ -112,7 +144,7 @@ struct SetPlan {
     int R = 0, tile = 32;
     int64_t n_pad = 0, n_tiles = 0, qblocks = 0;
     int tiles_per_chunk = 0, n_chunks = 1;
-    size_t staged_off = 0, keys_off = 0;
+    size_t staged_off = 0, keys_off = 0, origin_off = 0;
 };
 
 constexpr int64_t kItemPairs = int64_t(1) << 22;  // target pairs per work item
@@ -173,6 +205,8 @@ extern "C" lip_status lip_plan_create(lip_plan **plan, const lip_batch_desc *set
         p.qblocks = (d.q + 64 * p.R - 1) / (64 * p.R);
         p.staged_off = off;
         off += align_up((size_t)p.n_pad * (size_t)(p.mi.d + 3) * sizeof(float), 256);
+        p.origin_off = off;
+        off += align_up(kMaxDim * sizeof(float), 256);
         if (p.n_chunks > 1 && d.q > 0) chunked.push_back(s);
     }
     size_t keys_begin = off;
@@ -232,6 +266,7 @@ extern "C" lip_status lip_plan_create(lip_plan **plan, const lip_batch_desc *set
         a.xq = d.xq;
         a.q = d.q;
         a.xf = q.mi.xf;
+        a.xf.origin = (const float *)(base + q.origin_off);
         a.g = d.g;
         a.h_up = d.h_up;
         a.h_lo = d.h_lo;
@@ -248,7 +283,8 @@ extern "C" lip_status lip_plan_create(lip_plan **plan, const lip_batch_desc *set
         b.l1_mon = q.mi.norm == LIP_L1 ? q.mi.dm : 0;
         b.n = d.n;
         b.n_pad = q.n_pad;
-        b.xf = q.mi.xf;
+        b.xf = a.xf;
+        b.origin = (float *)(base + q.origin_off);
         b.out = (float *)(base + q.staged_off);
         stg[s] = b;
     }

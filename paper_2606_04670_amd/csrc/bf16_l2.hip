@@ -178,7 +178,7 @@ __global__ void __launch_bounds__(256) bf16_stage_kernel(Bf16Stage a)
     const float *xs = a.x + orig * D;
     float xv[D];
 #pragma unroll
-    for (int jj = 0; jj < D; ++jj) xv[jj] = xs[a.xf.perm[jj]] * a.xf.scale[jj];
+    for (int jj = 0; jj < D; ++jj) xv[jj] = xf_coord(a.xf, xs, jj);
     const float y = a.y[orig];
     const float m = a.Mk ? a.Mk[orig] : a.M;
     float *o = a.rec + p * S;
@@ -280,7 +280,7 @@ __global__ void __launch_bounds__(256) bf16_bounds_kernel(Bf16Args a)
         const float *src = a.xq + row * D;
         float av[D];
 #pragma unroll
-        for (int jj = 0; jj < D; ++jj) av[jj] = src[a.xf.perm[jj]] * a.xf.scale[jj];
+        for (int jj = 0; jj < D; ++jj) av[jj] = xf_coord(a.xf, src, jj);
         float nq = av[0] * av[0];
 #pragma unroll
         for (int jj = 1; jj < D; ++jj) nq = fmaf(av[jj], av[jj], nq);
@@ -337,7 +337,7 @@ __global__ void __launch_bounds__(256) bf16_bounds_kernel(Bf16Args a)
                 const float *src = a.xq + row * D;
                 float qv[D], xk[D];
 #pragma unroll
-                for (int jj = 0; jj < D; ++jj) qv[jj] = src[a.xf.perm[jj]] * a.xf.scale[jj];
+                for (int jj = 0; jj < D; ++jj) qv[jj] = xf_coord(a.xf, src, jj);
                 const float *rp = a.rec + p * S;
 #pragma unroll
                 for (int jj = 0; jj < D; ++jj) xk[jj] = rp[jj];
@@ -646,8 +646,11 @@ lip_status run_bounds_bf16(const MetricInfo &mi, const float *x, const float *y,
     if (mi.norm != LIP_L2 || mi.dm != 0) return LIP_E_UNSUPPORTED;
     const int d = mi.d;
     const Bf16Layout L = bf16_layout(n, q, d);
-    if (ws_bytes < L.total) return LIP_E_WORKSPACE;
-    char *base = (char *)ws;
+    if (ws_bytes < kOriginBytes + L.total) return LIP_E_WORKSPACE;
+    Xform xf = mi.xf;
+    const lip_status st = origin_for(x, n, d, xf, ws, stream);
+    if (st != LIP_OK) return st;
+    char *base = (char *)ws + kOriginBytes;
     unsigned long long *sorted = (unsigned long long *)(base + L.sort);
 
     // sort (y, index) keys
@@ -671,7 +674,7 @@ lip_status run_bounds_bf16(const MetricInfo &mi, const float *x, const float *y,
     sa.n_pad = L.n_pad;
     sa.per = per;
     sa.rem = rem;
-    sa.xf = mi.xf;
+    sa.xf = xf;
     sa.sorted = sorted;
     sa.rec = (float *)(base + L.rec);
     sa.idx = (int32_t *)(base + L.idx);
@@ -686,7 +689,7 @@ lip_status run_bounds_bf16(const MetricInfo &mi, const float *x, const float *y,
     ba.idx = sa.idx;
     ba.xq = xq;
     ba.q = q;
-    ba.xf = mi.xf;
+    ba.xf = xf;
     ba.per = per;
     ba.rem = rem;
     ba.C = C;

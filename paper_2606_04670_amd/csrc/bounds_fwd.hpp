@@ -97,7 +97,7 @@ __device__ __forceinline__ void fwd_wave(const FwdArgs &a, int chunk, int64_t qb
         qi = qi < a.q ? qi : a.q - 1;
         const float *src = a.xq + qi * D;
 #pragma unroll
-        for (int j = 0; j < D; ++j) qv[r][j] = src[a.xf.perm[j]] * a.xf.scale[j];
+        for (int j = 0; j < D; ++j) qv[r][j] = xf_coord(a.xf, src, j);
         qm[r] = query_mon_sum<D, DM>(qv[r]);
     }
 

@@ -7,8 +7,8 @@ namespace lip {
 
 namespace {
 
-// Records [w x_free.. | c_ND, c_NI per restricted coordinate | y | M_k] in
-// the kernel's coordinate order (A.perm); padded records are zero.
+// Records [w (x_free - o).. | c_ND, c_NI per restricted coordinate | y | M_k]
+// in the kernel's coordinate order (A.perm); padded records are zero.
 __global__ void reg_stage_kernel(const float *x, const float *y, const float *Mk, float M, int d,
                                  int df, int64_t n, int64_t npad, RegArgs A, float *rec)
 {
@@ -17,11 +17,11 @@ __global__ void reg_stage_kernel(const float *x, const float *y, const float *Mk
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < npad; k += stride) {
         float *o = rec + k * S;
         const bool in = k < n;
-        for (int i = 0; i < df; ++i) o[i] = in ? A.w[i] * x[k * d + A.perm[i]] : 0.0f;
+        for (int i = 0; i < df; ++i) o[i] = in ? A.w[i] * (x[k * d + A.perm[i]] - A.origin[i]) : 0.0f;
         for (int i = df; i < d; ++i) {
             const float v = in ? x[k * d + A.perm[i]] : 0.0f;
-            o[df + 2 * (i - df)] = reg_clamp(v, A.nd_s[i], A.nd_t[i], A.w[i]);
-            o[df + 2 * (i - df) + 1] = reg_clamp(v, A.ni_s[i], A.ni_t[i], A.w[i]);
+            o[df + 2 * (i - df)] = reg_clamp(v, A.nd_s[i], A.nd_t[i], A.w[i], A.origin[i]);
+            o[df + 2 * (i - df) + 1] = reg_clamp(v, A.ni_s[i], A.ni_t[i], A.w[i], A.origin[i]);
         }
         o[S - 2] = in ? y[k] : 0.0f;
         o[S - 1] = in ? (Mk ? Mk[k] : M) : 0.0f;
@@ -36,7 +36,8 @@ int64_t reg_npad(int64_t n) { return (n + 63) / 64 * 64; }
 
 size_t reg_ws_bytes(int64_t n, int64_t q, int d)
 {
-    return align_up((size_t)reg_npad(n) * (size_t)(2 * d + 2) * 4, 256) + partial_bytes(q) + 256;
+    return kOriginBytes + align_up((size_t)reg_npad(n) * (size_t)(2 * d + 2) * 4, 256) +
+           partial_bytes(q) + 256;
 }
 
 lip_status run_bounds_reg(const MetricInfo &mi, const float *x, const float *y, int64_t n,
@@ -78,6 +79,9 @@ lip_status run_bounds_reg(const MetricInfo &mi, const float *x, const float *y, 
                        : mi.norm == LIP_L2 ? reg_l2(mi.d, df)
                                            : reg_linf(mi.d, df);
     if (!launch) return LIP_E_UNSUPPORTED;
+    if (launch_origin(x, n, mi.d, A.perm, (float *)ws, s) != hipSuccess) return LIP_E_DEVICE;
+    A.origin = (const float *)ws;
+    ws = (char *)ws + kOriginBytes;
     float *rec = (float *)ws;
     char *p = (char *)ws + align_up((size_t)A.npad * (size_t)(2 * mi.d + 2) * 4, 256);
     A.rec = rec;

@@ -4,7 +4,9 @@
 // Every coordinate carries the two intervals where f is not decreasing (ND)
 // and not increasing (NI) (kinds 0 / +1 / -1 are the cases where these are
 // everything or nothing; an empty interval is stored as [0, 0]).  With
-// c(v) = w clamp(v, s, t) the clamped, weighted coordinate, the travelled
+// c(v) = w (clamp(v, s, t) - o) the clamped, weighted coordinate (o the
+// data's mid-range in that coordinate, so that rounding happens at the scale
+// of the data's extent rather than of |v|; see lip_device.hpp), the travelled
 // length inside [s, t] is |c(q) - c(x)|, and the difference a = c_ND(q) -
 // c_ND(x) is positive when moving towards larger values, negative otherwise
 // (likewise b for NI).  So the upper component (length where f may rise in
@@ -41,6 +43,7 @@ struct RegArgs {
     // per position (free coordinates first): source coordinate, intervals, weight
     int32_t perm[kMaxDim];
     float nd_s[kMaxDim], nd_t[kMaxDim], ni_s[kMaxDim], ni_t[kMaxDim], w[kMaxDim];
+    const float *origin;  // device [kMaxDim], per position
     const float *xq;
     int64_t q;
     float *g, *h_up, *h_lo;
@@ -53,10 +56,11 @@ constexpr int kRegTile = 64;  // records per tile; chunks are whole tiles
 
 constexpr int reg_rows(int D) { return rows_for_dim(D) / 2 > 0 ? rows_for_dim(D) / 2 : 1; }
 
-// w clamp(v, s, t) (s <= t; the median of three needs no canonicalisation)
-__device__ __forceinline__ float reg_clamp(float v, float s, float t, float w)
+// w (clamp(v, s, t) - o) (s <= t; the median of three needs no
+// canonicalisation)
+__device__ __forceinline__ float reg_clamp(float v, float s, float t, float w, float o)
 {
-    return w * __builtin_amdgcn_fmed3f(v, s, t);
+    return w * (__builtin_amdgcn_fmed3f(v, s, t) - o);
 }
 
 // Upper and lower distances of one pair: q and xk hold the DF free weighted
@@ -123,12 +127,12 @@ __global__ void __launch_bounds__(256) bounds_reg_kernel(RegArgs A)
         int64_t j = q0 + r * 64 + lane;
         j = j < A.q ? j : A.q - 1;
 #pragma unroll
-        for (int i = 0; i < DF; ++i) qv[r][i] = A.w[i] * A.xq[j * D + A.perm[i]];
+        for (int i = 0; i < DF; ++i) qv[r][i] = A.w[i] * (A.xq[j * D + A.perm[i]] - A.origin[i]);
 #pragma unroll
         for (int i = DF; i < D; ++i) {
             const float v = A.xq[j * D + A.perm[i]];
-            qv[r][DF + 2 * (i - DF)] = reg_clamp(v, A.nd_s[i], A.nd_t[i], A.w[i]);
-            qv[r][DF + 2 * (i - DF) + 1] = reg_clamp(v, A.ni_s[i], A.ni_t[i], A.w[i]);
+            qv[r][DF + 2 * (i - DF)] = reg_clamp(v, A.nd_s[i], A.nd_t[i], A.w[i], A.origin[i]);
+            qv[r][DF + 2 * (i - DF) + 1] = reg_clamp(v, A.ni_s[i], A.ni_t[i], A.w[i], A.origin[i]);
         }
         hu[r] = __builtin_inff();
         hl[r] = -__builtin_inff();

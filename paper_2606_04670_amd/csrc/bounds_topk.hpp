@@ -80,7 +80,7 @@ __global__ void __launch_bounds__(256) bounds_topk_kernel(TopkArgs A)
         int64_t qi = q0 + r * 64 + lane;
         qi = qi < a.q ? qi : a.q - 1;
 #pragma unroll
-        for (int j = 0; j < D; ++j) qv[r][j] = a.xq[qi * D + a.xf.perm[j]] * a.xf.scale[j];
+        for (int j = 0; j < D; ++j) qv[r][j] = xf_coord(a.xf, a.xq + qi * D, j);
         qm[r] = query_mon_sum<D, DM>(qv[r]);
 #pragma unroll
         for (int j = 0; j < kTopK; ++j) {

@@ -17,7 +17,22 @@ constexpr int kMaxChunks = 64;                // largest data split
 constexpr int64_t kMaxPartials = 1ll << 23;   // n_chunks * q cap (per bound)
 constexpr int64_t kMaxIndex = 2147483647ll;   // indices are int32
 
-inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+constexpr size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Every path that stages coordinates (bound kernels, k-best, step-function
+// forward, smoothing, regional bounds) takes this many bytes off the front
+// of its workspace for the coordinate origin (launch_origin).
+constexpr size_t kOriginBytes = align_up(kOriginAreaBytes, 256);
+
+// Launches the origin reduction for the data x [n][d] into `area` and
+// returns xf with its origin pointer set.
+inline lip_status origin_for(const float *x, int64_t n, int d, Xform &xf, void *area,
+                             hipStream_t s)
+{
+    xf.origin = (const float *)area;
+    return launch_origin(x, n, d, xf.perm, (float *)area, s) == hipSuccess ? LIP_OK
+                                                                            : LIP_E_DEVICE;
+}
 
 // Validated metric: transform of the coordinates and monotone count.
 struct MetricInfo {

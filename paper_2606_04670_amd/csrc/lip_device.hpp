@@ -3,12 +3,26 @@
 // Staged data layout in HBM (written by the staging kernel, read by every
 // bound kernel): one record of STRIDE = D + 3 floats per data point,
 //     [ x'_0 .. x'_{D-1} | y | M | yU ]
-// where x'_j = c_j * x[perm_j]: the unconstrained coordinates come first,
-// then the monotone ones, and c_j folds in the distance weight w and the
-// sign -1 of a decreasing coordinate (which turns it into an increasing
-// one).  yU is the value the l1 upper bound starts from (see pair_bounds);
-// it equals y for the other norms and without monotone coordinates.  Queries
-// get the same transform when they are loaded into registers.
+// where x'_j = c_j * (x[perm_j] - o_j): the unconstrained coordinates come
+// first, then the monotone ones; o_j is the mid-range of coordinate perm_j
+// over the data (an FP32 value inside the data's range), and c_j folds in
+// the distance weight w and the sign -1 of a decreasing coordinate (which
+// turns it into an increasing one).  yU is the value the l1 upper bound
+// starts from (see pair_bounds); it equals y for the other norms and without
+// monotone coordinates.  Queries get the same transform when they are loaded
+// into registers.
+//
+// Why the origin.  Eq. (2) depends on the coordinates only through
+// x - x^k.  Rounding w x (or sums of coordinates) at the magnitude of the
+// coordinates would put an error proportional to |x| into every candidate,
+// which cancels later and is large when the data sit far from 0.  With the
+// origin inside the data's range, |x - o| is at most the data's extent for a
+// datum, and at most the query-datum distance plus that extent for a query;
+// the subtraction is exact when x and o are within a factor 2 of each other
+// (Sterbenz), and otherwise errs by half an ulp of |x - o|.  Every FP32 error
+// of the bound path is therefore bounded by a small multiple of
+// 2^-24 (|y_k| + M_k (dist + sum_i w_i ext_i)), ext_i the data's extent in
+// coordinate i, whatever the position of the data.
 //
 // A wave reads one record at a time with a wave-uniform address, so the
 // compiler emits scalar (SMEM) loads through the constant address space and
@@ -34,11 +48,31 @@ typedef const float __attribute__((address_space(4))) *cfloat_ptr;
 
 __device__ __forceinline__ cfloat_ptr as_const(const float *p) { return (cfloat_ptr)(p); }
 
-// Per-coordinate transform applied to queries (data are staged with it).
+// Per-coordinate transform applied to queries (data are staged with it):
+// staged coordinate j = scale[j] * (x[perm[j]] - origin[j]).  `origin` is a
+// device array of kMaxDim floats in the permuted order, written on the
+// stream by launch_origin before any kernel that reads it.
 struct Xform {
     int32_t perm[kMaxDim];
     float scale[kMaxDim];
+    const float *origin;
 };
+
+// The origin of a coordinate whose data lie in [mn, mx]: the mid-range,
+// with -0 turned into +0 (so that every path that reduces the same data gets
+// the same bits) and 0 for a non-finite range (NaN / Inf inputs are outside
+// the contract).
+__device__ __forceinline__ float origin_of_range(float mn, float mx)
+{
+    const float o = (0.5f * mn + 0.5f * mx) + 0.0f;
+    return __builtin_isfinite(o) ? o : 0.0f;
+}
+
+// Staged value of coordinate j of the row `row` (an untransformed [D] row).
+__device__ __forceinline__ float xf_coord(const Xform &xf, const float *row, int j)
+{
+    return (row[xf.perm[j]] - xf.origin[j]) * xf.scale[j];
+}
 
 // Per-query constant of the l1 form with monotone coordinates:
 // Qm = sum over the monotone coordinates of q'_i (in index order).

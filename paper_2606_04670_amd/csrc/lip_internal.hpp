@@ -77,6 +77,14 @@ struct CombineArgs {
     int32_t *arg_up, *arg_lo;
 };
 
+// Coordinate origin (stage.hip): the area holds origin[kMaxDim] (permuted
+// order, perm[j] = original coordinate of staged coordinate j) followed by
+// the pass-1 partials; kOriginAreaBytes of device memory.
+constexpr int kOriginBlocks = 240;
+constexpr size_t kOriginAreaBytes = (size_t)(kMaxDim * 4 + kOriginBlocks * kMaxDim * 2) * 4;
+hipError_t launch_origin(const float *x, int64_t n, int d, const int32_t *perm, float *area,
+                         hipStream_t s);
+
 hipError_t launch_stage(int d, const StageArgs &a, hipStream_t s);
 hipError_t launch_combine(const CombineArgs &a, hipStream_t s);
 hipError_t launch_nonfinite(const float *v, int64_t n, int *flag, hipStream_t s);

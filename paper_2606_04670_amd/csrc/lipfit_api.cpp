@@ -183,10 +183,14 @@ lip_status run_bounds(const MetricInfo &mi, const float *x, const float *y, int6
 {
     const FwdPlan p = make_fwd_plan(mi, n, q, cfg);
     const size_t sb = staged_bytes(n, mi.d);
-    const size_t need = sb + (p.n_chunks > 1 ? partial_bytes(q) : 0);
+    const size_t need = kOriginBytes + sb + (p.n_chunks > 1 ? partial_bytes(q) : 0);
     if (ws_bytes < need) return LIP_E_WORKSPACE;
     FwdLauncher launch = fwd_launchers(mi.norm, mi.d, mi.dm).plain;
     if (!launch) return LIP_E_UNSUPPORTED;
+    Xform xf = mi.xf;
+    lip_status st = origin_for(x, n, mi.d, xf, ws, stream);
+    if (st != LIP_OK) return st;
+    ws = (char *)ws + kOriginBytes;
     float *staged = (float *)ws;
 
     StageArgs sa{};
@@ -197,7 +201,7 @@ lip_status run_bounds(const MetricInfo &mi, const float *x, const float *y, int6
     sa.l1_mon = mi.norm == LIP_L1 ? mi.dm : 0;
     sa.n = n;
     sa.n_pad = p.n_pad;
-    sa.xf = mi.xf;
+    sa.xf = xf;
     sa.out = staged;
     if (launch_stage(mi.d, sa, stream) != hipSuccess) return LIP_E_DEVICE;
 
@@ -210,7 +214,7 @@ lip_status run_bounds(const MetricInfo &mi, const float *x, const float *y, int6
     a.n_chunks = p.n_chunks;
     a.xq = xq;
     a.q = q;
-    a.xf = mi.xf;
+    a.xf = xf;
     a.g = g;
     a.h_up = h_up;
     a.h_lo = h_lo;
@@ -270,7 +274,7 @@ size_t lip_workspace_size(int64_t n, int64_t q, int32_t d, uint32_t flags)
     if (q < 0) q = 0;
     if (d < 1) d = 1;
     if (d > kMaxDim) d = kMaxDim;
-    size_t fwd = staged_bytes(n, d) + partial_bytes(q) + bf16_extra_bytes(n, q, d);
+    size_t fwd = kOriginBytes + staged_bytes(n, d) + partial_bytes(q) + bf16_extra_bytes(n, q, d);
     size_t m = fwd;
     const size_t ds = data_side_ws_bytes(n, d);
     const size_t bwd = backward_ws_bytes(n);

@@ -25,10 +25,14 @@
 //
 // D1hi.  |t32 - t64| <= rho t64 + alpha with rho = 2^-18 (the FP32
 // distance's relative rounding, (d + 6) 2^-24 at most, with margin) and
-// alpha = 2^-21 sum_j max|x'_j| + 2^-70 (the rounding of the staged
-// coordinates x' = fl(c x), relative to the coordinates rather than to their
-// difference, plus FP32 underflow of squares).  So t32 > D1hi =
-// up(d1 (1 + rho) + alpha) implies t64 > d1.
+// alpha = 2^-21 sum_j max|x'_j| + 2^-70: the staged coordinates
+// x' = fl(fl(x - o) c) carry two roundings each, relative to the centred
+// coordinates rather than to their difference, so a coordinate difference
+// of a query and a datum errs by at most (2^-23 + 2^-48) (|q'_j| + |x'_j|)
+// <= 2^-22 max|x'_j| (the maximum taken over the data and the queries);
+// any of the three norms passes this on to the distance with factor <= 1
+// per coordinate; the factor 2 is margin; 2^-70 covers FP32 underflow of
+// squares.  So t32 > D1hi = up(d1 (1 + rho) + alpha) implies t64 > d1.
 //
 // The queries are processed in spatial (Morton) order, so that the queries
 // of one wave are close together and few data can beat their running bounds.
@@ -181,7 +185,7 @@ __global__ void __launch_bounds__(256) steps_fwd32_kernel(StepArgs A)
         const int64_t j = (int64_t)(uint32_t)(A.qorder[p] & 0xFFFFFFFFull);
         qi[r] = (int)j;
 #pragma unroll
-        for (int i = 0; i < D; ++i) qv[r][i] = A.xq[j * D + A.xf.perm[i]] * A.xf.scale[i];
+        for (int i = 0; i < D; ++i) qv[r][i] = xf_coord(A.xf, A.xq + j * D, i);
         hu[r] = __builtin_inff();
         hl[r] = -__builtin_inff();
         au[r] = -1;

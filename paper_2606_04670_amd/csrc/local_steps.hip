@@ -136,8 +136,8 @@ __global__ void steps_stage_kernel(const double *d1, const float *V, int K, int 
 }
 
 // Largest |x'_j| over the data and the queries (x' = the FP32 transform of
-// the bound path: weights, signs, free coordinates first), as float bits
-// (non-negative floats order like their bit patterns).
+// the bound path: origin, weights, signs, free coordinates first), as float
+// bits (non-negative floats order like their bit patterns).
 __global__ void steps_amax_kernel(const float *x, int64_t n, const float *xq, int64_t q, int d,
                                   Xform xf, unsigned int *amax)
 {
@@ -146,8 +146,8 @@ __global__ void steps_amax_kernel(const float *x, int64_t n, const float *xq, in
     for (int j = 0; j < d; ++j) {
         float m = 0.0f;
         for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += stride) {
-            const float v = k < n ? x[k * d + xf.perm[j]] : xq[(k - n) * d + xf.perm[j]];
-            m = fmaxf(m, fabsf(v * xf.scale[j]));
+            const float v = k < n ? xf_coord(xf, x + k * d, j) : xf_coord(xf, xq + (k - n) * d, j);
+            m = fmaxf(m, fabsf(v));
         }
         for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
         if ((threadIdx.x & 63) == 0) atomicMax(amax + j, __float_as_uint(m));
@@ -177,7 +177,7 @@ __global__ void steps_rec_kernel(const float *x, const float *y, const double *d
             for (int j = 0; j < S; ++j) o[j] = 0.0f;
             continue;
         }
-        for (int j = 0; j < d; ++j) o[j] = x[k * d + xf.perm[j]] * xf.scale[j];
+        for (int j = 0; j < d; ++j) o[j] = xf_coord(xf, x + k * d, j);
         o[d] = y[k];
         float v0 = V[k * (K + 2)], v1 = V[k * (K + 2) + 1];
         for (int s = 1; s < K + 2; ++s) {
@@ -446,7 +446,7 @@ extern "C" lip_status lip_fit_eval_steps(const lip_metric *metric, const float *
     st = check_knots(steps->knots, steps->K);
     if (st != LIP_OK) return st;
     if (!x || !y || !steps->d1 || !steps->V || (q > 0 && !xq)) return LIP_E_ARG;
-    if (!ws || ws_bytes < local_ws_bytes(n, q, mi.d)) return LIP_E_WORKSPACE;
+    if (!ws || ws_bytes < kOriginBytes + local_ws_bytes(n, q, mi.d)) return LIP_E_WORKSPACE;
     if (q == 0) return LIP_OK;
     hipStream_t s = (hipStream_t)stream;
     const int K = steps->K;
@@ -469,6 +469,9 @@ extern "C" lip_status lip_fit_eval_steps(const lip_metric *metric, const float *
     }
     for (int j = 0; j < kMaxDim; ++j) A.qsign[j] = sg.s[j];
     A.xf = mi.xf;
+    st = origin_for(x, n, mi.d, A.xf, ws, s);
+    if (st != LIP_OK) return st;
+    ws = (char *)ws + kOriginBytes;
     A.ds.n = n;
     A.ds.npad = ds_npad(n);
     A.ds.norm = mi.norm;
@@ -523,9 +526,9 @@ extern "C" lip_status lip_fit_eval_steps(const lip_metric *metric, const float *
     int64_t ga = (n + q + 255) / 256;
     if (ga > 1024) ga = 1024;
     hipLaunchKernelGGL(steps_amax_kernel, dim3((unsigned)ga), dim3(256), 0, s, x, n, xq, q, mi.d,
-                       mi.xf, amax);
+                       A.xf, amax);
     hipLaunchKernelGGL(steps_rec_kernel, dim3(grid1d(A.ds.npad)), dim3(256), 0, s, x, y,
-                       steps->d1, steps->V, K, mi.d, n, A.ds.npad, mi.xf,
+                       steps->d1, steps->V, K, mi.d, n, A.ds.npad, A.xf,
                        (const unsigned int *)amax, rec);
     hipLaunchKernelGGL(qbox_init_kernel, dim3(1), dim3(64), 0, s, qbb, mi.d);
     int64_t gq = (q + 255) / 256;

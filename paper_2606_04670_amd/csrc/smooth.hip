@@ -22,7 +22,7 @@ __global__ void smooth_stage_kernel(const float *x, const float *y, const float 
             for (int j = 0; j < S; ++j) o[j] = 0.0f;
             continue;
         }
-        for (int j = 0; j < d; ++j) o[j] = x[k * d + xf.perm[j]] * xf.scale[j];
+        for (int j = 0; j < d; ++j) o[j] = xf_coord(xf, x + k * d, j);
         o[d] = y[k] + eps[k];
         const float m = Mk ? Mk[k] : M;
         o[d + 1] = m;
@@ -41,16 +41,18 @@ __global__ void smooth_amax_kernel(const float *x, int64_t n, int d, Xform xf, u
     for (int j = 0; j < d; ++j) {
         float m = 0.0f;
         for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride)
-            m = fmaxf(m, fabsf(x[k * d + xf.perm[j]] * xf.scale[j]));
+            m = fmaxf(m, fabsf(xf_coord(xf, x + k * d, j)));
         for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
         if ((threadIdx.x & 63) == 0) atomicMax(amax + j, __float_as_uint(m));
     }
 }
 
 // alpha = 2^-21 sum_j max |x'_j| + 2^-70, rounded up: the absolute part of
-// the FP32 distance's error against the FP64 one (the staged coordinates are
-// rounded relative to themselves, not to their difference; plus underflow of
-// FP32 squares).  Runs as one wave.
+// the FP32 distance's error against the FP64 one (the staged coordinates
+// fl(fl(x - o) c) carry two roundings relative to the centred coordinates,
+// not to their difference: at most 2^-22 max |x'_j| per coordinate
+// difference, doubled for margin; plus underflow of FP32 squares).  Runs as
+// one wave.
 __global__ void smooth_alpha_kernel(unsigned int *amax, int d, float *alpha)
 {
     if (threadIdx.x != 0) return;
@@ -150,7 +152,7 @@ extern "C" lip_status lip_smooth_objective(const lip_metric *metric, const float
     if (!Mk && (!(M >= 0.0f) || !__builtin_isfinite(M))) return LIP_E_VALUE;
     if (!(p > 0.0) || !__builtin_isfinite(p)) return LIP_E_VALUE;
     if (!(prune >= 0.0) || !__builtin_isfinite(prune)) return LIP_E_VALUE;
-    if (!ws || ws_bytes < smooth_ws_bytes(n, mi.d)) return LIP_E_WORKSPACE;
+    if (!ws || ws_bytes < kOriginBytes + smooth_ws_bytes(n, mi.d)) return LIP_E_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     if (flags & LIP_FLAG_CHECK_FINITE) {
         const float *arr[4] = {x, y, eps, Mk};
@@ -165,7 +167,10 @@ extern "C" lip_status lip_smooth_objective(const lip_metric *metric, const float
     A.n = n;
     A.npad = smooth_npad(n);
     A.c = prune;
-    char *p0 = (char *)ws;
+    Xform xf = mi.xf;
+    st = origin_for(x, n, mi.d, xf, ws, s);
+    if (st != LIP_OK) return st;
+    char *p0 = (char *)ws + kOriginBytes;
     float *rec = (float *)p0;
     p0 += align_up((size_t)A.npad * (size_t)(mi.d + 4) * 4, 256);
     const int R = smooth_rows(mi.d, pr);
@@ -192,7 +197,7 @@ extern "C" lip_status lip_smooth_objective(const lip_metric *metric, const float
     int64_t gs = (A.npad + 255) / 256;
     if (gs > 65536) gs = 65536;
     hipLaunchKernelGGL(smooth_stage_kernel, dim3((unsigned)gs), dim3(256), 0, s, x, y, eps, Mk, M,
-                       prune, mi.d, n, A.npad, mi.xf, rec);
+                       prune, mi.d, n, A.npad, xf, rec);
     if (pr) {
         DsArgs ds{};
         Signs sg{};
@@ -212,7 +217,7 @@ extern "C" lip_status lip_smooth_objective(const lip_metric *metric, const float
         if (ga > 1024) ga = 1024;
         hipLaunchKernelGGL(smooth_zero_kernel, dim3(1), dim3(64), 0, s, amax, kMaxDim);
         hipLaunchKernelGGL(smooth_amax_kernel, dim3((unsigned)ga), dim3(256), 0, s, x, n, mi.d,
-                           mi.xf, amax);
+                           xf, amax);
         hipLaunchKernelGGL(smooth_alpha_kernel, dim3(1), dim3(64), 0, s, amax, mi.d, alpha);
         A.alpha = alpha;
     }

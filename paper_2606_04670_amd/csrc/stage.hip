@@ -7,6 +7,68 @@
 
 namespace lip {
 
+// ---- coordinate origin ------------------------------------------------------
+//
+// Per coordinate, the mid-range of the data, o = fl(min / 2 + max / 2), an
+// FP32 value in [min, max] (halving is exact for normal numbers and the
+// rounded sum of two values in [min / 2, max / 2] stays in [min, max]).
+// Pass 1: each of G workgroups reduces a strided part of the rows to
+// partial (min, max) per coordinate; pass 2 (one workgroup) combines the G
+// partials and writes origin[j] for the permuted coordinate j.  Rows are
+// read whole, so the loads are coalesced for any d.
+
+__global__ void __launch_bounds__(256) origin_partial_kernel(const float *x, int64_t n, int d,
+                                                             float *part)
+{
+    __shared__ float smin[256], smax[256];
+    for (int j = 0; j < d; ++j) {
+        float mn = __builtin_inff(), mx = -__builtin_inff();
+        for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+             k += (int64_t)gridDim.x * blockDim.x) {
+            const float v = x[k * d + j];
+            mn = fminf(mn, v);
+            mx = fmaxf(mx, v);
+        }
+        smin[threadIdx.x] = mn;
+        smax[threadIdx.x] = mx;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h) {
+                smin[threadIdx.x] = fminf(smin[threadIdx.x], smin[threadIdx.x + h]);
+                smax[threadIdx.x] = fmaxf(smax[threadIdx.x], smax[threadIdx.x + h]);
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            part[((int64_t)blockIdx.x * kMaxDim + j) * 2] = smin[0];
+            part[((int64_t)blockIdx.x * kMaxDim + j) * 2 + 1] = smax[0];
+        }
+        __syncthreads();
+    }
+}
+
+struct OriginPerm {
+    int32_t perm[kMaxDim];
+};
+
+__global__ void origin_final_kernel(const float *part, int n_part, int d, OriginPerm pm,
+                                    float *origin)
+{
+    const int j = threadIdx.x;
+    if (j >= kMaxDim) return;
+    if (j >= d) {
+        origin[j] = 0.0f;
+        return;
+    }
+    const int c = pm.perm[j];
+    float mn = __builtin_inff(), mx = -__builtin_inff();
+    for (int b = 0; b < n_part; ++b) {
+        mn = fminf(mn, part[((int64_t)b * kMaxDim + c) * 2]);
+        mx = fmaxf(mx, part[((int64_t)b * kMaxDim + c) * 2 + 1]);
+    }
+    origin[j] = origin_of_range(mn, mx);
+}
+
 // Stage the data set into records [x'_0..x'_{D-1} | y | M | yU] (see
 // lip_device.hpp), padding up to n_pad by repeating the last datum.  A
 // repeated record has the same candidates as the datum it copies and a
@@ -22,7 +84,7 @@ __global__ void stage_kernel(StageArgs a)
         float *o = a.out + k * S;
         float xv[D];
 #pragma unroll
-        for (int j = 0; j < D; ++j) xv[j] = xs[a.xf.perm[j]] * a.xf.scale[j];
+        for (int j = 0; j < D; ++j) xv[j] = xf_coord(a.xf, xs, j);
         const float y = a.y[src];
         const float m = a.Mk ? a.Mk[src] : a.M;
         // l1 with monotone coordinates: yU = y - M * sum_mon x'_i (summed in
@@ -119,6 +181,21 @@ hipError_t launch_stage(int d, const StageArgs &a, hipStream_t s)
 #undef LIP_STAGE_CASE
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_origin(const float *x, int64_t n, int d, const int32_t *perm, float *area,
+                         hipStream_t s)
+{
+    if (n < 1 || d < 1 || d > kMaxDim) return hipErrorInvalidValue;
+    OriginPerm pm{};
+    for (int j = 0; j < kMaxDim; ++j) pm.perm[j] = j < d ? perm[j] : 0;
+    int64_t g = (n + 255) / 256;
+    if (g > kOriginBlocks) g = kOriginBlocks;
+    float *part = area + kMaxDim * 4;
+    hipLaunchKernelGGL(origin_partial_kernel, dim3((unsigned)g), dim3(256), 0, s, x, n, d, part);
+    hipLaunchKernelGGL(origin_final_kernel, dim3(1), dim3(64), 0, s, (const float *)part, (int)g,
+                       d, pm, area);
     return hipGetLastError();
 }
 

@@ -54,8 +54,8 @@ constexpr int kTopkMaxChunks = 16;
 
 size_t topk_ws_bytes(int64_t n, int64_t q, int d)
 {
-    return staged_bytes(n, d) + align_up((size_t)2 * kTopkMaxChunks * (size_t)q * kTopK * 4, 256) +
-           256;
+    return kOriginBytes + staged_bytes(n, d) +
+           align_up((size_t)2 * kTopkMaxChunks * (size_t)q * kTopK * 4, 256) + 256;
 }
 
 }  // namespace lip
@@ -91,6 +91,10 @@ extern "C" lip_status lip_fit_eval_k(const lip_metric *metric, const float *x, c
     TopkLaunch launch = get_topk(mi.norm, mi.d, mi.dm);
     if (!launch) return LIP_E_UNSUPPORTED;
     const int64_t n_pad = (n + 7) / 8 * 8;
+    Xform xf = mi.xf;
+    st = origin_for(x, n, mi.d, xf, ws, s);
+    if (st != LIP_OK) return st;
+    ws = (char *)ws + kOriginBytes;
     float *staged = (float *)ws;
     StageArgs sa{};
     sa.x = x;
@@ -100,7 +104,7 @@ extern "C" lip_status lip_fit_eval_k(const lip_metric *metric, const float *x, c
     sa.l1_mon = mi.norm == LIP_L1 ? mi.dm : 0;
     sa.n = n;
     sa.n_pad = n_pad;
-    sa.xf = mi.xf;
+    sa.xf = xf;
     sa.out = staged;
     if (launch_stage(mi.d, sa, s) != hipSuccess) return LIP_E_DEVICE;
     TopkArgs A{};
@@ -108,7 +112,7 @@ extern "C" lip_status lip_fit_eval_k(const lip_metric *metric, const float *x, c
     A.f.n = n;
     A.f.xq = xq;
     A.f.q = q;
-    A.f.xf = mi.xf;
+    A.f.xf = xf;
     A.f.g = g;
     A.f.h_up = h_up;
     A.f.h_lo = h_lo;
