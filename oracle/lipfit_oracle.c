@@ -331,7 +331,7 @@ static double dcomp(int i, double delta, const signed char *mon, int up)
 static void dist_grad(int d, int norm, const double *w, const signed char *mon,
                       const float *a, const float *b, int up, double dist, double *out)
 {
-    double cmax = -1.0;
+    float cmax = -1.0f;
     int jmax = -1;
     for (int i = 0; i < d; ++i) {
         double delta = (double)a[i] - (double)b[i];
@@ -344,8 +344,17 @@ static void dist_grad(int d, int norm, const double *w, const signed char *mon,
         } else if (norm == ORC_L2) {
             out[i] = dist > 0.0 ? c * dc / dist : 0.0;
         } else {
+            /* Which coordinate carries the linf subgradient is an integer
+             * decided by floating point: it is decided in single precision,
+             * with the component formed as the evaluation precision forms it
+             * (the single-precision difference, its absolute value or
+             * positive part, times the weight), lowest coordinate on ties. */
+            const float df = a[i] - b[i];
+            double cu32, cl32;
+            components(i, (double)df, mon, &cu32, &cl32);
+            const float c32 = (float)w[i] * (float)(up ? cu32 : cl32);
             out[i] = 0.0;
-            if (c > cmax) { cmax = c; jmax = i; }
+            if (c32 > cmax) { cmax = c32; jmax = i; }
         }
     }
     if (norm == ORC_LINF && jmax >= 0) {

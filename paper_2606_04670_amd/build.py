@@ -79,29 +79,12 @@ def build(force: bool = False, jobs: int = 0) -> str:
     return LIB
 
 
-CALIB_SRC = os.path.join(HERE, "calib", "valu_rates.hip")
-CALIB_BIN = os.path.join(HERE, "calib", "valu_rates")
-
-
-def build_calibration(force: bool = False) -> str:
-    """The VALU-rate microbenchmark behind the roofline peaks (calib/)."""
-    if force or not os.path.exists(CALIB_BIN) or \
-            os.path.getmtime(CALIB_BIN) < os.path.getmtime(CALIB_SRC):
-        cmd = [HIPCC, *CFLAGS, "-o", CALIB_BIN + ".tmp", CALIB_SRC]
-        r = subprocess.run(cmd, capture_output=True, text=True)
-        if r.returncode != 0:
-            raise RuntimeError(f"hipcc failed for {CALIB_SRC}:\n{r.stderr}")
-        os.replace(CALIB_BIN + ".tmp", CALIB_BIN)
-    return CALIB_BIN
-
-
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--force", action="store_true")
     ap.add_argument("-j", type=int, default=0)
     a = ap.parse_args(argv)
     print(build(force=a.force, jobs=a.j))
-    print(build_calibration(force=a.force))
 
 
 if __name__ == "__main__":
