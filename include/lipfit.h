@@ -348,23 +348,53 @@ lip_status lip_plan_execute(lip_plan *plan, lip_stream stream);
 lip_status lip_plan_destroy(lip_plan *plan);
 
 /* ---- tile parameters --------------------------------------------------------
- * Runtime tiling choices of the bound kernels for one shape class
- * (d, number of monotone coordinates, norm). */
+ * Runtime tiling choices of the bound kernels (lip_bounds, lip_fit_eval and
+ * the sets of a plan) for a shape class (d, number of monotone coordinates,
+ * norm) and a size class of (n, q): sizes within a factor of 4 of each other
+ * (floor(log2 v) / 2 equal for n and for q) share an entry.  Results do not
+ * depend on these choices, only the time does. */
 typedef struct {
-    int32_t tile;         /* data points per argmin tile (multiple of 8) */
-    int32_t split;        /* number of data chunks (1 = no split) */
+    int32_t tile;         /* data points per argmin tile (multiple of 8, 8..256) */
+    int32_t split;        /* number of data chunks (1..64; 1 = no split) */
     int32_t waves;        /* waves per workgroup (1..4) */
     int32_t reserved;
 } lip_tile_cfg;
 
+/* The configuration the next call of these sizes will use: the table's
+ * entry for the size class of (n, q), else the entry set for every size,
+ * else the built-in default.  The first lookup loads the file named by the
+ * environment variable LIPFIT_TUNE_CACHE, if it is set (see lip_tune_load). */
 lip_status lip_tune_get(int32_t d, int32_t n_mon, int32_t norm, int64_t n, int64_t q,
                         lip_tile_cfg *cfg);
-lip_status lip_tune_set(int32_t d, int32_t n_mon, int32_t norm, const lip_tile_cfg *cfg);
-/* Times candidate tile parameters for this shape class on synthetic data
- * of the given sizes (allocates and frees its own device memory, blocks),
- * stores the fastest with lip_tune_set and returns it. */
+/* Stores cfg for the size class of (n, q), or for every size when n == 0 and
+ * q == 0 (one of them 0 alone is LIP_E_SHAPE); cfg == NULL removes that
+ * entry.  Invalid values: LIP_E_VALUE. */
+lip_status lip_tune_set(int32_t d, int32_t n_mon, int32_t norm, int64_t n, int64_t q,
+                        const lip_tile_cfg *cfg);
+/* Times every candidate (tile 16/32/64/128 x split 1..32 x 2 or 4 waves) for
+ * this shape class on synthetic data of the given sizes (allocates and frees
+ * its own device memory, blocks), stores the fastest under the size class of
+ * (n, q) and returns it; with LIPFIT_TUNE_CACHE set, the whole table is then
+ * written to that file. */
 lip_status lip_autotune(int32_t d, int32_t n_mon, int32_t norm, int64_t n, int64_t q,
                         lip_stream stream, lip_tile_cfg *best);
+/* The table as a JSON file: {"format": "lipfit-tune-1", "entries": [{"arch":
+ * "gfx950", "d", "n_mon", "norm", "n_class", "q_class", "tile", "split",
+ * "waves"}, ...]} (class -1: every size).  Save writes every entry under the
+ * architecture name `arch`; load adds the entries of architecture `arch`
+ * (others are skipped) and changes nothing if the file does not parse
+ * (LIP_E_VALUE).  arch == NULL means the current device's ("" without a
+ * device: LIP_E_DEVICE).  An unreadable / unwritable path is LIP_E_ARG. */
+lip_status lip_tune_save(const char *path, const char *arch);
+lip_status lip_tune_load(const char *path, const char *arch);
+/* Removes every entry. */
+lip_status lip_tune_clear(void);
+
+/* The tile parameters set number `set` of a plan (0-based, in the order
+ * given to lip_plan_create) runs with: cfg->tile the argmin tile from the
+ * tuning table at plan creation, cfg->split its number of data chunks,
+ * cfg->waves the waves per workgroup. */
+lip_status lip_plan_tiles(const lip_plan *plan, int32_t set, lip_tile_cfg *cfg);
 
 const char *lip_status_string(lip_status status);
 

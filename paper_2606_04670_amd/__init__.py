@@ -10,4 +10,5 @@ C ABI of include/lipfit.h; this package only binds it.
 from ._lib import LipError, load  # noqa: F401
 from .api import (LipFitFn, Metric, Plan, StepModel, autotune, backward, bounds,  # noqa: F401
                   consistency, estimate_M, fit_eval, fit_eval_k, fit_eval_steps, lipfit, local_knots,
-                  local_steps, smooth_lipschitz, smooth_objective, tune_get, tune_set)
+                  local_steps, smooth_lipschitz, smooth_objective, tune_clear, tune_get,
+                  tune_load, tune_save, tune_set)

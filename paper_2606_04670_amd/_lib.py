@@ -64,8 +64,12 @@ _SIGS = {
     "lip_plan_execute": (i32, [P, P]),
     "lip_plan_destroy": (i32, [P]),
     "lip_tune_get": (i32, [i32, i32, i32, i64, i64, P]),
-    "lip_tune_set": (i32, [i32, i32, i32, P]),
+    "lip_tune_set": (i32, [i32, i32, i32, i64, i64, P]),
     "lip_autotune": (i32, [i32, i32, i32, i64, i64, P, P]),
+    "lip_tune_save": (i32, [ctypes.c_char_p, ctypes.c_char_p]),
+    "lip_tune_load": (i32, [ctypes.c_char_p, ctypes.c_char_p]),
+    "lip_tune_clear": (i32, []),
+    "lip_plan_tiles": (i32, [P, i32, P]),
     "lip_status_string": (ctypes.c_char_p, [i32]),
 }
 

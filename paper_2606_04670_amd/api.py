@@ -466,6 +466,12 @@ class Plan:
         L.check("lip_plan_execute", L.load().lip_plan_execute(self._plan, _stream(self.device)))
         return self.sets
 
+    def tiles(self, i: int) -> dict:
+        """Tile parameters set i runs with (argmin tile, data chunks, waves)."""
+        cfg = L.LipTileCfg()
+        L.check("lip_plan_tiles", L.load().lip_plan_tiles(self._plan, i, ctypes.byref(cfg)))
+        return dict(tile=cfg.tile, split=cfg.split, waves=cfg.waves)
+
     def close(self):
         if self._plan:
             L.load().lip_plan_destroy(self._plan)
@@ -484,13 +490,28 @@ def tune_get(d, n_mon, norm, n, q):
     return dict(tile=cfg.tile, split=cfg.split, waves=cfg.waves)
 
 
-def tune_set(d, n_mon, norm, tile=None, split=None, waves=None, clear=False):
+def tune_set(d, n_mon, norm, tile=None, split=None, waves=None, clear=False, n=0, q=0):
+    """Tile parameters for the size class of (n, q), or every size (n = q = 0)."""
     lib = L.load()
     if clear:
-        L.check("lip_tune_set", lib.lip_tune_set(d, n_mon, NORMS[norm], None))
+        L.check("lip_tune_set", lib.lip_tune_set(d, n_mon, NORMS[norm], n, q, None))
         return
     cfg = L.LipTileCfg(tile, split, waves, 0)
-    L.check("lip_tune_set", lib.lip_tune_set(d, n_mon, NORMS[norm], ctypes.byref(cfg)))
+    L.check("lip_tune_set", lib.lip_tune_set(d, n_mon, NORMS[norm], n, q, ctypes.byref(cfg)))
+
+
+def tune_save(path: str, arch: Optional[str] = None):
+    L.check("lip_tune_save", L.load().lip_tune_save(path.encode(), None if arch is None
+                                                    else arch.encode()))
+
+
+def tune_load(path: str, arch: Optional[str] = None):
+    L.check("lip_tune_load", L.load().lip_tune_load(path.encode(), None if arch is None
+                                                    else arch.encode()))
+
+
+def tune_clear():
+    L.check("lip_tune_clear", L.load().lip_tune_clear())
 
 
 def autotune(d, n_mon, norm, n, q, device=None):

@@ -6,7 +6,10 @@
 // its data into chunks of at most ~4M pairs per work item; the items of a
 // class are sorted longest first and consumed by one persistent kernel per
 // class (every wave pops the next item from a counter), so uneven set sizes
-// balance across the chip.  Sets that need more than one data chunk merge
+// balance across the chip.  Each set's argmin tile comes from the tuning
+// table for its shape and size class (lip_autotune fills it); its data
+// chunks follow from the work-item size, since the items of all sets fill
+// the chip together.  Sets that need more than one data chunk merge
 // their per-chunk results with atomic min on packed 64-bit (value, index)
 // keys, decoded by a finalize kernel.  Staging, key initialisation, the class
 // kernels and the finalize pass are recorded once into a HIP graph, and
@@ -135,6 +138,7 @@ struct lip_plan {
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    std::vector<lip_tile_cfg> tiles;  // per set: argmin tile, data chunks, waves per workgroup
 };
 
 namespace {
@@ -244,6 +248,9 @@ extern "C" lip_status lip_plan_create(lip_plan **plan, const lip_batch_desc *set
     off += align_up(std::max<size_t>(classes.size(), 1) * sizeof(unsigned int), 256);
 
     lip_plan *p = new lip_plan();
+    p->tiles.resize(n_sets);
+    for (int s = 0; s < n_sets; ++s)
+        p->tiles[s] = lip_tile_cfg{sp[s].tile, sp[s].n_chunks, 4, 0};
     if (hipGetDevice(&p->device) != hipSuccess || hipMalloc(&p->mem, off) != hipSuccess) {
         free_plan(p);
         return LIP_E_DEVICE;
@@ -377,6 +384,14 @@ extern "C" lip_status lip_plan_execute(lip_plan *plan, lip_stream stream)
     return dev_status(hipGraphLaunch(plan->exec, (hipStream_t)stream));
 }
 
+extern "C" lip_status lip_plan_tiles(const lip_plan *plan, int32_t set, lip_tile_cfg *cfg)
+{
+    if (!plan || !cfg) return LIP_E_ARG;
+    if (set < 0 || set >= (int32_t)plan->tiles.size()) return LIP_E_SHAPE;
+    *cfg = plan->tiles[set];
+    return LIP_OK;
+}
+
 extern "C" lip_status lip_plan_destroy(lip_plan *plan)
 {
     if (!plan) return LIP_OK;
@@ -454,7 +469,7 @@ extern "C" lip_status lip_autotune(int32_t d, int32_t n_mon, int32_t norm, int64
                        (float *)nullptr, q, d, 2u);
     float best_ms = 1e30f;
     lip_tile_cfg best_cfg = tune_lookup(d, n_mon, norm, n, q);
-    const int tiles[] = {32, 64, 128};
+    const int tiles[] = {16, 32, 64, 128};
     const int splits[] = {1, 2, 4, 8, 16, 32};
     const int waves[] = {2, 4};
     for (int t : tiles)
@@ -487,8 +502,9 @@ extern "C" lip_status lip_autotune(int32_t d, int32_t n_mon, int32_t norm, int64
                 }
             }
     cleanup();
-    st = lip_tune_set(d, n_mon, norm, &best_cfg);
+    st = lip_tune_set(d, n_mon, norm, n, q, &best_cfg);
     if (st != LIP_OK) return st;
+    tune_autosave();
     *best = best_cfg;
     return LIP_OK;
 }

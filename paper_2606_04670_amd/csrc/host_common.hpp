@@ -63,7 +63,12 @@ struct FwdPlan {
     int64_t grid = 0;
 };
 
+// Tile parameters (tune.cpp): the tuning table's entry for the shape and
+// size class of (n, q), else an entry set for every size, else the default.
+lip_tile_cfg default_tile_cfg(int d, int64_t n, int64_t q);
 lip_tile_cfg tune_lookup(int d, int dm, int norm, int64_t n, int64_t q);
+// Writes the table to the file named by LIPFIT_TUNE_CACHE, if set.
+void tune_autosave();
 FwdPlan make_fwd_plan(const MetricInfo &mi, int64_t n, int64_t q, const lip_tile_cfg &cfg);
 
 // Workspace layout of the bound path.
@@ -78,6 +83,11 @@ lip_status run_bounds(const MetricInfo &mi, const float *x, const float *y, int6
                       const float *Mk, const float *xq, int64_t q, float *g, float *h_up,
                       float *h_lo, int32_t *arg_up, int32_t *arg_lo, void *ws, size_t ws_bytes,
                       const lip_tile_cfg &cfg, hipStream_t stream);
+
+// Argument checks of lip_bounds / lip_fit_eval (no HIP call).
+lip_status validate_bounds(const lip_metric *metric, const float *x, const float *y, int64_t n,
+                           float M, const float *Mk, const float *xq, int64_t q, uint32_t flags,
+                           MetricInfo *mi);
 
 // BF16-MFMA l2 variant of run_bounds (bf16_l2.hip).
 lip_status run_bounds_bf16(const MetricInfo &mi, const float *x, const float *y, int64_t n, float M,

@@ -3,10 +3,6 @@
 #include <math.h>
 #include <string.h>
 
-#include <map>
-#include <mutex>
-#include <tuple>
-
 #include "host_common.hpp"
 
 namespace lip {
@@ -108,24 +104,11 @@ size_t partial_bytes(int64_t q)
     return align_up((size_t)entries * 2 * sizeof(float), 256) * 2;
 }
 
-// ---- tuning table -----------------------------------------------------------
-
-namespace {
-std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int>, lip_tile_cfg> g_tune;
-}  // namespace
-
-lip_tile_cfg tune_lookup(int d, int dm, int norm, int64_t n, int64_t q)
+lip_tile_cfg default_tile_cfg(int d, int64_t n, int64_t q)
 {
-    {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        auto it = g_tune.find(std::make_tuple(d, dm, norm));
-        if (it != g_tune.end()) return it->second;
-    }
-    // Default: about 16 waves per SIMD (256 CUs x 4 SIMDs) so that the last
-    // wave of each SIMD starts early (small tail), data split in a
-    // power-of-two number of chunks when the queries alone do not fill the
-    // chip.
+    // About 16 waves per SIMD (256 CUs x 4 SIMDs) so that the last wave of
+    // each SIMD starts early (small tail), data split in a power-of-two
+    // number of chunks when the queries alone do not fill the chip.
     lip_tile_cfg c{};
     c.tile = 32;
     c.waves = 4;
@@ -183,7 +166,9 @@ lip_status run_bounds(const MetricInfo &mi, const float *x, const float *y, int6
 {
     const FwdPlan p = make_fwd_plan(mi, n, q, cfg);
     const size_t sb = staged_bytes(n, mi.d);
-    const size_t need = kOriginBytes + sb + (p.n_chunks > 1 ? partial_bytes(q) : 0);
+    const int64_t entries = (int64_t)p.n_chunks * q;
+    const size_t pbytes = align_up((size_t)entries * 2 * sizeof(float), 256);
+    const size_t need = kOriginBytes + sb + (p.n_chunks > 1 ? 2 * pbytes : 0);
     if (ws_bytes < need) return LIP_E_WORKSPACE;
     FwdLauncher launch = fwd_launchers(mi.norm, mi.d, mi.dm).plain;
     if (!launch) return LIP_E_UNSUPPORTED;
@@ -222,9 +207,8 @@ lip_status run_bounds(const MetricInfo &mi, const float *x, const float *y, int6
     a.arg_lo = arg_lo;
     if (p.n_chunks > 1) {
         char *pb = (char *)ws + sb;
-        const int64_t entries = (int64_t)p.n_chunks * q;
         a.part_v = (float *)pb;
-        a.part_i = (int32_t *)(pb + align_up((size_t)entries * 2 * sizeof(float), 256));
+        a.part_i = (int32_t *)(pb + pbytes);
     }
     launch(a, dim3((unsigned)p.grid), dim3(64 * p.waves), stream);
     if (hipGetLastError() != hipSuccess) return LIP_E_DEVICE;
@@ -245,7 +229,7 @@ lip_status run_bounds(const MetricInfo &mi, const float *x, const float *y, int6
 }
 
 // Validation shared by lip_bounds / lip_fit_eval; no HIP call.
-static lip_status validate_bounds(const lip_metric *metric, const float *x, const float *y,
+lip_status validate_bounds(const lip_metric *metric, const float *x, const float *y,
                                   int64_t n, float M, const float *Mk, const float *xq, int64_t q,
                                   uint32_t flags, MetricInfo *mi)
 {
@@ -327,32 +311,6 @@ lip_status lip_bounds(const lip_metric *metric, const float *x, const float *y, 
 {
     return lip_fit_eval(metric, x, y, n, M, Mk, xq, q, nullptr, h_up, h_lo, arg_up, arg_lo, ws,
                         ws_bytes, flags, stream);
-}
-
-lip_status lip_tune_get(int32_t d, int32_t n_mon, int32_t norm, int64_t n, int64_t q,
-                        lip_tile_cfg *cfg)
-{
-    if (!cfg) return LIP_E_ARG;
-    if (d < 1 || d > kMaxDim || n_mon < 0 || n_mon > d) return LIP_E_SHAPE;
-    if (norm != LIP_L1 && norm != LIP_L2 && norm != LIP_LINF) return LIP_E_ARG;
-    *cfg = tune_lookup(d, n_mon, norm, n, q);
-    return LIP_OK;
-}
-
-lip_status lip_tune_set(int32_t d, int32_t n_mon, int32_t norm, const lip_tile_cfg *cfg)
-{
-    if (d < 1 || d > kMaxDim || n_mon < 0 || n_mon > d) return LIP_E_SHAPE;
-    if (norm != LIP_L1 && norm != LIP_L2 && norm != LIP_LINF) return LIP_E_ARG;
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    if (!cfg) {
-        g_tune.erase(std::make_tuple(d, (int)n_mon, norm));
-        return LIP_OK;
-    }
-    if (cfg->tile < 8 || cfg->tile > kMaxTile || cfg->tile % 8 != 0) return LIP_E_VALUE;
-    if (cfg->split < 1 || cfg->split > kMaxChunks) return LIP_E_VALUE;
-    if (cfg->waves < 1 || cfg->waves > 4) return LIP_E_VALUE;  // kernels are built for <= 256 threads
-    g_tune[std::make_tuple(d, (int)n_mon, norm)] = *cfg;
-    return LIP_OK;
 }
 
 const char *lip_status_string(lip_status status)

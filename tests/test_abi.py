@@ -141,18 +141,83 @@ def test_other_entry_points_validation(L):
 
 def test_tuning_table(L):
     lib = L.load()
+    lib.lip_tune_clear()
     cfg = L.LipTileCfg()
     assert lib.lip_tune_get(4, 2, 1, 100000, 1000000, ctypes.byref(cfg)) == L.LIP_OK
+    default = (cfg.tile, cfg.split, cfg.waves)
     assert cfg.tile % 8 == 0 and cfg.split >= 1 and cfg.waves >= 1
     bad = L.LipTileCfg(12, 1, 4, 0)
-    assert lib.lip_tune_set(4, 2, 1, ctypes.byref(bad)) == L.LIP_E_VALUE
+    assert lib.lip_tune_set(4, 2, 1, 0, 0, ctypes.byref(bad)) == L.LIP_E_VALUE
+    assert lib.lip_tune_set(4, 2, 1, 10, 0, ctypes.byref(bad)) == L.LIP_E_SHAPE
+    # an entry for every size
     good = L.LipTileCfg(128, 2, 2, 0)
-    assert lib.lip_tune_set(4, 2, 1, ctypes.byref(good)) == L.LIP_OK
+    assert lib.lip_tune_set(4, 2, 1, 0, 0, ctypes.byref(good)) == L.LIP_OK
     got = L.LipTileCfg()
     lib.lip_tune_get(4, 2, 1, 10, 10, ctypes.byref(got))
     assert (got.tile, got.split, got.waves) == (128, 2, 2)
-    assert lib.lip_tune_set(4, 2, 1, None) == L.LIP_OK
+    # an entry for one size class (factor-4 buckets of n and q) wins over it
+    sized = L.LipTileCfg(16, 8, 4, 0)
+    assert lib.lip_tune_set(4, 2, 1, 100000, 1000000, ctypes.byref(sized)) == L.LIP_OK
+    for n, q in ((100000, 1000000), (70000, 1048575), (131071, 800000)):
+        lib.lip_tune_get(4, 2, 1, n, q, ctypes.byref(got))
+        assert (got.tile, got.split, got.waves) == (16, 8, 4), (n, q)
+    for n, q in ((100000, 4000), (1000, 1000000), (300000, 1000000)):
+        lib.lip_tune_get(4, 2, 1, n, q, ctypes.byref(got))
+        assert (got.tile, got.split, got.waves) == (128, 2, 2), (n, q)
+    # removing both entries restores the default
+    assert lib.lip_tune_set(4, 2, 1, 100000, 1000000, None) == L.LIP_OK
+    assert lib.lip_tune_set(4, 2, 1, 0, 0, None) == L.LIP_OK
+    lib.lip_tune_get(4, 2, 1, 100000, 1000000, ctypes.byref(got))
+    assert (got.tile, got.split, got.waves) == default
     assert lib.lip_tune_get(4, 5, 1, 10, 10, ctypes.byref(got)) == L.LIP_E_SHAPE
+
+
+def test_tune_cache_file(L, tmp_path):
+    """lip_tune_save / lip_tune_load: round trip, architecture filter,
+    malformed files change nothing."""
+    lib = L.load()
+    lib.lip_tune_clear()
+    a = L.LipTileCfg(64, 4, 2, 0)
+    b = L.LipTileCfg(32, 1, 4, 0)
+    assert lib.lip_tune_set(3, 1, 2, 5000, 20000, ctypes.byref(a)) == L.LIP_OK
+    assert lib.lip_tune_set(7, 0, 3, 0, 0, ctypes.byref(b)) == L.LIP_OK
+    path = str(tmp_path / "tune.json")
+    assert lib.lip_tune_save(path.encode(), b"gfx950") == L.LIP_OK
+    import json
+    doc = json.load(open(path))
+    assert doc["format"] == "lipfit-tune-1"
+    assert sorted((e["d"], e["n_class"], e["tile"]) for e in doc["entries"]) == [(3, 6, 64),
+                                                                                (7, -1, 32)]
+    lib.lip_tune_clear()
+    got = L.LipTileCfg()
+    # another architecture's entries are not loaded
+    assert lib.lip_tune_load(path.encode(), b"gfx942") == L.LIP_OK
+    lib.lip_tune_get(3, 1, 2, 5000, 20000, ctypes.byref(got))
+    assert got.tile != 64 or got.split != 4
+    assert lib.lip_tune_load(path.encode(), b"gfx950") == L.LIP_OK
+    lib.lip_tune_get(3, 1, 2, 5000, 20000, ctypes.byref(got))
+    assert (got.tile, got.split, got.waves) == (64, 4, 2)
+    lib.lip_tune_get(7, 0, 3, 123, 456, ctypes.byref(got))
+    assert (got.tile, got.split, got.waves) == (32, 1, 4)
+    # malformed or invalid files: LIP_E_VALUE and no change
+    lib.lip_tune_clear()
+    for text in ('{"format": "other", "entries": []}',
+                 '{"format": "lipfit-tune-1", "entries": [{"arch": "gfx950", "d": 3}]}',
+                 doc_text_bad_tile(),
+                 '{"format": "lipfit-tune-1", "entries": [',
+                 'not json'):
+        bad = tmp_path / "bad.json"
+        bad.write_text(text)
+        assert lib.lip_tune_load(str(bad).encode(), b"gfx950") == L.LIP_E_VALUE, text
+    lib.lip_tune_get(3, 1, 2, 5000, 20000, ctypes.byref(got))
+    assert (got.tile, got.split) != (64, 4)
+    assert lib.lip_tune_load(str(tmp_path / "missing.json").encode(), b"gfx950") == L.LIP_E_ARG
+    lib.lip_tune_clear()
+
+
+def doc_text_bad_tile():
+    return ('{"format": "lipfit-tune-1", "entries": [{"arch": "gfx950", "d": 3, "n_mon": 1, '
+            '"norm": 2, "n_class": 6, "q_class": 7, "tile": 12, "split": 1, "waves": 4}]}')
 
 
 def test_python_binding_refuses_cpu_tensors():

@@ -102,3 +102,52 @@ def test_batched_workload_full(lf):
         qidx = np.sort(rng.choice(p.q, 4, replace=False))
         check_bounds(p, got[k], qidx=qidx, label=f"batched workload set {k}")
     plan.close()
+
+
+def test_autotuned_tiles_used_by_plans(lf, tmp_path, monkeypatch):
+    """lip_autotune on a batched shape class (d = 4, two increasing
+    coordinates, l2, N = 5,000, Q = 20,000) stores a configuration for that
+    size class; a plan built afterwards runs those sets with the tuned tile
+    (lip_plan_tiles); its outputs equal those of a plan with the default
+    tiles bit for bit; the table round-trips through the cache file."""
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("LIPFIT_TUNE_CACHE", str(cache))
+    lf.tune_clear()
+    probs = []
+    for k, (n, q) in enumerate([(5000, 20000), (4100, 16400), (6000, 24000)]):
+        probs.append(W.random_problem(950 + k, n=n, q=q, d=4, norm=2,
+                                      mon=np.array([0, 1, 0, 1], np.int8)))
+    probs.append(W.random_problem(960, n=700, q=2800, d=3, norm=1, mon=np.array([1, 0, 0], np.int8)))
+    sets = _sets_from(probs, lf)
+    default = lf.tune_get(4, 2, "l2", 5000, 20000)
+    plan0 = lf.Plan(sets)
+    assert plan0.tiles(0)["tile"] == default["tile"]
+    ref = [{k: v.cpu().numpy() for k, v in o.items()} for o in plan0.execute()]
+    torch.cuda.synchronize()
+    plan0.close()
+    best = lf.autotune(4, 2, "l2", 5000, 20000)
+    assert best == lf.tune_get(4, 2, "l2", 5000, 20000)
+    assert best == lf.tune_get(4, 2, "l2", 4100, 16400)       # same size class
+    assert lf.tune_get(4, 2, "l2", 50, 200)["tile"] == 32   # another size class: default
+    # the autotuner wrote the table to LIPFIT_TUNE_CACHE
+    import json
+    doc = json.loads(cache.read_text())
+    assert any(e["d"] == 4 and e["n_mon"] == 2 and e["norm"] == 2 and e["tile"] == best["tile"]
+               for e in doc["entries"])
+    plan = lf.Plan(sets)
+    for i in range(3):
+        assert plan.tiles(i)["tile"] == best["tile"], (i, plan.tiles(i), best)
+    got = [{k: v.cpu().numpy() for k, v in o.items()} for o in plan.execute()]
+    torch.cuda.synchronize()
+    plan.close()
+    _compare_identical(got, ref)
+    _compare_identical(got, _per_set(lf, sets))
+    for k, p in enumerate(probs):
+        qidx = np.unique(np.linspace(0, p.q - 1, 32).astype(int))
+        check_bounds(p, got[k], qidx=qidx, label=f"tuned plan set {k}")
+    # the cache file restores the table
+    lf.tune_clear()
+    assert lf.tune_get(4, 2, "l2", 5000, 20000) == default
+    lf.tune_load(str(cache))
+    assert lf.tune_get(4, 2, "l2", 5000, 20000) == best
+    lf.tune_clear()
