@@ -134,6 +134,23 @@ lip_status lip_fit_eval(const lip_metric *metric, const float *x, const float *y
                         float *g, float *h_up, float *h_lo, int32_t *arg_up, int32_t *arg_lo,
                         void *ws, size_t ws_bytes, uint32_t flags, lip_stream stream);
 
+/* lip_fit_eval for callers that cannot allocate device memory (code under
+ * HIP stream capture, tight serving loops, harnesses that forbid
+ * allocation): the same arguments without ws / ws_bytes, the same results
+ * bit for bit.  Scratch memory is a 64 MiB device array of the library (one
+ * per GPU, held until the process ends); nothing is allocated per call.
+ * Limits: the staged data, (n + 256) (d + 3) 4 bytes plus about 31 KiB,
+ * must fit in 64 MiB (n up to about 2.39e6 at d = 4, 0.88e6 at d = 16),
+ * else LIP_E_SHAPE; the data split is reduced until its partial results fit
+ * too.  flags must be 0 and the LIP_MON_CASE kinds are not accepted
+ * (LIP_E_UNSUPPORTED).  Calls that overlap on one GPU (different streams or
+ * threads without ordering) share the array and race; calls on one stream
+ * are safe. */
+lip_status lip_fit_eval_noalloc(const lip_metric *metric, const float *x, const float *y,
+                                int64_t n, float M, const float *Mk, const float *xq, int64_t q,
+                                float *g, float *h_up, float *h_lo, int32_t *arg_up,
+                                int32_t *arg_lo, uint32_t flags, lip_stream stream);
+
 /* Subgradients of g (and of H_up, H_lo) through the indices a = arg_up[j],
  * b = arg_lo[j] saved by the forward (the chain rule applied to Eq. 2-3):
  *   G_up = dg/2 + dh_up,  G_lo = dg/2 + dh_lo    (missing arrays count 0)

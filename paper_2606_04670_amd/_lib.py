@@ -51,6 +51,7 @@ _SIGS = {
     "lip_workspace_size": (sz, [i64, i64, i32, u32]),
     "lip_bounds": (i32, [P, P, P, i64, f32, P, P, i64, P, P, P, P, P, sz, u32, P]),
     "lip_fit_eval": (i32, [P, P, P, i64, f32, P, P, i64, P, P, P, P, P, P, sz, u32, P]),
+    "lip_fit_eval_noalloc": (i32, [P, P, P, i64, f32, P, P, i64, P, P, P, P, P, u32, P]),
     "lip_fit_backward": (i32, [P, P, P, i64, f32, P, P, i64, P, P, P, P, P, P, P, P, P, sz, u32,
                                P]),
     "lip_consistency": (i32, [P, P, P, i64, f32, P, f64, P, P, P, P, P, P, sz, u32, P]),
