@@ -165,7 +165,9 @@ lip_status lip_fit_eval_noalloc(const lip_metric *metric, const float *x, const 
  *   dy [n]                optional, ACCUMULATED (the caller zeroes it)
  *   dM [1] or [n]         optional, ACCUMULATED
  * Uses FP32 atomics for dy / dM unless LIP_FLAG_DETERMINISTIC, which takes
- * ws (>= lip_workspace_size) and gives bitwise reproducible sums. */
+ * ws (>= lip_workspace_size) and gives bitwise reproducible sums.
+ * LIP_FLAG_CHECK_FINITE (needs ws too) scans x, Mk, xq and the upstream
+ * gradients first. */
 lip_status lip_fit_backward(const lip_metric *metric, const float *x, const float *y, int64_t n,
                             float M, const float *Mk, const float *xq, int64_t q,
                             const int32_t *arg_up, const int32_t *arg_lo,
@@ -183,11 +185,18 @@ lip_status lip_fit_backward(const lip_metric *metric, const float *x, const floa
  * coordinates accumulated in index order, correctly rounded operations.
  *   counts [2] (int64, required)  number of ordered pairs with t_up < -tol
  *                                 and with t_lo < -tol (overwritten)
+ *   worst_slack [1] (FP64), worst_pair [2] (int64), optional: the smallest
+ *                                 t_up or t_lo over all ordered pairs and the
+ *                                 pair (i, k) attaining it, lowest i then
+ *                                 lowest k on ties (+inf and (-1, -1) if
+ *                                 n == 1); the data are consistent with
+ *                                 tolerance tol iff worst_slack >= -tol
  *   slack_up, slack_lo [n]        optional: min_k t_up, min_k t_lo (+inf if n == 1)
  *   partner_up, partner_lo [n]    optional: the k attaining them (lowest on ties)
  * Equality (|y_i - y_k| = M dist) is consistent.  Needs ws. */
 lip_status lip_consistency(const lip_metric *metric, const float *x, const float *y, int64_t n,
                            float M, const float *Mk, double tol, int64_t *counts,
+                           double *worst_slack, int64_t *worst_pair,
                            double *slack_up, double *slack_lo,
                            int32_t *partner_up, int32_t *partner_lo,
                            void *ws, size_t ws_bytes, uint32_t flags, lip_stream stream);
@@ -208,8 +217,11 @@ lip_status lip_consistency(const lip_metric *metric, const float *x, const float
  *   M64 [n] optional, M32 [n] optional (rounded up), pair unused.
  * Coincident points with equal y are skipped; coincident points with
  * different y make the slope infinite: the result is +inf (and, for
- * LIP_M_GLOBAL, pair names the lowest such pair).  knn in 1..LIP_MAX_KNN.
- * Needs ws. */
+ * LIP_M_GLOBAL, pair names the lowest such pair).  The call is asynchronous,
+ * so it reports an infinite estimate through the outputs; with
+ * LIP_FLAG_CHECK_FINITE it also synchronises at the end and returns
+ * LIP_E_VALUE when an estimate written to M64 or M32 is infinite (the
+ * outputs are written either way).  knn in 1..LIP_MAX_KNN.  Needs ws. */
 lip_status lip_estimate_M(const lip_metric *metric, const float *x, const float *y, int64_t n,
                           int32_t mode, int32_t knn, double *M64, float *M32, int64_t *pair,
                           void *ws, size_t ws_bytes, uint32_t flags, lip_stream stream);

@@ -155,7 +155,18 @@ def consistency(x, y, norm: int, M: float = 0.0, Mk=None, mon=None, w=None, tol:
     _load().orc_consistency(d, norm, _p(w), _p(mon), _p(x), _p(y), x.shape[0], float(M), _p(Mk),
                             float(tol), _p(rows_a), nr, _p(su), _p(sl), _p(pu), _p(pl),
                             _p(vu), _p(vl))
-    return dict(slack_up=su, slack_lo=sl, partner_up=pu, partner_lo=pl, viol_up=vu, viol_lo=vl)
+    # the smallest of all slack terms over the rows checked, with its ordered
+    # pair (row i, partner k), lowest i then lowest k on ties; no pair: inf
+    ri = np.arange(x.shape[0]) if rows_a is None else rows_a
+    v, i, k = np.concatenate([su, sl]), np.concatenate([ri, ri]), np.concatenate([pu, pl])
+    has = k >= 0
+    best = (np.inf, -1, -1)
+    if has.any():
+        v, i, k = v[has], i[has], k[has]
+        j = np.lexsort((k, i, v))[0]
+        best = (float(v[j]), int(i[j]), int(k[j]))
+    return dict(slack_up=su, slack_lo=sl, partner_up=pu, partner_lo=pl, viol_up=vu, viol_lo=vl,
+                worst_slack=best[0], worst_pair=(best[1], best[2]))
 
 
 def estimate_M_global(x, y, norm: int, w=None):

@@ -54,7 +54,7 @@ _SIGS = {
     "lip_fit_eval_noalloc": (i32, [P, P, P, i64, f32, P, P, i64, P, P, P, P, P, u32, P]),
     "lip_fit_backward": (i32, [P, P, P, i64, f32, P, P, i64, P, P, P, P, P, P, P, P, P, sz, u32,
                                P]),
-    "lip_consistency": (i32, [P, P, P, i64, f32, P, f64, P, P, P, P, P, P, sz, u32, P]),
+    "lip_consistency": (i32, [P, P, P, i64, f32, P, f64, P, P, P, P, P, P, P, P, sz, u32, P]),
     "lip_estimate_M": (i32, [P, P, P, i64, i32, i32, P, P, P, P, sz, u32, P]),
     "lip_local_knots": (i32, [P, P, i64, P, i64, P, i32, P, P, sz, u32, P]),
     "lip_local_steps": (i32, [P, P, P, i64, P, i32, P, P, P, P, sz, u32, P]),

@@ -135,7 +135,7 @@ def fit_eval(x: torch.Tensor, y: torch.Tensor, xq: torch.Tensor, metric: Metric,
 
 
 def fit_eval_k(x, y, xq, metric: Metric, wk, M=None, Mk=None,
-               want=("g", "h_up", "h_lo")) -> Dict[str, torch.Tensor]:
+               want=("g", "h_up", "h_lo"), check_finite: bool = False) -> Dict[str, torch.Tensor]:
     """Weighted k-best bounds (k = len(wk)) and their midpoint."""
     x, y, M, Mk, dev = _prep(x, y, M, Mk)
     xq = _f32(xq, "xq", dev)
@@ -147,7 +147,7 @@ def fit_eval_k(x, y, xq, metric: Metric, wk, M=None, Mk=None,
     st = lib.lip_fit_eval_k(metric.ref(), _ptr(x), _ptr(y), n, M, _ptr(Mk), w.shape[0],
                             w.ctypes.data_as(ctypes.c_void_p), _ptr(xq), q, _ptr(out.get("g")),
                             _ptr(out.get("h_up")), _ptr(out.get("h_lo")), _ptr(ws), ws.numel(),
-                            0, _stream(dev))
+                            L.LIP_FLAG_CHECK_FINITE if check_finite else 0, _stream(dev))
     L.check("lip_fit_eval_k", st)
     return out
 
@@ -158,7 +158,7 @@ def bounds(x, y, xq, metric: Metric, M=None, Mk=None, **kw):
 
 def backward(x, y, xq, metric: Metric, arg_up, arg_lo, dg=None, dh_up=None, dh_lo=None,
              M=None, Mk=None, want_dxq=True, want_dy=True, want_dM=True,
-             deterministic: bool = False):
+             deterministic: bool = False, check_finite: bool = False):
     """Subgradients through the saved indices: returns (dxq, dy, dM)."""
     x, y, M, Mk, dev = _prep(x, y, M, Mk)
     xq = _f32(xq, "xq", dev)
@@ -171,7 +171,8 @@ def backward(x, y, xq, metric: Metric, arg_up, arg_lo, dg=None, dh_up=None, dh_l
     dy = torch.zeros(n, dtype=torch.float32, device=dev) if want_dy else None
     dM = (torch.zeros(n if Mk is not None else 1, dtype=torch.float32, device=dev)
           if want_dM else None)
-    flags = L.LIP_FLAG_DETERMINISTIC if deterministic else 0
+    flags = (L.LIP_FLAG_DETERMINISTIC if deterministic else 0) | \
+        (L.LIP_FLAG_CHECK_FINITE if check_finite else 0)
     lib = L.load()
     ws = workspace(dev, lib.lip_workspace_size(n, q, metric.d, flags))
     st = lib.lip_fit_backward(metric.ref(), _ptr(x), _ptr(y), n, M, _ptr(Mk), _ptr(xq), q,
@@ -182,12 +183,17 @@ def backward(x, y, xq, metric: Metric, arg_up, arg_lo, dg=None, dh_up=None, dh_l
 
 
 def consistency(x, y, metric: Metric, M=None, Mk=None, tol: float = 0.0,
-                per_row: bool = True) -> Dict[str, torch.Tensor]:
-    """FP64 pairwise consistency check; counts[0] / counts[1] = violations up / lo."""
+                per_row: bool = True, worst: bool = True,
+                check_finite: bool = False) -> Dict[str, torch.Tensor]:
+    """FP64 pairwise consistency check; counts[0] / counts[1] = violations up / lo,
+    worst_slack[1] and worst_pair[2] the smallest slack and its (i, k)."""
     x, y, M, Mk, dev = _prep(x, y, M, Mk)
     n = x.shape[0]
     counts = torch.zeros(2, dtype=torch.int64, device=dev)
     out = {"counts": counts}
+    if worst:
+        out["worst_slack"] = torch.empty(1, dtype=torch.float64, device=dev)
+        out["worst_pair"] = torch.empty(2, dtype=torch.int64, device=dev)
     if per_row:
         out["slack_up"] = torch.empty(n, dtype=torch.float64, device=dev)
         out["slack_lo"] = torch.empty(n, dtype=torch.float64, device=dev)
@@ -195,16 +201,20 @@ def consistency(x, y, metric: Metric, M=None, Mk=None, tol: float = 0.0,
         out["partner_lo"] = torch.empty(n, dtype=torch.int32, device=dev)
     lib = L.load()
     ws = workspace(dev, lib.lip_workspace_size(n, 0, metric.d, 0))
+    flags = L.LIP_FLAG_CHECK_FINITE if check_finite else 0
     st = lib.lip_consistency(metric.ref(), _ptr(x), _ptr(y), n, M, _ptr(Mk), float(tol),
-                             _ptr(counts), _ptr(out.get("slack_up")), _ptr(out.get("slack_lo")),
+                             _ptr(counts), _ptr(out.get("worst_slack")), _ptr(out.get("worst_pair")),
+                             _ptr(out.get("slack_up")), _ptr(out.get("slack_lo")),
                              _ptr(out.get("partner_up")), _ptr(out.get("partner_lo")), _ptr(ws),
-                             ws.numel(), 0, _stream(dev))
+                             ws.numel(), flags, _stream(dev))
     L.check("lip_consistency", st)
     return out
 
 
-def estimate_M(x, y, metric: Metric, mode: str = "global", knn: int = 16):
-    """Global: (M64[1], M32[1], pair[2]); local kNN: (M64[n], M32[n], None)."""
+def estimate_M(x, y, metric: Metric, mode: str = "global", knn: int = 16,
+               check_finite: bool = False):
+    """Global: (M64[1], M32[1], pair[2]); local kNN: (M64[n], M32[n], None).
+    check_finite: scan the inputs first and raise on an infinite estimate."""
     x = _f32(x, "x")
     dev = x.device
     y = _f32(y, "y", dev)
@@ -216,8 +226,9 @@ def estimate_M(x, y, metric: Metric, mode: str = "global", knn: int = 16):
     pair = torch.empty(2, dtype=torch.int64, device=dev) if m == L.LIP_M_GLOBAL else None
     lib = L.load()
     ws = workspace(dev, lib.lip_workspace_size(n, 0, metric.d, 0))
+    flags = L.LIP_FLAG_CHECK_FINITE if check_finite else 0
     st = lib.lip_estimate_M(metric.ref(), _ptr(x), _ptr(y), n, m, int(knn), _ptr(M64), _ptr(M32),
-                            _ptr(pair), _ptr(ws), ws.numel(), 0, _stream(dev))
+                            _ptr(pair), _ptr(ws), ws.numel(), flags, _stream(dev))
     L.check("lip_estimate_M", st)
     return M64, M32, pair
 
@@ -250,7 +261,8 @@ def local_knots(x: torch.Tensor, metric: Metric, pairs, probs) -> torch.Tensor:
     return out
 
 
-def local_steps(x: torch.Tensor, y: torch.Tensor, metric: Metric, knots):
+def local_steps(x: torch.Tensor, y: torch.Tensor, metric: Metric, knots,
+                check_finite: bool = False):
     """Step tables: (d1 float64 [n], V64 float64 [n, K+2], V32 float32 [n, K+2]).
     knots: host array-like or tensor (copied to the host)."""
     x = _f32(x, "x")
@@ -266,7 +278,8 @@ def local_steps(x: torch.Tensor, y: torch.Tensor, metric: Metric, knots):
     ws = workspace(dev, lib.lip_workspace_size(n, 0, metric.d, 0))
     st = lib.lip_local_steps(metric.ref(), _ptr(x), _ptr(y), n,
                              kn.ctypes.data_as(ctypes.c_void_p) if K else None, K, _ptr(d1),
-                             _ptr(V64), _ptr(V32), _ptr(ws), ws.numel(), 0, _stream(dev))
+                             _ptr(V64), _ptr(V32), _ptr(ws), ws.numel(),
+                             L.LIP_FLAG_CHECK_FINITE if check_finite else 0, _stream(dev))
     L.check("lip_local_steps", st)
     return d1, V64, V32
 
@@ -336,7 +349,8 @@ class StepModel:
 
 
 def smooth_objective(x, y, eps, metric: Metric, M=None, Mk=None, p: float = 1.0,
-                     prune: float = 0.0, want_F: bool = True, want_grad: bool = True):
+                     prune: float = 0.0, want_F: bool = True, want_grad: bool = True,
+                     check_finite: bool = False):
     """Eq. (7) at the corrections eps: (F float64 [1] tensor or None,
     grad float32 [n] tensor or None).  prune = c > 0 leaves out the pairs of
     the Sec. 5 pre-screening (data within c times their Lipschitz allowance;
@@ -350,7 +364,7 @@ def smooth_objective(x, y, eps, metric: Metric, M=None, Mk=None, p: float = 1.0,
     ws = workspace(dev, lib.lip_workspace_size(n, 0, metric.d, 0))
     st = lib.lip_smooth_objective(metric.ref(), _ptr(x), _ptr(y), n, M, _ptr(Mk), _ptr(eps),
                                   float(p), float(prune), _ptr(F), _ptr(g), _ptr(ws),
-                                  ws.numel(), 0,
+                                  ws.numel(), L.LIP_FLAG_CHECK_FINITE if check_finite else 0,
                                   _stream(dev))
     L.check("lip_smooth_objective", st)
     return F, g

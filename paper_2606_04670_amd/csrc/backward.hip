@@ -265,9 +265,17 @@ extern "C" lip_status lip_fit_backward(const lip_metric *metric, const float *x,
     if (!x || (q > 0 && (!xq || !arg_up || !arg_lo))) return LIP_E_ARG;
     if (!Mk && (!(M >= 0.0f) || !__builtin_isfinite(M))) return LIP_E_VALUE;
     const bool det = (flags & LIP_FLAG_DETERMINISTIC) != 0;
-    if (det && (!ws || ws_bytes < backward_ws_bytes(n))) return LIP_E_WORKSPACE;
+    const bool chk = (flags & LIP_FLAG_CHECK_FINITE) != 0;
+    if ((det || chk) && (!ws || ws_bytes < backward_ws_bytes(n))) return LIP_E_WORKSPACE;
     if (q == 0) return LIP_OK;
     hipStream_t s = (hipStream_t)stream;
+    if (chk) {
+        const float *arr[6] = {x, Mk, xq, dg, dh_up, dh_lo};
+        const int64_t cnt[6] = {n * mi.d, Mk ? n : 0, q * mi.d, dg ? q : 0, dh_up ? q : 0,
+                                dh_lo ? q : 0};
+        st = check_finite(arr, cnt, 6, ws, s);
+        if (st != LIP_OK) return st;
+    }
     BwdArgs a{};
     a.x = x;
     a.Mk = Mk;

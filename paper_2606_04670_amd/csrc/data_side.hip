@@ -236,6 +236,73 @@ __global__ void consistency_combine_kernel(DsArgs A)
     if (A.partner_lo) A.partner_lo[i] = pl;
 }
 
+// Smallest slack over all rows and both bounds, with the pair attaining it:
+// (value, row i, partner k) compared lexicographically, so ties go to the
+// lowest i, then the lowest k.  No pair at all (n == 1): +inf and (-1, -1).
+// One workgroup of 1024 threads.
+__global__ void __launch_bounds__(1024) worst_slack_kernel(const double *su, const double *sl,
+                                                           const int32_t *pu, const int32_t *pl,
+                                                           int64_t n, double *worst,
+                                                           int64_t *pair)
+{
+    __shared__ double sv[1024];
+    __shared__ long long si[1024], sk[1024];
+    double bv = __builtin_inf();
+    long long bi = -1, bk = -1;
+    auto better = [](double v, long long i, long long k, double bv, long long bi, long long bk) {
+        if (k < 0) return false;
+        if (bk < 0) return true;
+        if (v != bv) return v < bv;
+        if (i != bi) return i < bi;
+        return k < bk;
+    };
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        if (better(su[i], i, pu[i], bv, bi, bk)) {
+            bv = su[i];
+            bi = i;
+            bk = pu[i];
+        }
+        if (better(sl[i], i, pl[i], bv, bi, bk)) {
+            bv = sl[i];
+            bi = i;
+            bk = pl[i];
+        }
+    }
+    sv[threadIdx.x] = bv;
+    si[threadIdx.x] = bi;
+    sk[threadIdx.x] = bk;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            const int o = threadIdx.x + h;
+            if (better(sv[o], si[o], sk[o], sv[threadIdx.x], si[threadIdx.x], sk[threadIdx.x])) {
+                sv[threadIdx.x] = sv[o];
+                si[threadIdx.x] = si[o];
+                sk[threadIdx.x] = sk[o];
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (worst) worst[0] = sk[0] >= 0 ? sv[0] : __builtin_inf();
+        if (pair) {
+            pair[0] = sk[0] >= 0 ? si[0] : -1;
+            pair[1] = sk[0] >= 0 ? sk[0] : -1;
+        }
+    }
+}
+
+// Sets flag[0] to 1 if any of the n values (FP64 when v64, else FP32) is
+// +inf (an infinite slope).
+__global__ void any_inf_kernel(const double *v64, const float *v32, int64_t n, int *flag)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int bad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        bad |= v64 ? (v64[i] == __builtin_inf()) : (v32[i] == __builtin_inff());
+    if (bad) atomicOr(flag, 1);
+}
+
 // Single-workgroup reduction over all (chunk, row) slope partials.  Order: a
 // coincident pair with different values (lowest i, then lowest k) wins
 // outright; otherwise the largest slope, then the lowest i, then the lowest
@@ -330,7 +397,8 @@ size_t data_side_ws_bytes(int64_t n, int d)
 {
     const size_t staged = align_up((size_t)ds_npad(n) * (size_t)(d + 2) * 8, 256);
     const size_t cons = align_up((size_t)kDsMaxChunks * (size_t)n * 24, 256) +
-                        align_up((size_t)ds_npad(n) * (size_t)(d + 2) * 4, 256) + 256;
+                        align_up((size_t)ds_npad(n) * (size_t)(d + 2) * 4, 256) + 256 +
+                        align_up((size_t)n * 24, 256);
     const size_t knn = align_up((size_t)n * 4, 256) + align_up((size_t)n * kKnnCap * 4, 256) +
                        align_up((size_t)sort_len(n) * 8, 256) + align_up((size_t)n * 8, 256) +
                        2 * kMaxDim * 8;
@@ -388,9 +456,10 @@ using namespace lip;
 
 extern "C" lip_status lip_consistency(const lip_metric *metric, const float *x, const float *y,
                                       int64_t n, float M, const float *Mk, double tol,
-                                      int64_t *counts, double *slack_up, double *slack_lo,
-                                      int32_t *partner_up, int32_t *partner_lo, void *ws,
-                                      size_t ws_bytes, uint32_t flags, lip_stream stream)
+                                      int64_t *counts, double *worst_slack, int64_t *worst_pair,
+                                      double *slack_up, double *slack_lo, int32_t *partner_up,
+                                      int32_t *partner_lo, void *ws, size_t ws_bytes,
+                                      uint32_t flags, lip_stream stream)
 {
     MetricInfo mi;
     lip_status st = parse_metric(metric, &mi);
@@ -431,12 +500,18 @@ extern "C" lip_status lip_consistency(const lip_metric *metric, const float *x, 
     float *c32 = (float *)q;
     q += align_up((size_t)A.npad * (size_t)(mi.d + 2) * 4, 256);
     double *cE = (double *)q;
+    q += 256;
     A.c32 = c32;
     A.cE = cE;
-    A.slack_up = slack_up;
-    A.slack_lo = slack_lo;
-    A.partner_up = partner_up;
-    A.partner_lo = partner_lo;
+    // the worst pair needs every row's slacks and partners: rows the caller
+    // did not ask for go to the workspace
+    const bool worst = worst_slack || worst_pair;
+    double *row_v = (double *)q;
+    int32_t *row_i = (int32_t *)(row_v + 2 * n);
+    A.slack_up = slack_up ? slack_up : (worst ? row_v : nullptr);
+    A.slack_lo = slack_lo ? slack_lo : (worst ? row_v + n : nullptr);
+    A.partner_up = partner_up ? partner_up : (worst ? row_i : nullptr);
+    A.partner_lo = partner_lo ? partner_lo : (worst ? row_i + n : nullptr);
     A.counts = (unsigned long long *)counts;
     if (launch_stage64(mi.d, x, y, Mk, M, n, A.npad, sg, (double *)ws, s) != hipSuccess)
         return LIP_E_DEVICE;
@@ -452,9 +527,14 @@ extern "C" lip_status lip_consistency(const lip_metric *metric, const float *x, 
     hipLaunchKernelGGL(zero_counts_kernel, dim3(1), dim3(64), 0, s, A.counts);
     (mi.dm > 0 ? L.consistency_mon : L.consistency)(A, dim3(grid_for_rows(n, rows, A.n_chunks)),
                                                     dim3(256), s);
-    if (A.n_chunks > 1 && (slack_up || slack_lo || partner_up || partner_lo))
+    if (A.n_chunks > 1 && (A.slack_up || A.slack_lo || A.partner_up || A.partner_lo))
         hipLaunchKernelGGL(consistency_combine_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256),
                            0, s, A);
+    if (worst)
+        hipLaunchKernelGGL(worst_slack_kernel, dim3(1), dim3(1024), 0, s,
+                           (const double *)A.slack_up, (const double *)A.slack_lo,
+                           (const int32_t *)A.partner_up, (const int32_t *)A.partner_lo, n,
+                           worst_slack, worst_pair);
     return dev_status(hipGetLastError());
 }
 
@@ -535,5 +615,22 @@ extern "C" lip_status lip_estimate_M(const lip_metric *metric, const float *x, c
         L.scan(A, dim3(grid_for_rows(n, rows, A.n_chunks)), dim3(256), s);
         (K == 16 ? L.select16 : L.select32)(A, dim3((unsigned)((n + 255) / 256)), dim3(256), s);
     }
-    return dev_status(hipGetLastError());
+    if (hipGetLastError() != hipSuccess) return LIP_E_DEVICE;
+    // with the synchronous checks: an infinite estimate (coincident data with
+    // different values) is reported as LIP_E_VALUE
+    if ((flags & LIP_FLAG_CHECK_FINITE) && (M64 || M32)) {
+        int *flag = (int *)((char *)ws + data_side_ws_bytes(n, mi.d) - 256);
+        const int64_t cnt = mode == LIP_M_GLOBAL ? 1 : n;
+        if (launch_fill_i32(flag, 1, 0, s) != hipSuccess) return LIP_E_DEVICE;
+        int64_t g = (cnt + 255) / 256;
+        if (g > 1024) g = 1024;
+        hipLaunchKernelGGL(any_inf_kernel, dim3((unsigned)g), dim3(256), 0, s,
+                           (const double *)M64, (const float *)M32, cnt, flag);
+        int host = 0;
+        if (hipMemcpyAsync(&host, flag, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return LIP_E_DEVICE;
+        if (host) return LIP_E_VALUE;
+    }
+    return LIP_OK;
 }

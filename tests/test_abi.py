@@ -122,11 +122,11 @@ def test_other_entry_points_validation(L):
     assert lib.lip_fit_backward(ctypes.byref(m), FAKE, FAKE, 10, 1.0, None, FAKE, 0, FAKE, FAKE,
                                 FAKE, None, None, FAKE, FAKE, FAKE, None, 0, 0, None) == L.LIP_OK
     # consistency
-    assert lib.lip_consistency(ctypes.byref(m), FAKE, FAKE, 10, 1.0, None, -1.0, FAKE, None, None,
+    assert lib.lip_consistency(ctypes.byref(m), FAKE, FAKE, 10, 1.0, None, -1.0, FAKE, None, None, None, None,
                                None, None, FAKE, 1 << 30, 0, None) == L.LIP_E_VALUE
-    assert lib.lip_consistency(ctypes.byref(m), FAKE, FAKE, 10, 1.0, None, 0.0, None, None, None,
+    assert lib.lip_consistency(ctypes.byref(m), FAKE, FAKE, 10, 1.0, None, 0.0, None, None, None, None, None,
                                None, None, FAKE, 1 << 30, 0, None) == L.LIP_E_ARG
-    assert lib.lip_consistency(ctypes.byref(m), FAKE, FAKE, 10, 1.0, None, 0.0, FAKE, None, None,
+    assert lib.lip_consistency(ctypes.byref(m), FAKE, FAKE, 10, 1.0, None, 0.0, FAKE, None, None, None, None,
                                None, None, FAKE, 16, 0, None) == L.LIP_E_WORKSPACE
     # estimate_M
     assert lib.lip_estimate_M(ctypes.byref(m), FAKE, FAKE, 10, 7, 16, None, None, None, FAKE,
@@ -338,5 +338,5 @@ def test_regional_metric_validation(L):
     bad_kind = np.array([6, 0, 0], np.int8)
     assert ev(L.LipMetric(3, 2, None, pp(bad_kind), pp(a), pp(good_b))) == L.LIP_E_VALUE
     # the other entry points do not take the regional kinds
-    assert lib.lip_consistency(ctypes.byref(m_ok), FAKE, FAKE, 10, 1.0, None, 0.0, FAKE, None,
+    assert lib.lip_consistency(ctypes.byref(m_ok), FAKE, FAKE, 10, 1.0, None, 0.0, FAKE, None, None, None,
                                None, None, None, FAKE, 1 << 30, 0, None) == L.LIP_E_UNSUPPORTED

@@ -34,6 +34,12 @@ def _consistency(lf, p, M, Mk, tol=0.0):
     return {k: v.cpu().numpy() for k, v in r.items()}
 
 
+def _check_worst(g, o):
+    """The smallest slack and its pair (lowest i, then k, on ties)."""
+    assert g["worst_slack"][0] == o["worst_slack"], (g["worst_slack"], o["worst_slack"])
+    assert tuple(g["worst_pair"].tolist()) == o["worst_pair"]
+
+
 CASES = [
     (1, [0, 0, 0], False, False),
     (2, [1, 0, -1], True, True),
@@ -55,6 +61,7 @@ def test_consistency_exact(lf, norm, mon, local, weighted):
         np.testing.assert_array_equal(g["partner_up"], o["partner_up"])
         np.testing.assert_array_equal(g["partner_lo"], o["partner_lo"])
         assert g["counts"][0] == o["viol_up"].sum() and g["counts"][1] == o["viol_lo"].sum()
+        _check_worst(g, o)
 
 
 def test_consistency_boundary_ties_and_tolerance(lf):
@@ -223,6 +230,7 @@ def test_consistency_every_pattern_low_dim(lf, d):
         for key in ("slack_up", "slack_lo", "partner_up", "partner_lo"):
             np.testing.assert_array_equal(g[key], o[key], err_msg=f"d={d} mon={mon.tolist()} {key}")
         assert g["counts"].tolist() == [o["viol_up"].sum(), o["viol_lo"].sum()], mon.tolist()
+        _check_worst(g, o)
 
 
 def test_consistency_l2_filter_off_for_huge_values(lf):
@@ -284,3 +292,92 @@ def test_consistency_exact_higher_dims(lf, d, norm):
         for key in ("slack_up", "slack_lo", "partner_up", "partner_lo"):
             np.testing.assert_array_equal(g[key], o[key], err_msg=f"d={d} n={n} {key}")
         assert g["counts"].tolist() == [o["viol_up"].sum(), o["viol_lo"].sum()]
+        _check_worst(g, o)
+
+
+def test_consistency_worst_pair_ties_and_tiny_sets(lf):
+    """Equal slacks on several rows (dyadic 1-D data, slope exactly above M
+    everywhere): the worst pair is the lowest (i, k); n = 1 has none."""
+    x = (np.arange(40, dtype=np.float32) / 4.0)[:, None]
+    y = (np.arange(40, dtype=np.float32) * 0.75).astype(np.float32)  # slope 3
+    p = W.Problem("ties", x, y, 2.0, None, x, 1, np.zeros(1, np.int8), np.ones(1, np.float32))
+    for norm in (1, 2, 3):
+        p.norm = norm
+        g = _consistency(lf, p, 2.0, None)
+        o = oracle.consistency(x, y, norm, M=2.0)
+        _check_worst(g, o)
+    one = W.random_problem(5, n=1, q=1, d=2, norm=2)
+    g = _consistency(lf, one, 1.0, None)
+    assert np.isinf(g["worst_slack"][0]) and g["worst_pair"].tolist() == [-1, -1]
+    # the binding without per-row outputs still reports the worst pair
+    p3 = W.random_problem(6, n=2500, q=1, d=4, norm=3, mon=np.array([1, 0, 0, -1], np.int8),
+                          local=True)
+    met = lf.Metric(4, 3, mon=p3.mon)
+    r = lf.consistency(_t(p3.x), _t(p3.y), met, Mk=_t(p3.Mk), per_row=False)
+    o = oracle.consistency(p3.x, p3.y, 3, Mk=p3.Mk, mon=p3.mon)
+    _check_worst({k: v.cpu().numpy() for k, v in r.items()}, o)
+
+
+@pytest.mark.slow
+def test_consistency_mixed_l2_200k(lf):
+    """The FP64 consistency check of the mixed-precision workload's first
+    200,000 points (d = 16, l2, M = 1): 256 seeded rows and every row the GPU
+    flags, bit-exact; the worst pair's row reproduced by the oracle.  Again
+    with M = 0.02, where most rows violate: 512 of the flagged rows."""
+    full = W.mixed_l2(q=1)
+    n = 200_000
+    p = W.Problem("mixed_l2 200k", full.x[:n].copy(), full.y[:n].copy(), 1.0, None, full.xq, 2,
+                  full.mon, full.w)
+    rng = np.random.default_rng(200)
+    for M in (1.0, float(np.float32(0.02))):  # the FP32 constant both sides read
+        g = _consistency(lf, p, M, None)
+        flagged = np.nonzero((g["slack_up"] < 0) | (g["slack_lo"] < 0))[0]
+        if flagged.size > 512:
+            flagged = np.sort(rng.choice(flagged, 512, replace=False))
+        rows = np.unique(np.concatenate([rng.choice(n, 256, replace=False), flagged,
+                                         [int(g["worst_pair"][0])]]))
+        o = oracle.consistency(p.x, p.y, 2, M=M, rows=rows)
+        for key in ("slack_up", "slack_lo", "partner_up", "partner_lo"):
+            np.testing.assert_array_equal(g[key][rows], o[key], err_msg=f"M={M} {key}")
+        # the per-row violation counts of the sampled rows add up below the totals
+        assert o["viol_up"].sum() <= g["counts"][0] and o["viol_lo"].sum() <= g["counts"][1]
+        w = g["worst_slack"][0]
+        assert w == min(g["slack_up"].min(), g["slack_lo"].min())
+        i, k = (int(v) for v in g["worst_pair"])
+        r = int(np.nonzero(rows == i)[0][0])
+        assert (o["slack_up"][r] == w and o["partner_up"][r] == k) or \
+            (o["slack_lo"][r] == w and o["partner_lo"][r] == k)
+        if M == 1.0:
+            print(f"M=1: violations {g['counts'].tolist()}, worst slack {w:.6g} at {(i, k)}")
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("norm", [1, 2, 3])
+def test_estimate_global_monotone_local_full(lf, norm):
+    """The global constant of the d = 4, N = 100,000 data over all 5e9
+    pairs, against the oracle's full brute force: M64 and the pair exact."""
+    p = W.monotone_local(q=1, norm=norm)
+    met = lf.Metric(4, norm)
+    G64, G32, pair = lf.estimate_M(_t(p.x), _t(p.y), met, mode="global")
+    st, Mo, po = oracle.estimate_M_global(p.x, p.y, norm)
+    assert st == 0
+    assert G64.item() == Mo and tuple(pair.cpu().tolist()) == po, (G64.item(), Mo, pair, po)
+
+
+def test_estimate_infinite_slope_status(lf):
+    """Coincident data with different values: +inf through the outputs, and
+    LIP_E_VALUE when the synchronous checks are asked for."""
+    from paper_2606_04670_amd import LipError
+    x = np.array([[0, 0], [1, 0], [0, 0], [3, 3]], np.float32)
+    y = np.array([0, 1, 0.5, 2], np.float32)
+    met = lf.Metric(2, "l2")
+    for mode in ("global", "knn"):
+        M64, _, _ = lf.estimate_M(_t(x), _t(y), met, mode=mode, knn=2)
+        torch.cuda.synchronize()
+        assert np.isinf(M64.cpu().numpy()).any()
+        with pytest.raises(LipError) as e:
+            lf.estimate_M(_t(x), _t(y), met, mode=mode, knn=2, check_finite=True)
+        assert e.value.status == 3  # LIP_E_VALUE
+    y2 = np.array([0, 1, 0, 2], np.float32)
+    M64, _, _ = lf.estimate_M(_t(x), _t(y2), met, check_finite=True)
+    assert np.isfinite(M64.item())
