@@ -27,42 +27,31 @@ sys.path.insert(0, ROOT)
 
 METRIC = ("query×data pair-evals/s (d=4, N=1e5, Q=1e6) fwd and fwd+bwd; % VALU peak")
 
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz = VALU issue slots per
-# second (one slot = one lane-operation at the base issue rate).
-VALU_PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
-FP32_DATASHEET_TFLOPS = 157.3
+# Published MI355X peaks: FP32 vector 157.3 TFLOP/s, FP64 vector 78.6 TFLOP/s,
+# dense BF16 MFMA 2.5 PFLOP/s.
+FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6
+BF16_PEAK_TFLOPS = 2500.0
 
-# Issue cost of one instruction in slots, from the measured single-kind
-# rates on this chip (profiles/valu_issue_rates_gfx950.txt): v_add/v_sub_f32
-# issue at twice the base rate (~65 T lane-ops/s), v_sqrt_f32 at half
-# (~19 T), FMA / mul / max / min / med3 / min3 / max3 at the base rate.
-SLOT = {"add": 0.5, "fma": 1.0, "max": 1.0, "med3": 1.0, "minmax3": 1.0, "sqrt": 2.0}
+# Algorithmic FLOP per (query, datum) pair at d = 4 with two monotone
+# coordinates (the convention of the design notes, section 6): a free
+# coordinate costs 2 (l1 / linf: difference, absolute-value accumulate) or 3
+# (l2: difference, FMA), a monotone one 3 (l1 / linf) or 5 (l2), l2 adds one
+# square root per distance (two with monotone coordinates), every pair adds the
+# two bounds (2 FMA = 4) and min + max (2).
+FLOP_PER_PAIR = {"l1": 2 * 2 + 2 * 3 + 6, "linf": 2 * 2 + 2 * 3 + 6,
+                 "l2": 2 * 3 + 2 * 5 + 2 + 6}
+# The consistency pass: the same pair work plus a compare and a count (2),
+# l1 / linf in FP64, l2 FP32-filtered (FP64 for the undecided pairs).
+CONS_FLOP_PER_PAIR = {nm: f + 2 for nm, f in FLOP_PER_PAIR.items()}
+# l2 at d = 16 without monotone coordinates: 16 x 3 + 1 root + 4 + 2
+FLOP_PER_PAIR_L2_D16 = 16 * 3 + 1 + 6
+CONS_PEAK_TFLOPS = {"l1": FP64_PEAK_TFLOPS, "linf": FP64_PEAK_TFLOPS, "l2": FP32_PEAK_TFLOPS}
 
-# Minimal instruction mix per (query, datum) pair of the fused bound kernel,
-# d = 4 with 2 monotone coordinates (derivation in the design notes):
-MIX = {
-    # 2 sub + 1 add(|a|,|b|) + 2 add + 1 sub; 2 med3; 2 FMA; min3/max3 per 2 pairs x 2 bounds
-    "l1": {"add": 6, "med3": 2, "fma": 2, "minmax3": 1},
-    # 4 sub; max + 2 max3; 2 FMA; min3/max3
-    "linf": {"add": 4, "max": 3, "fma": 2, "minmax3": 1},
-    # 4 sub; mul + FMA (free); 2 max + 2 min + 4 FMA (monotone); 2 sqrt; 2 FMA; min3/max3
-    "l2": {"add": 4, "fma": 8, "max": 4, "sqrt": 2, "minmax3": 1},
-}
-SLOTS_PER_PAIR = {nm: sum(SLOT[c] * k for c, k in mix.items()) for nm, mix in MIX.items()}
-INSTR_PER_PAIR = {nm: sum(mix.values()) for nm, mix in MIX.items()}
-# Conventional FLOP per pair (each add/sub/min/max/abs-accumulate 1, FMA 2,
-# sqrt 1) used for the datasheet comparison.
-FLOP_PER_PAIR = {"l1": 16, "l2": 24, "linf": 16}
-# Minimal instructions per ordered data pair of the consistency kernels at
-# d = 4 with the monotone pattern known at compile time.  l1 / linf (FP64
-# kernel, one slot each): 4 differences, 4 positive parts (the monotone
-# coordinates), 3 + 3 accumulations, 2 x 3 for the bounds (mul, add, sub in
-# the definition's order), 2 minima, 2 violation compares = 24.  l2 (FP32
-# filter kernel, slots): 4 differences (2), 4 positive parts (4), 2 x (mul
-# + 3 FMA) squares (8), 2 v_sqrt_f32 (4), 2 x (FMA + sub) bounds (3), 6
-# compares (certain violation, tolerance band, running-minimum candidate for
-# each bound) = 27; the rare FP64 re-evaluations come on top.
-CONS_SLOTS_PER_PAIR = {"l1": 24, "linf": 24, "l2": 27}
+# Hardware-counter figures of the kernels (VALU issue busy), from the
+# rocprofv3 --pmc summary in profiles/; reported only while the kernel sources
+# hash to the profiled ones.
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "valu_busy_monotone_local.txt")
 
 
 # HBM traffic of the forward kernel, from rocprofv3 FETCH_SIZE / WRITE_SIZE
@@ -83,19 +72,30 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(norm):
-    """Bytes per launch of the forward kernel for `norm`, or None."""
+def _profile_record(path, tag):
+    """The JSON record after `tag` in a profile summary, or None when the
+    file is missing or was made from other kernel sources."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             for line in fh:
-                if line.startswith("TRAFFIC_JSON "):
-                    rec = json.loads(line[len("TRAFFIC_JSON "):])
-                    if rec.get("source_sha256") != kernel_source_hash():
-                        return None
-                    return rec["bytes_per_launch"].get(norm)
+                if line.startswith(tag + " "):
+                    rec = json.loads(line[len(tag) + 1:])
+                    return rec if rec.get("source_sha256") == kernel_source_hash() else None
     except OSError:
         return None
     return None
+
+
+def measured_traffic(norm):
+    """Bytes per launch of the forward kernel for `norm`, or None."""
+    rec = _profile_record(TRAFFIC_FILE, "TRAFFIC_JSON")
+    return None if rec is None else rec["bytes_per_launch"].get(norm)
+
+
+def measured_valu_busy():
+    """VALU issue busy fraction per kernel name from the counters, or None."""
+    rec = _profile_record(COUNTERS_FILE, "COUNTERS_JSON")
+    return None if rec is None else rec.get("valu_busy")
 
 
 def parse():
@@ -110,6 +110,9 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the BF16-vs-FP32, batched-vs-per-set, step-function, "
                          "smoothing, k-best, regional-monotonicity and other-workload runs")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="only copy a 1 GiB buffer 4 times (torch's copy kernel): the "
+                         "reference for scaling FETCH_SIZE / WRITE_SIZE counters")
     return ap.parse_args()
 
 
@@ -148,27 +151,42 @@ def extra_bf16(lf, W, torch, dev, reps=3):
                for k in outs[True])
     pairs = float(p.n) * float(p.q)
     ks = 1 if p.d + 6 <= 16 else 2
-    mfma_flop_per_pair = 2 * 16 * ks  # one 32x32x16 BF16 MFMA per 1024 pairs per K-step
+    issued_flop_per_pair = 2 * 16 * ks  # 32x32x16 MFMA K-steps as issued (K padded)
+    algo_flop_per_pair = 2 * p.d        # the cross term x . x^k
     rate16 = pairs / (t16 * 1e-3)
     return {"workload": f"mixed_l2 d={p.d} N={p.n} Q={p.q} M={p.M} l2",
             "fp32_ms": t32, "bf16_ms": t16, "speedup": t32 / t16,
             "fp32_pair_evals_per_s": pairs / (t32 * 1e-3), "bf16_pair_evals_per_s": rate16,
+            "fp32_peak_frac": FLOP_PER_PAIR_L2_D16 * pairs / (t32 * 1e-3) / 1e12
+            / FP32_PEAK_TFLOPS,
             "identical_to_fp32": bool(same),
-            "bf16_mfma_issued_tflops": mfma_flop_per_pair * rate16 / 1e12,
-            "bf16_mfma_frac_of_2500_tflops": mfma_flop_per_pair * rate16 / 2.5e15,
-            "note": "bf16_ms includes the y sort and staging of the data (per call)"}
+            "bf16_cross_term_tflops": algo_flop_per_pair * rate16 / 1e12,
+            "bf16_cross_term_frac_of_2500_tflops": algo_flop_per_pair * rate16 / 1e12
+            / BF16_PEAK_TFLOPS,
+            "bf16_mfma_issued_tflops": issued_flop_per_pair * rate16 / 1e12,
+            "note": "bf16_ms includes the y sort and staging of the data (per call); the "
+                    "cross-term figure counts 2 d FLOP per pair, the issued one the padded "
+                    "K of the MFMA"}
 
 
 def extra_batched(lf, W, torch, dev, reps=3):
     """512 independent l2 sets (N log-uniform in [500, 50000], d in 2..10,
-    Q = 4N): one graph launch of a plan against per-set lip_fit_eval calls."""
+    Q = 4N): one graph launch of a plan with the default tiles, per-set
+    lip_fit_eval calls, and a plan built after lip_autotune has tuned every
+    (shape class, size class) the sets fall in (timed on synthetic data at
+    the geometric-mean size of the class's sets)."""
+    import math
+
+    import numpy as np
     probs = W.batched()
     sets = []
     for pb in probs:
         sets.append(dict(x=torch.from_numpy(pb.x).to(dev), y=torch.from_numpy(pb.y).to(dev),
                          xq=torch.from_numpy(pb.xq).to(dev),
                          metric=lf.Metric(pb.d, pb.norm, mon=pb.mon, w=pb.w), M=pb.M))
+    lf.tune_clear()
     plan = lf.Plan(sets)
+    outs = [{k: v.clone() for k, v in o.items()} for o in plan.execute()]
 
     def per_set():
         for s_ in sets:
@@ -177,10 +195,35 @@ def extra_batched(lf, W, torch, dev, reps=3):
     t_plan = _time_ms(torch, plan.execute, reps)
     t_sets = _time_ms(torch, per_set, reps)
     plan.close()
+    # tune every class the sets fall in
+    cls = {}
+    for pb in probs:
+        key = (pb.d, int(np.count_nonzero(pb.mon)), pb.norm,
+               int(math.log2(pb.n)) // 2, int(math.log2(pb.q)) // 2)
+        cls.setdefault(key, []).append(pb)
+    t0 = time.perf_counter()
+    tuned = {}
+    for (d, m, nrm, _, _), group in sorted(cls.items()):
+        n = int(round(math.exp(np.mean([math.log(g.n) for g in group]))))
+        q = int(round(math.exp(np.mean([math.log(g.q) for g in group]))))
+        cfg = lf.autotune(d, m, nrm, n, q)
+        tuned[f"d={d} mon={m} n~{n} q~{q}"] = cfg["tile"]
+    t_tune = time.perf_counter() - t0
+    plan_t = lf.Plan(sets)
+    got = plan_t.execute()
+    torch.cuda.synchronize()
+    same = all(torch.equal(a[k], b[k]) for a, b in zip(outs, got) for k in a)
+    t_tuned = _time_ms(torch, plan_t.execute, reps)
+    tiles = sorted({plan_t.tiles(i)["tile"] for i in range(len(sets))})
+    plan_t.close()
+    lf.tune_clear()
     pairs = float(sum(pb.n * pb.q for pb in probs))
     return {"workload": f"batched {len(probs)} sets, l2, sum N*Q = {pairs:.3e}",
             "plan_ms": t_plan, "per_set_ms": t_sets, "speedup": t_sets / t_plan,
-            "plan_pair_evals_per_s": pairs / (t_plan * 1e-3)}
+            "plan_pair_evals_per_s": pairs / (t_plan * 1e-3),
+            "tuned_plan_ms": t_tuned, "tuned_vs_default": t_plan / t_tuned,
+            "tuned_identical_to_default": bool(same), "classes_tuned": len(cls),
+            "autotune_s": t_tune, "tuned_tiles_used": tiles}
 
 
 def extra_steps(lf, W, torch, dev, base, x, y, xq, norms, scalar_fwd_ms, reps=3):
@@ -325,6 +368,17 @@ def main():
     import workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if a.copy_calib:
+        # the reference of the HBM counters: 4 plain copies of 1 GiB
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calib": {"bytes_read_per_copy": src.numel() * 4,
+                                         "bytes_written_per_copy": dst.numel() * 4,
+                                         "copies": 4}}))
+        return
     lf.load()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -381,28 +435,34 @@ def main():
     for nm in norms:
         f = stage_ms[nm]["forward"]
         b = stage_ms[nm]["backward"]
+        c = stage_ms[nm]["consistency"]
         rate = pairs / (f * 1e-3)
         per_norm[nm] = {
             "fwd_pair_evals_per_s": rate,
             "fwd_bwd_pair_evals_per_s": pairs / ((f + b) * 1e-3),
             "fwd_ms": f, "bwd_ms": b,
-            "knn16_ms": stage_ms[nm]["knn"], "consistency_fp64_ms": stage_ms[nm]["consistency"],
-            # fraction of the VALU issue peak spent on the minimal instruction mix
-            "valu_frac": SLOTS_PER_PAIR[nm] * rate / VALU_PEAK_SLOTS,
-            "datasheet_fp32_frac": FLOP_PER_PAIR[nm] * rate / 1e12 / FP32_DATASHEET_TFLOPS,
-            "consistency_valu_frac": CONS_SLOTS_PER_PAIR[nm] * float(N) * float(N)
-            / (stage_ms[nm]["consistency"] * 1e-3) / VALU_PEAK_SLOTS,
+            "knn16_ms": stage_ms[nm]["knn"], "consistency_ms": c,
+            # algorithmic FLOP (design notes, section 6) over the published peaks
+            "fwd_fp32_peak_frac": FLOP_PER_PAIR[nm] * rate / 1e12 / FP32_PEAK_TFLOPS,
+            "consistency_peak_frac": CONS_FLOP_PER_PAIR[nm] * float(N) * float(N)
+            / (c * 1e-3) / 1e12 / CONS_PEAK_TFLOPS[nm],
+            "consistency_peak": "fp64" if CONS_PEAK_TFLOPS[nm] == FP64_PEAK_TFLOPS else "fp32",
         }
-    # dominant kernel: the forward bound kernel of the slowest norm
+    # dominant kernel: the forward bound kernel of the slowest norm, timed by
+    # HIP events on its launch stream around each call (origin and staging
+    # kernels, a few microseconds, included)
     dom = max(norms, key=lambda nm: stage_ms[nm]["forward"])
     f_ms = stage_ms[dom]["forward"]
-    achieved = SLOTS_PER_PAIR[dom] * pairs / (f_ms * 1e-3) / 1e12
-    peak = VALU_PEAK_SLOTS / 1e12
-    roofline = {"bound": "alu", "kernel": f"bounds_fwd_kernel<4,2,{nid[dom]}> ({dom})",
-                "achieved": round(achieved, 3), "peak": round(peak, 3),
-                "unit": "T VALU-slot/s", "frac": round(achieved / peak, 4),
+    achieved = FLOP_PER_PAIR[dom] * pairs / (f_ms * 1e-3) / 1e12
+    kname = (f"bounds_fwd_kernel{'_o4' if dom != 'l1' else ''}<4, 2, {nid[dom]}>")
+    busy = measured_valu_busy()
+    roofline = {"bound": "alu", "kernel": f"{kname} ({dom} forward)",
+                "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
                 "traffic": measured_traffic(dom),
-                "slots_per_pair": SLOTS_PER_PAIR[dom], "instructions_per_pair": INSTR_PER_PAIR[dom]}
+                "flop_per_pair": FLOP_PER_PAIR[dom], "pairs_per_launch": pairs,
+                "launch_ms": round(f_ms, 3),
+                "valu_issue_busy_counters": None if busy is None else busy.get(dom)}
 
     cpu = None
     if not a.no_cpu_baseline:

@@ -70,17 +70,23 @@ class Metric:
         return ctypes.byref(self._c)
 
 
-# ---- workspace cache: one growing byte buffer per device (caching allocator) --
+# ---- workspace cache: one growing byte buffer per (device, stream) ----------
+#
+# Calls are asynchronous on the current stream, so two streams must not share
+# scratch: each (device, stream) pair keeps its own buffer, allocated through
+# the caching allocator while that stream is current (a replaced buffer is
+# returned to the allocator in that stream's order).
 
-_WS: Dict[int, torch.Tensor] = {}
+_WS: Dict[tuple, torch.Tensor] = {}
 
 
 def workspace(device: torch.device, nbytes: int) -> torch.Tensor:
     idx = device.index if device.index is not None else torch.cuda.current_device()
-    t = _WS.get(idx)
+    key = (idx, torch.cuda.current_stream(device).cuda_stream)
+    t = _WS.get(key)
     if t is None or t.numel() < nbytes:
         t = torch.empty(int(nbytes), dtype=torch.uint8, device=device)
-        _WS[idx] = t
+        _WS[key] = t
     return t
 
 
@@ -384,9 +390,11 @@ def smooth_lipschitz(x, y, metric: Metric, M=None, Mk=None, p: float = 1.0, prun
                             line_search_fn="strong_wolfe")
 
     def closure():
+        # the objective stays FP64 (the fixed-order sums of the kernel): the
+        # optimiser compares its values in the line search
         F, g = smooth_objective(x, y, eps.detach(), metric, M=M, Mk=Mk, p=p, prune=prune)
         eps.grad = g
-        return F.to(torch.float32).reshape(())
+        return F.reshape(())
 
     opt.step(closure)
     F, _ = smooth_objective(x, y, eps.detach(), metric, M=M, Mk=Mk, p=p, prune=prune,

@@ -159,3 +159,29 @@ def test_mixed_l2_workload_full_size_sampled(lf):
     out = run(lf, p)
     qidx = np.sort(np.random.default_rng(5).choice(p.q, 64, replace=False))
     print(check_bounds(p, out, qidx=qidx, label="mixed_l2"))
+
+
+def test_two_streams_keep_separate_scratch(lf):
+    """Calls on two streams at once (each with its own workspace) give the
+    same results as one after the other."""
+    pa = W.random_problem(41, n=20000, q=30000, d=4, norm=1, mon=np.array([1, 0, 1, 0], np.int8),
+                          local=True)
+    pb = W.random_problem(42, n=15000, q=25000, d=3, norm=2, weighted=True)
+    ref = [run(lf, pa), run(lf, pb)]
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+    args = []
+    for p in (pa, pb):
+        args.append((t(p.x), t(p.y), t(p.xq), lf.Metric(p.d, p.norm, mon=p.mon, w=p.w),
+                     None if p.Mk is None else t(p.Mk), p.M))
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(DEV), torch.cuda.Stream(DEV)]
+    outs = [None, None]
+    for rep in range(3):
+        for i, (s, (x, y, xq, met, mk, M)) in enumerate(zip(streams, args)):
+            with torch.cuda.stream(s):
+                outs[i] = lf.fit_eval(x, y, xq, met, M=None if mk is not None else M, Mk=mk)
+        torch.cuda.synchronize()
+        for i in range(2):
+            for k in ref[i]:
+                np.testing.assert_array_equal(outs[i][k].cpu().numpy(), ref[i][k],
+                                              err_msg=f"stream {i} {k} rep {rep}")
