@@ -396,7 +396,10 @@ int64_t ds_npad(int64_t n) { return (n + kDsTile - 1) / kDsTile * kDsTile; }
 size_t data_side_ws_bytes(int64_t n, int d)
 {
     const size_t staged = align_up((size_t)ds_npad(n) * (size_t)(d + 2) * 8, 256);
-    const size_t cons = align_up((size_t)kDsMaxChunks * (size_t)n * 24, 256) +
+    int cc = cons_chunks(n, d, LIP_L1);
+    if (cons_chunks(n, d, LIP_L2) > cc) cc = cons_chunks(n, d, LIP_L2);
+    if (cc < kDsMaxChunks) cc = kDsMaxChunks;  // the slope pass uses up to kDsMaxChunks here
+    const size_t cons = align_up((size_t)cc * (size_t)n * 24, 256) +
                         align_up((size_t)ds_npad(n) * (size_t)(d + 2) * 4, 256) + 256 +
                         align_up((size_t)n * 24, 256);
     const size_t knn = align_up((size_t)n * 4, 256) + align_up((size_t)n * kKnnCap * 4, 256) +
@@ -432,16 +435,24 @@ bool fill_ds_metric(const MetricInfo &mi, bool use_mon, DsArgs *A, Signs *sg)
 
 // Column split: enough waves to fill the chip, chunks a multiple of the
 // partner tile, at most max_chunks of them.
-void choose_chunks(int64_t n, int rows_per_wave, int max_chunks, DsArgs *A)
+void choose_chunks(int64_t n, int rows_per_wave, int max_chunks, DsArgs *A, int64_t target_waves)
 {
     const int64_t row_waves = (n + rows_per_wave - 1) / rows_per_wave;
-    int64_t nc = (kDsTargetWaves + row_waves - 1) / row_waves;
+    int64_t nc = (target_waves + row_waves - 1) / row_waves;
     if (nc > max_chunks) nc = max_chunks;
     if (nc < 1) nc = 1;
     int64_t cols = (n + nc - 1) / nc;
     cols = (cols + kDsTile - 1) / kDsTile * kDsTile;
     A->chunk_cols = cols;
     A->n_chunks = (int)((n + cols - 1) / cols);
+}
+
+int cons_chunks(int64_t n, int d, int norm)
+{
+    DsArgs A{};
+    const int rows = 64 * (norm == LIP_L2 ? c32_rows(d) : ds_cons_rows(d));
+    choose_chunks(n, rows, kConsMaxChunks, &A, kConsTargetWaves);
+    return A.n_chunks;
 }
 
 unsigned grid_for_rows(int64_t n, int rows_per_wave, int n_chunks)
@@ -489,14 +500,14 @@ extern "C" lip_status lip_consistency(const lip_metric *metric, const float *x, 
     // l2 runs the FP32-filtered kernel (c32_rows(d) rows per lane), l1 / linf
     // the FP64 kernel (ds_cons_rows(d))
     const int rows = 64 * (mi.norm == LIP_L2 ? c32_rows(mi.d) : ds_cons_rows(mi.d));
-    choose_chunks(n, rows, kDsMaxChunks, &A);
+    choose_chunks(n, rows, kConsMaxChunks, &A, kConsTargetWaves);
     char *p = (char *)ws + align_up((size_t)A.npad * (size_t)(mi.d + 2) * 8, 256);
     const size_t e = (size_t)A.n_chunks * (size_t)n;
     A.pv_up = (double *)p;
     A.pv_lo = A.pv_up + e;
     A.pi_up = (int32_t *)(A.pv_lo + e);
     A.pi_lo = A.pi_up + e;
-    char *q = p + align_up((size_t)kDsMaxChunks * (size_t)n * 24, 256);
+    char *q = p + align_up(e * 24, 256);
     float *c32 = (float *)q;
     q += align_up((size_t)A.npad * (size_t)(mi.d + 2) * 4, 256);
     double *cE = (double *)q;

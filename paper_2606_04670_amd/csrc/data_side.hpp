@@ -263,13 +263,18 @@ __device__ __forceinline__ bool wave_range(const DsArgs &A, int rows_per_wave, W
 
 // ---- consistency -------------------------------------------------------------
 
-template <int D, int NORM, bool HASW, bool MON, bool MASK, int FM, int R>
+// One group of kDsGroup columns for the R rows of each lane.  MASK: the group
+// holds columns past n or the rows' own columns (such pairs are skipped);
+// FULLW: every row of the wave exists, so the violation ballots need no row
+// mask.  Violations are counted in 32 bits per tile (at most 64 R x 64 per
+// tile) by the caller.
+template <int D, int NORM, bool HASW, bool MON, bool MASK, int FM, int R, bool FULLW = false>
 __device__ __forceinline__ void cons_group(const DsArgs &A, cdouble_ptr X, int64_t g0,
                                            const double (&xr)[R][D],
                                            const double (&yr)[R], const int (&ir)[R],
                                            const unsigned long long (&vmask)[R],
-                                           double (&bu)[R], double (&bl)[R],
-                                           unsigned long long &cu, unsigned long long &cl)
+                                           double (&bu)[R], double (&bl)[R], unsigned &cu,
+                                           unsigned &cl)
 {
     double su[kDsGroup][R], sl[kDsGroup][R];
     ds_dist_group<D, NORM, HASW, MON, R, FM>(A, X, g0, xr, su, sl);
@@ -300,8 +305,13 @@ __device__ __forceinline__ void cons_group(const DsArgs &A, cdouble_ptr X, int64
             bl[r] = fmin(bl[r], tl);
             // lanes past the last row are removed with the wave-uniform mask
             // (scalar work) instead of a per-pair vector condition
-            cu += __popcll(__ballot(tu < -A.tol) & vmask[r]);
-            cl += __popcll(__ballot(tl < -A.tol) & vmask[r]);
+            if constexpr (FULLW) {
+                cu += __popcll(__ballot(tu < -A.tol));
+                cl += __popcll(__ballot(tl < -A.tol));
+            } else {
+                cu += __popcll(__ballot(tu < -A.tol) & vmask[r]);
+                cl += __popcll(__ballot(tl < -A.tol) & vmask[r]);
+            }
         }
 }
 
@@ -344,6 +354,7 @@ __global__ void __launch_bounds__(256) consistency_kernel(DsArgs A)
     }
     const cdouble_ptr X = (cdouble_ptr)(A.X);
     unsigned long long cu = 0, cl = 0;
+    const bool fullw = w.r0 + RW <= A.n;
     int t = 0;
     for (int64_t tb = w.c0; tb < w.c1; tb += kDsTile, ++t) {
         const int64_t te = tb + kDsTile < w.c1 ? tb + kDsTile : w.c1;
@@ -353,14 +364,22 @@ __global__ void __launch_bounds__(256) consistency_kernel(DsArgs A)
             pu[r] = bu[r];
             pl[r] = bl[r];
         }
+        unsigned tcu = 0, tcl = 0;
 #pragma unroll 1
         for (int64_t g0 = tb; g0 < te; g0 += kDsGroup) {
             const bool masked = (g0 + kDsGroup > A.n) || (g0 < w.r1 && g0 + kDsGroup > w.r0);
             if (masked)
-                cons_group<D, NORM, HASW, MON, true, FM, R>(A, X, g0, xr, yr, ir, vmask, bu, bl, cu, cl);
+                cons_group<D, NORM, HASW, MON, true, FM, R>(A, X, g0, xr, yr, ir, vmask, bu, bl,
+                                                            tcu, tcl);
+            else if (fullw)
+                cons_group<D, NORM, HASW, MON, false, FM, R, true>(A, X, g0, xr, yr, ir, vmask,
+                                                                   bu, bl, tcu, tcl);
             else
-                cons_group<D, NORM, HASW, MON, false, FM, R>(A, X, g0, xr, yr, ir, vmask, bu, bl, cu, cl);
+                cons_group<D, NORM, HASW, MON, false, FM, R>(A, X, g0, xr, yr, ir, vmask, bu, bl,
+                                                             tcu, tcl);
         }
+        cu += tcu;
+        cl += tcl;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             tu_t[r] = bu[r] < pu[r] ? t : tu_t[r];
@@ -1143,7 +1162,13 @@ hipError_t launch_stage64(int d, const float *x, const float *y, const float *Mk
                           int64_t n, int64_t npad, const Signs &sg, double *X, hipStream_t s);
 int64_t ds_npad(int64_t n);
 bool fill_ds_metric(const MetricInfo &mi, bool use_mon, DsArgs *A, Signs *sg);
-void choose_chunks(int64_t n, int rows_per_wave, int max_chunks, DsArgs *A);
+void choose_chunks(int64_t n, int rows_per_wave, int max_chunks, DsArgs *A,
+                   int64_t target_waves = kDsTargetWaves);
+// Column chunks of the consistency passes: finer than the other passes' so
+// that the grid holds ~6 waves per SIMD slot and the last round is short.
+constexpr int kConsMaxChunks = 32;
+constexpr int64_t kConsTargetWaves = 24576;
+int cons_chunks(int64_t n, int d, int norm);
 unsigned grid_for_rows(int64_t n, int rows_per_wave, int n_chunks);
 
 bool ds_table_l1(int d, bool hasw, DsLaunchers *L);
