@@ -377,8 +377,8 @@ lip_status lip_plan_execute(lip_plan *plan, lip_stream stream);
 lip_status lip_plan_destroy(lip_plan *plan);
 
 /* ---- tile parameters --------------------------------------------------------
- * Runtime tiling choices of the bound kernels (lip_bounds, lip_fit_eval and
- * the sets of a plan) for a shape class (d, number of monotone coordinates,
+ * Runtime choices of the bound kernels (lip_bounds, lip_fit_eval and the
+ * sets of a plan) for a shape class (d, number of monotone coordinates,
  * norm) and a size class of (n, q): sizes within a factor of 4 of each other
  * (floor(log2 v) / 2 equal for n and for q) share an entry.  Results do not
  * depend on these choices, only the time does. */
@@ -386,8 +386,15 @@ typedef struct {
     int32_t tile;         /* data points per argmin tile (multiple of 8, 8..256) */
     int32_t split;        /* number of data chunks (1..64; 1 = no split) */
     int32_t waves;        /* waves per workgroup (1..4) */
-    int32_t reserved;
+    int32_t flags;        /* LIP_TILE_* bits */
 } lip_tile_cfg;
+
+/* l2 with monotone coordinates: give every pair root-free bounds of its
+ * candidates first (from the largest weighted component of each distance)
+ * and form the exact candidates (two square roots) only for the rows of 64
+ * queries where some query could improve.  Identical results; faster when
+ * few data compete for each query (default on for d <= 4). */
+#define LIP_TILE_L2_FILTER 1
 
 /* The configuration the next call of these sizes will use: the table's
  * entry for the size class of (n, q), else the entry set for every size,
@@ -400,7 +407,8 @@ lip_status lip_tune_get(int32_t d, int32_t n_mon, int32_t norm, int64_t n, int64
  * entry.  Invalid values: LIP_E_VALUE. */
 lip_status lip_tune_set(int32_t d, int32_t n_mon, int32_t norm, int64_t n, int64_t q,
                         const lip_tile_cfg *cfg);
-/* Times every candidate (tile 16/32/64/128 x split 1..32 x 2 or 4 waves) for
+/* Times every candidate (tile 16/32/64/128 x split 1..32 x 2 or 4 waves, and
+ * for l2 with monotone coordinates with and without LIP_TILE_L2_FILTER) for
  * this shape class on synthetic data of the given sizes (allocates and frees
  * its own device memory, blocks), stores the fastest under the size class of
  * (n, q) and returns it; with LIPFIT_TUNE_CACHE set, the whole table is then
@@ -409,7 +417,7 @@ lip_status lip_autotune(int32_t d, int32_t n_mon, int32_t norm, int64_t n, int64
                         lip_stream stream, lip_tile_cfg *best);
 /* The table as a JSON file: {"format": "lipfit-tune-1", "entries": [{"arch":
  * "gfx950", "d", "n_mon", "norm", "n_class", "q_class", "tile", "split",
- * "waves"}, ...]} (class -1: every size).  Save writes every entry under the
+ * "waves", "flags"}, ...]} (class -1: every size; "flags" may be absent: 0).  Save writes every entry under the
  * architecture name `arch`; load adds the entries of architecture `arch`
  * (others are skipped) and changes nothing if the file does not parse
  * (LIP_E_VALUE).  arch == NULL means the current device's ("" without a

@@ -23,6 +23,7 @@ LIP_FLAG_DETERMINISTIC = 1 << 2
 LIP_M_GLOBAL, LIP_M_LOCAL_KNN = 0, 1
 LIP_MAX_DIM, LIP_MAX_KNN, LIP_MAX_KNOTS, LIP_MAX_K = 16, 32, 8, 4
 LIP_MON_CASE_I, LIP_MON_CASE_II, LIP_MON_CASE_III, LIP_MON_CASE_IV = 2, 3, 4, 5
+LIP_TILE_L2_FILTER = 1
 
 P = ctypes.c_void_p
 i32, i64, u32, f32, f64, sz = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_float,
@@ -34,7 +35,7 @@ class LipMetric(ctypes.Structure):
 
 
 class LipTileCfg(ctypes.Structure):
-    _fields_ = [("tile", i32), ("split", i32), ("waves", i32), ("reserved", i32)]
+    _fields_ = [("tile", i32), ("split", i32), ("waves", i32), ("flags", i32)]
 
 
 class LipSteps(ctypes.Structure):

@@ -492,7 +492,7 @@ class Plan:
         """Tile parameters set i runs with (argmin tile, data chunks, waves)."""
         cfg = L.LipTileCfg()
         L.check("lip_plan_tiles", L.load().lip_plan_tiles(self._plan, i, ctypes.byref(cfg)))
-        return dict(tile=cfg.tile, split=cfg.split, waves=cfg.waves)
+        return dict(tile=cfg.tile, split=cfg.split, waves=cfg.waves, flags=cfg.flags)
 
     def close(self):
         if self._plan:
@@ -509,16 +509,18 @@ class Plan:
 def tune_get(d, n_mon, norm, n, q):
     cfg = L.LipTileCfg()
     L.check("lip_tune_get", L.load().lip_tune_get(d, n_mon, NORMS[norm], n, q, ctypes.byref(cfg)))
-    return dict(tile=cfg.tile, split=cfg.split, waves=cfg.waves)
+    return dict(tile=cfg.tile, split=cfg.split, waves=cfg.waves, flags=cfg.flags)
 
 
-def tune_set(d, n_mon, norm, tile=None, split=None, waves=None, clear=False, n=0, q=0):
-    """Tile parameters for the size class of (n, q), or every size (n = q = 0)."""
+def tune_set(d, n_mon, norm, tile=None, split=None, waves=None, clear=False, n=0, q=0,
+             flags=0):
+    """Tile parameters for the size class of (n, q), or every size (n = q = 0);
+    flags: LIP_TILE_* bits (1: the root-free l2 filter)."""
     lib = L.load()
     if clear:
         L.check("lip_tune_set", lib.lip_tune_set(d, n_mon, NORMS[norm], n, q, None))
         return
-    cfg = L.LipTileCfg(tile, split, waves, 0)
+    cfg = L.LipTileCfg(tile, split, waves, flags)
     L.check("lip_tune_set", lib.lip_tune_set(d, n_mon, NORMS[norm], n, q, ctypes.byref(cfg)))
 
 
@@ -541,4 +543,4 @@ def autotune(d, n_mon, norm, n, q, device=None):
     cfg = L.LipTileCfg()
     L.check("lip_autotune", L.load().lip_autotune(d, n_mon, NORMS[norm], n, q, _stream(device),
                                                    ctypes.byref(cfg)))
-    return dict(tile=cfg.tile, split=cfg.split, waves=cfg.waves)
+    return dict(tile=cfg.tile, split=cfg.split, waves=cfg.waves, flags=cfg.flags)

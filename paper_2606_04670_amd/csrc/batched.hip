@@ -145,7 +145,7 @@ namespace {
 
 struct SetPlan {
     MetricInfo mi;
-    int R = 0, tile = 32;
+    int R = 0, tile = 32, flags = 0;
     int64_t n_pad = 0, n_tiles = 0, qblocks = 0;
     int tiles_per_chunk = 0, n_chunks = 1;
     size_t staged_off = 0, keys_off = 0, origin_off = 0;
@@ -198,6 +198,7 @@ extern "C" lip_status lip_plan_create(lip_plan **plan, const lip_batch_desc *set
         const lip_tile_cfg cfg = tune_lookup(p.mi.d, p.mi.dm, p.mi.norm, d.n, d.q);
         p.R = rows_for_dim(p.mi.d);
         p.tile = cfg.tile;
+        p.flags = cfg.flags;
         p.n_pad = (d.n + p.tile - 1) / p.tile * p.tile;
         p.n_tiles = p.n_pad / p.tile;
         int64_t chunk_records = kItemPairs / (64 * p.R);
@@ -250,7 +251,7 @@ extern "C" lip_status lip_plan_create(lip_plan **plan, const lip_batch_desc *set
     lip_plan *p = new lip_plan();
     p->tiles.resize(n_sets);
     for (int s = 0; s < n_sets; ++s)
-        p->tiles[s] = lip_tile_cfg{sp[s].tile, sp[s].n_chunks, 4, 0};
+        p->tiles[s] = lip_tile_cfg{sp[s].tile, sp[s].n_chunks, 4, sp[s].flags};
     if (hipGetDevice(&p->device) != hipSuccess || hipMalloc(&p->mem, off) != hipSuccess) {
         free_plan(p);
         return LIP_E_DEVICE;
@@ -270,6 +271,7 @@ extern "C" lip_status lip_plan_create(lip_plan **plan, const lip_batch_desc *set
         a.tile = q.tile;
         a.tiles_per_chunk = q.tiles_per_chunk;
         a.n_chunks = q.n_chunks;
+        a.l2_filter = (q.flags & LIP_TILE_L2_FILTER) ? 1 : 0;
         a.xq = d.xq;
         a.q = d.q;
         a.xf = q.mi.xf;
@@ -472,10 +474,12 @@ extern "C" lip_status lip_autotune(int32_t d, int32_t n_mon, int32_t norm, int64
     const int tiles[] = {16, 32, 64, 128};
     const int splits[] = {1, 2, 4, 8, 16, 32};
     const int waves[] = {2, 4};
+    const int n_flags = (norm == LIP_L2 && n_mon > 0) ? 2 : 1;
+    for (int fl = 0; fl < n_flags; ++fl)
     for (int t : tiles)
         for (int sp : splits)
             for (int w : waves) {
-                lip_tile_cfg c{t, sp, w, 0};
+                lip_tile_cfg c{t, sp, w, fl ? LIP_TILE_L2_FILTER : 0};
                 // warm-up, then the mean of 3 runs
                 st = run_bounds(mi, x, y, n, 1.0f, nullptr, xq, q, g, nullptr, nullptr, nullptr,
                                 nullptr, ws, ws_bytes, c, s);

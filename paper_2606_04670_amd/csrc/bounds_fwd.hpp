@@ -74,6 +74,84 @@ __device__ __forceinline__ void eval_group(const float (&v)[group_for_dim(D) * R
     }
 }
 
+// l2 with monotone coordinates, filtered: the exact candidates need two
+// square roots per pair (v_sqrt_f32 issues at a quarter of the VALU rate and
+// takes about half of the pair's time), but few records can change a row's
+// running bounds.  Each pair first gets root-free bounds of its candidates
+// from the largest weighted component of each distance; a record is
+// evaluated exactly (pair_bounds) for a row of 64 queries only if some lane
+// of the row could improve.  Results are identical to the unfiltered loop:
+//   * with c_max the largest component (of the rounded differences the exact
+//     path squares), the exact path's rounded sum of squares is at least
+//     fl(c_max^2) (every step adds a non-negative term, rounding is
+//     monotone), which is >= c_max^2 (1 - 2^-24) when c_max >= 2^-60 (no
+//     underflow); v_sqrt_f32 errs by far less than 2^-21 relative (taken as
+//     its bound), so the exact root s >= c_max (1 - 2^-20);
+//   * t = fl(c_max (1 - 2^-19) - 2^-60) is below c_max (1 - 2^-20) for
+//     c_max >= 2^-60 and negative below that, so t <= s always; fma is
+//     monotone in its middle argument for M >= 0, hence
+//     fma(M, t, y) <= fma(M, s, y) = u (and fma(-M, t', y) >= l likewise);
+//   * a record is skipped for a row only when every lane's bound is >= its
+//     running minimum and <= its running maximum, so its exact candidates
+//     could not have changed either (ties included: a tie leaves the running
+//     value as it is, and the attaining index comes from the re-scan).
+template <int D, int DM, int R>
+__device__ __forceinline__ void eval_group_l2f(const float (&v)[group_for_dim(D) * Rec<D>::S],
+                                               const float (&q)[R][D], float big,
+                                               float (&hu)[R], float (&hl)[R])
+{
+    constexpr int S = Rec<D>::S;
+    constexpr int kGroup = group_for_dim(D);
+    constexpr int DF = D - DM;
+    const float shrink = 1.0f - 0x1p-19f, tiny = -0x1p-60f;
+#pragma unroll
+    for (int g = 0; g < kGroup; ++g) {
+        float xk[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) xk[j] = v[g * S + j];
+        const float yk = v[g * S + Rec<D>::Y], mk = v[g * S + Rec<D>::M];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            float f = 0.0f;
+#pragma unroll
+            for (int i = 0; i < DF; ++i) f = fmaxf(f, fabsf(q[r][i] - xk[i]));
+            float su = f, sl = f;
+#pragma unroll
+            for (int i = DF; i < D; ++i) {
+                const float dl = q[r][i] - xk[i];
+                su = fmaxf(su, dl);
+                sl = fmaxf(sl, -dl);
+            }
+            const float ulb = fmaf(mk, fmaf(su, shrink, tiny), yk);
+            const float lub = fmaf(-mk, fmaf(sl, shrink, tiny), yk);
+            if (__builtin_amdgcn_ballot_w64((ulb < hu[r]) | (lub > hl[r]))) {
+                float u, l;
+                pair_bounds<D, DM, kNormL2>(q[r], 0.0f, xk, yk, mk, yk, big, u, l);
+                hu[r] = fminf(hu[r], u);
+                hl[r] = fmaxf(hl[r], l);
+            }
+        }
+    }
+}
+
+// One group of records for all R rows of a lane: filtered (l2 with monotone
+// coordinates, when the launch asks for it) or plain.
+template <int D, int DM, int NORM, int R>
+__device__ __forceinline__ void eval_group_rows(const FwdArgs &a,
+                                                const float (&v)[group_for_dim(D) * Rec<D>::S],
+                                                const float (&qv)[R][D], const float (&qm)[R],
+                                                float big, float (&hu)[R], float (&hl)[R])
+{
+    if constexpr (NORM == kNormL2 && DM > 0) {
+        if (a.l2_filter) {
+            eval_group_l2f<D, DM, R>(v, qv, big, hu, hl);
+            return;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) eval_group<D, DM, NORM>(v, qv[r], qm[r], big, hu[r], hl[r]);
+}
+
 // One wave's work: queries [64 R qblock, 64 R (qblock + 1)) against data
 // chunk `chunk`.  Outputs: final values (one chunk), chunk partials, or
 // packed (value, index) keys merged with atomics (a.keys != NULL).
@@ -130,12 +208,10 @@ __device__ __forceinline__ void fwd_wave(const FwdArgs &a, int chunk, int64_t qb
     int64_t t = t0;
     for (int64_t gi = g0; gi < g1; gi += 2) {
         load_group<D>(base + (gi + 1) * GS, gb);
-#pragma unroll
-        for (int r = 0; r < R; ++r) eval_group<D, DM, NORM>(ga, qv[r], qm[r], big, hu[r], hl[r]);
+        eval_group_rows<D, DM, NORM, R>(a, ga, qv, qm, big, hu, hl);
         const int64_t gn = gi + 2 < g1 ? gi + 2 : gi + 1;
         load_group<D>(base + gn * GS, ga);
-#pragma unroll
-        for (int r = 0; r < R; ++r) eval_group<D, DM, NORM>(gb, qv[r], qm[r], big, hu[r], hl[r]);
+        eval_group_rows<D, DM, NORM, R>(a, gb, qv, qm, big, hu, hl);
         if (--left == 0) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {

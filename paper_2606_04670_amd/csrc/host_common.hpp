@@ -65,7 +65,7 @@ struct FwdPlan {
 
 // Tile parameters (tune.cpp): the tuning table's entry for the shape and
 // size class of (n, q), else an entry set for every size, else the default.
-lip_tile_cfg default_tile_cfg(int d, int64_t n, int64_t q);
+lip_tile_cfg default_tile_cfg(int d, int dm, int norm, int64_t n, int64_t q);
 lip_tile_cfg tune_lookup(int d, int dm, int norm, int64_t n, int64_t q);
 // Writes the table to the file named by LIPFIT_TUNE_CACHE, if set.
 void tune_autosave();

@@ -20,7 +20,7 @@ struct FwdArgs {
     int32_t tile;            // records per argmin tile (multiple of 8)
     int32_t tiles_per_chunk;
     int32_t n_chunks;
-    int32_t pad0;
+    int32_t l2_filter;       // l2 with monotone coordinates: root-free filter (bounds_fwd.hpp)
     const float *xq;         // [q][D] row-major, untransformed
     int64_t q;
     Xform xf;                // query transform (same as the staging one)

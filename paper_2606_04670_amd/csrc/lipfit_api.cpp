@@ -104,7 +104,7 @@ size_t partial_bytes(int64_t q)
     return align_up((size_t)entries * 2 * sizeof(float), 256) * 2;
 }
 
-lip_tile_cfg default_tile_cfg(int d, int64_t n, int64_t q)
+lip_tile_cfg default_tile_cfg(int d, int dm, int norm, int64_t n, int64_t q)
 {
     // About 16 waves per SIMD (256 CUs x 4 SIMDs) so that the last wave of
     // each SIMD starts early (small tail), data split in a power-of-two
@@ -121,7 +121,9 @@ lip_tile_cfg default_tile_cfg(int d, int64_t n, int64_t q)
            (int64_t)split * 2 * q <= kMaxPartials)
         split *= 2;
     c.split = split;
-    c.reserved = 0;
+    // the root-free l2 filter paid on the d = 4 workload (two monotone
+    // coordinates) and was neutral to slower on loose bounds at d >= 8
+    c.flags = (norm == LIP_L2 && dm > 0 && d <= 4) ? LIP_TILE_L2_FILTER : 0;
     return c;
 }
 
@@ -197,6 +199,7 @@ lip_status run_bounds(const MetricInfo &mi, const float *x, const float *y, int6
     a.tile = p.tile;
     a.tiles_per_chunk = p.tiles_per_chunk;
     a.n_chunks = p.n_chunks;
+    a.l2_filter = (cfg.flags & LIP_TILE_L2_FILTER) ? 1 : 0;
     a.xq = xq;
     a.q = q;
     a.xf = xf;

@@ -1,5 +1,5 @@
-// Tuning table of the bound kernels' runtime tile parameters (argmin tile,
-// data split, waves per workgroup): lookup, lip_tune_get / lip_tune_set and
+// Tuning table of the bound kernels' runtime parameters (argmin tile, data
+// split, waves per workgroup, the l2 filter flag): lookup, lip_tune_get / lip_tune_set and
 // the JSON cache (lip_tune_save / lip_tune_load, LIPFIT_TUNE_CACHE).
 //
 // Key: (d, number of monotone coordinates, norm, size class of n, size class
@@ -11,7 +11,7 @@
 // Cache file (one JSON object):
 //   {"format": "lipfit-tune-1", "entries": [
 //     {"arch": "gfx950", "d": 4, "n_mon": 2, "norm": 2, "n_class": 8,
-//      "q_class": 9, "tile": 32, "split": 8, "waves": 4}, ...]}
+//      "q_class": 9, "tile": 32, "split": 8, "waves": 4, "flags": 1}, ...]}
 // Entries of another architecture are kept in the file but not loaded.
 #include <ctype.h>
 #include <stdio.h>
@@ -46,7 +46,8 @@ int size_class(int64_t v)
 bool cfg_valid(const lip_tile_cfg &c)
 {
     return c.tile >= 8 && c.tile <= kMaxTile && c.tile % 8 == 0 && c.split >= 1 &&
-           c.split <= kMaxChunks && c.waves >= 1 && c.waves <= 4;
+           c.split <= kMaxChunks && c.waves >= 1 && c.waves <= 4 &&
+           (c.flags & ~LIP_TILE_L2_FILTER) == 0;
 }
 
 // Architecture name of the current device without feature suffixes
@@ -109,7 +110,7 @@ struct Reader {
 struct Entry {
     std::string arch;
     long long d = -1, n_mon = -1, norm = -1, n_class = -2, q_class = -2, tile = -1, split = -1,
-              waves = -1;
+              waves = -1, flags = 0;
 };
 
 bool read_entry(Reader &r, Entry *e)
@@ -132,6 +133,7 @@ bool read_entry(Reader &r, Entry *e)
             else if (key == "tile") e->tile = v;
             else if (key == "split") e->split = v;
             else if (key == "waves") e->waves = v;
+            else if (key == "flags") e->flags = v;
             else return false;
         }
         if (r.lit('}')) return true;
@@ -160,7 +162,7 @@ lip_status load_locked(const char *path, const std::string &arch)
         for (;;) {
             Entry e;
             if (!read_entry(r, &e)) return LIP_E_VALUE;
-            lip_tile_cfg c{(int32_t)e.tile, (int32_t)e.split, (int32_t)e.waves, 0};
+            lip_tile_cfg c{(int32_t)e.tile, (int32_t)e.split, (int32_t)e.waves, (int32_t)e.flags};
             const bool shape_ok = e.d >= 1 && e.d <= kMaxDim && e.n_mon >= 0 && e.n_mon <= e.d &&
                                   e.norm >= LIP_L1 && e.norm <= LIP_LINF && e.n_class >= -1 &&
                                   e.q_class >= -1 && (e.n_class == -1) == (e.q_class == -1);
@@ -189,9 +191,10 @@ lip_status save_locked(const char *path, const std::string &arch)
         const lip_tile_cfg &c = kv.second;
         fprintf(f,
                 "%s\n  {\"arch\": \"%s\", \"d\": %d, \"n_mon\": %d, \"norm\": %d, "
-                "\"n_class\": %d, \"q_class\": %d, \"tile\": %d, \"split\": %d, \"waves\": %d}",
+                "\"n_class\": %d, \"q_class\": %d, \"tile\": %d, \"split\": %d, \"waves\": %d, "
+                "\"flags\": %d}",
                 first ? "" : ",", arch.c_str(), std::get<0>(k), std::get<1>(k), std::get<2>(k),
-                std::get<3>(k), std::get<4>(k), c.tile, c.split, c.waves);
+                std::get<3>(k), std::get<4>(k), c.tile, c.split, c.waves, c.flags);
         first = false;
     }
     fprintf(f, "\n]}\n");
@@ -222,7 +225,7 @@ lip_tile_cfg tune_lookup(int d, int dm, int norm, int64_t n, int64_t q)
         if (it == g_table.end()) it = g_table.find(TuneKey(d, dm, norm, -1, -1));
         if (it != g_table.end()) return it->second;
     }
-    return default_tile_cfg(d, n, q);
+    return default_tile_cfg(d, dm, norm, n, q);
 }
 
 void tune_autosave()
@@ -264,7 +267,6 @@ lip_status lip_tune_set(int32_t d, int32_t n_mon, int32_t norm, int64_t n, int64
     }
     if (!cfg_valid(*cfg)) return LIP_E_VALUE;
     g_table[key] = *cfg;
-    g_table[key].reserved = 0;
     return LIP_OK;
 }
 

@@ -148,6 +148,12 @@ def test_tuning_table(L):
     assert cfg.tile % 8 == 0 and cfg.split >= 1 and cfg.waves >= 1
     bad = L.LipTileCfg(12, 1, 4, 0)
     assert lib.lip_tune_set(4, 2, 1, 0, 0, ctypes.byref(bad)) == L.LIP_E_VALUE
+    bad_flags = L.LipTileCfg(32, 1, 4, 2)
+    assert lib.lip_tune_set(4, 2, 1, 0, 0, ctypes.byref(bad_flags)) == L.LIP_E_VALUE
+    # the default turns the l2 filter on with monotone coordinates at d <= 4 only
+    for d, m, norm, want in ((4, 2, 2, 1), (4, 0, 2, 0), (8, 4, 2, 0), (4, 2, 1, 0), (2, 1, 2, 1)):
+        lib.lip_tune_get(d, m, norm, 1000, 1000, ctypes.byref(cfg))
+        assert cfg.flags == want, (d, m, norm)
     assert lib.lip_tune_set(4, 2, 1, 10, 0, ctypes.byref(bad)) == L.LIP_E_SHAPE
     # an entry for every size
     good = L.LipTileCfg(128, 2, 2, 0)
@@ -177,7 +183,7 @@ def test_tune_cache_file(L, tmp_path):
     malformed files change nothing."""
     lib = L.load()
     lib.lip_tune_clear()
-    a = L.LipTileCfg(64, 4, 2, 0)
+    a = L.LipTileCfg(64, 4, 2, 1)
     b = L.LipTileCfg(32, 1, 4, 0)
     assert lib.lip_tune_set(3, 1, 2, 5000, 20000, ctypes.byref(a)) == L.LIP_OK
     assert lib.lip_tune_set(7, 0, 3, 0, 0, ctypes.byref(b)) == L.LIP_OK
@@ -196,7 +202,7 @@ def test_tune_cache_file(L, tmp_path):
     assert got.tile != 64 or got.split != 4
     assert lib.lip_tune_load(path.encode(), b"gfx950") == L.LIP_OK
     lib.lip_tune_get(3, 1, 2, 5000, 20000, ctypes.byref(got))
-    assert (got.tile, got.split, got.waves) == (64, 4, 2)
+    assert (got.tile, got.split, got.waves, got.flags) == (64, 4, 2, 1)
     lib.lip_tune_get(7, 0, 3, 123, 456, ctypes.byref(got))
     assert (got.tile, got.split, got.waves) == (32, 1, 4)
     # malformed or invalid files: LIP_E_VALUE and no change

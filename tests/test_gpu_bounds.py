@@ -114,8 +114,9 @@ def test_tiling_and_split_do_not_change_results(lf, norm):
                          local=True)
     ref = None
     try:
-        for tile, split, waves in [(64, 1, 4), (8, 1, 1), (256, 3, 2), (32, 16, 4), (128, 64, 3)]:
-            lf.tune_set(4, 2, norm, tile=tile, split=split, waves=waves)
+        for tile, split, waves, fl in [(64, 1, 4, 0), (8, 1, 1, 1), (256, 3, 2, 0), (32, 16, 4, 1),
+                                       (128, 64, 3, 1)]:
+            lf.tune_set(4, 2, norm, tile=tile, split=split, waves=waves, flags=fl)
             out = run(lf, p)
             if ref is None:
                 ref = out
@@ -185,3 +186,66 @@ def test_two_streams_keep_separate_scratch(lf):
             for k in ref[i]:
                 np.testing.assert_array_equal(outs[i][k].cpu().numpy(), ref[i][k],
                                               err_msg=f"stream {i} {k} rep {rep}")
+
+
+FILTER_CASES = [
+    # (d, monotone pattern, local, weighted)
+    (1, [1], False, False),
+    (2, [0, -1], True, False),
+    (3, [1, 0, 1], False, True),
+    (4, [1, 0, 1, 0], True, False),
+    (4, [-1, -1, 1, 1], False, True),
+    (5, [0, 1, 0, 0, 1], True, True),
+    (8, [1, 0] * 4, False, False),
+    (12, [0, 0, 1] * 4, True, True),
+    (16, [1] * 16, False, False),
+]
+
+
+def _with_cfg(lf, p, d, dm, fl, **kw):
+    try:
+        lf.tune_set(d, dm, 2, tile=32, split=4, waves=4, flags=fl)
+        return run(lf, p, **kw)
+    finally:
+        lf.tune_set(d, dm, 2, clear=True)
+
+
+@pytest.mark.parametrize("d,mon,local,weighted", FILTER_CASES)
+def test_l2_filter_identical(lf, d, mon, local, weighted):
+    """The root-free l2 filter (LIP_TILE_L2_FILTER) changes no output: every
+    value and index equal to the unfiltered kernel's, on random data, data
+    translated by 2^10, and queries placed on data points (distance 0); the
+    oracle checks the filtered results."""
+    mon = np.array(mon, np.int8)
+    dm = int(np.count_nonzero(mon))
+    p = W.random_problem(1700 + d, n=3001, q=2500, d=d, norm=2, mon=mon, local=local,
+                         weighted=weighted)
+    xq = p.xq.copy()
+    xq[::7] = p.x[: len(xq[::7])]            # some queries on data points
+    p = W.Problem(p.name, p.x, p.y, p.M, p.Mk, xq, 2, mon, p.w)
+    for shift in (0.0, 2.0 ** 10):
+        ps = W.Problem(p.name, (p.x.astype(np.float64) + shift).astype(np.float32), p.y, p.M,
+                       p.Mk, (p.xq.astype(np.float64) + shift).astype(np.float32), 2, mon, p.w)
+        off = _with_cfg(lf, ps, d, dm, 0)
+        on = _with_cfg(lf, ps, d, dm, 1)
+        for k in off:
+            np.testing.assert_array_equal(on[k], off[k], err_msg=f"{k} shift={shift}")
+        check_bounds(ps, on, label=f"filtered d={d} shift={shift}")
+
+
+def test_l2_filter_tiny_differences(lf):
+    """Components far below 2^-60 (coordinates ~1e-30, queries a few ulp away
+    from data) with values near 0, the case the filter's absolute margin
+    covers: identical to the unfiltered kernel."""
+    g = np.random.default_rng(1801)
+    n, d = 2000, 3
+    x = (g.random((n, d)) * 1e-30).astype(np.float32)
+    y = (g.standard_normal(n) * 1e-38).astype(np.float32)
+    xq = x[g.integers(0, n, 1500)].copy()
+    xq.view(np.int32)[:] += g.integers(-3, 4, xq.shape).astype(np.int32)  # a few ulp away
+    mon = np.array([1, 0, -1], np.int8)
+    p = W.Problem("tiny", x, y, 1e8, None, xq, 2, mon, np.ones(d, np.float32))
+    off = _with_cfg(lf, p, d, 2, 0)
+    on = _with_cfg(lf, p, d, 2, 1)
+    for k in off:
+        np.testing.assert_array_equal(on[k], off[k], err_msg=k)
