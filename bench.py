@@ -48,10 +48,11 @@ CONS_FLOP_PER_PAIR = {nm: f + 2 for nm, f in FLOP_PER_PAIR.items()}
 FLOP_PER_PAIR_L2_D16 = 16 * 3 + 1 + 6
 CONS_PEAK_TFLOPS = {"l1": FP64_PEAK_TFLOPS, "linf": FP64_PEAK_TFLOPS, "l2": FP32_PEAK_TFLOPS}
 
-# Hardware-counter figures of the kernels (VALU issue busy), from the
+# Hardware-counter figures of the forward kernels (VALU instructions per pair,
+# issue rate against one wave64 FMA per SIMD every 4 cycles), from the
 # rocprofv3 --pmc summary in profiles/; reported only while the kernel sources
 # hash to the profiled ones.
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "valu_busy_monotone_local.txt")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "valu_instructions_monotone_local.txt")
 
 
 # HBM traffic of the forward kernel, from rocprofv3 FETCH_SIZE / WRITE_SIZE
@@ -92,10 +93,11 @@ def measured_traffic(norm):
     return None if rec is None else rec["bytes_per_launch"].get(norm)
 
 
-def measured_valu_busy():
-    """VALU issue busy fraction per kernel name from the counters, or None."""
+def measured_valu(norm):
+    """VALU instructions per pair and issue rate of the forward kernel for
+    `norm` from the counters, or None."""
     rec = _profile_record(COUNTERS_FILE, "COUNTERS_JSON")
-    return None if rec is None else rec.get("valu_busy")
+    return None if rec is None else rec.get("valu", {}).get(norm)
 
 
 def parse():
@@ -455,14 +457,14 @@ def main():
     f_ms = stage_ms[dom]["forward"]
     achieved = FLOP_PER_PAIR[dom] * pairs / (f_ms * 1e-3) / 1e12
     kname = (f"bounds_fwd_kernel{'_o4' if dom != 'l1' else ''}<4, 2, {nid[dom]}>")
-    busy = measured_valu_busy()
+    valu = measured_valu(dom)
     roofline = {"bound": "alu", "kernel": f"{kname} ({dom} forward)",
                 "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
                 "traffic": measured_traffic(dom),
                 "flop_per_pair": FLOP_PER_PAIR[dom], "pairs_per_launch": pairs,
                 "launch_ms": round(f_ms, 3),
-                "valu_issue_busy_counters": None if busy is None else busy.get(dom)}
+                "valu_counters": valu}
 
     cpu = None
     if not a.no_cpu_baseline:
