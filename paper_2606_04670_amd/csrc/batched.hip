@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "host_common.hpp"
+#include "lip_device.hpp"
 
 namespace lip {
 
@@ -103,27 +104,20 @@ __global__ void fill_u32_kernel(unsigned int *p, int n, unsigned int v)
     for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = v;
 }
 
-__device__ __forceinline__ float f32_from_order_key(uint32_t k)
-{
-    return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
-}
-
-// Decodes the packed keys of the chunked sets: up = min over (key | index),
-// lo stored complemented so that its atomic is also a min.
+// Decodes the packed keys of the chunked sets (up_key / lo_key).
 __global__ void batched_finalize_kernel(const FwdArgs *sets, const int32_t *chunked, int n_chunked)
 {
     for (int c = blockIdx.x; c < n_chunked; c += gridDim.x) {
         const FwdArgs a = sets[chunked[c]];
         for (int64_t j = threadIdx.x; j < a.q; j += blockDim.x) {
-            const unsigned long long ku = a.keys[j];
-            const unsigned long long kl = ~a.keys[a.q + j];
-            const float hu = f32_from_order_key((uint32_t)(ku >> 32));
-            const float hl = f32_from_order_key((uint32_t)(kl >> 32));
+            float hu, hl;
+            int au, al;
+            decode_keys(a.keys[j], a.keys[a.q + j], hu, au, hl, al);
             if (a.g) a.g[j] = 0.5f * (hu + hl);
             if (a.h_up) a.h_up[j] = hu;
             if (a.h_lo) a.h_lo[j] = hl;
-            if (a.arg_up) a.arg_up[j] = (int32_t)(uint32_t)ku;
-            if (a.arg_lo) a.arg_lo[j] = (int32_t)(~(uint32_t)kl);
+            if (a.arg_up) a.arg_up[j] = au;
+            if (a.arg_lo) a.arg_lo[j] = al;
         }
     }
 }
@@ -198,7 +192,7 @@ extern "C" lip_status lip_plan_create(lip_plan **plan, const lip_batch_desc *set
         const lip_tile_cfg cfg = tune_lookup(p.mi.d, p.mi.dm, p.mi.norm, d.n, d.q);
         p.R = rows_for_dim(p.mi.d);
         p.tile = cfg.tile;
-        p.flags = cfg.flags;
+        p.flags = cfg.flags & LIP_TILE_L2_FILTER;  // the persistent kernel merges with keys
         p.n_pad = (d.n + p.tile - 1) / p.tile * p.tile;
         p.n_tiles = p.n_pad / p.tile;
         int64_t chunk_records = kItemPairs / (64 * p.R);
@@ -473,13 +467,14 @@ extern "C" lip_status lip_autotune(int32_t d, int32_t n_mon, int32_t norm, int64
     lip_tile_cfg best_cfg = tune_lookup(d, n_mon, norm, n, q);
     const int tiles[] = {16, 32, 64, 128};
     const int splits[] = {1, 2, 4, 8, 16, 32};
-    const int waves[] = {2, 4};
+    // (waves per workgroup, workgroup merge)
+    const int shapes[][2] = {{2, 0}, {4, 0}, {4, LIP_TILE_WG_MERGE}, {8, LIP_TILE_WG_MERGE}};
     const int n_flags = (norm == LIP_L2 && n_mon > 0) ? 2 : 1;
     for (int fl = 0; fl < n_flags; ++fl)
     for (int t : tiles)
         for (int sp : splits)
-            for (int w : waves) {
-                lip_tile_cfg c{t, sp, w, fl ? LIP_TILE_L2_FILTER : 0};
+            for (const auto &w : shapes) {
+                lip_tile_cfg c{t, sp, w[0], (fl ? LIP_TILE_L2_FILTER : 0) | w[1]};
                 // warm-up, then the mean of 3 runs
                 st = run_bounds(mi, x, y, n, 1.0f, nullptr, xq, q, g, nullptr, nullptr, nullptr,
                                 nullptr, ws, ws_bytes, c, s);

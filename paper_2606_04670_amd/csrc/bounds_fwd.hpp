@@ -22,6 +22,13 @@
 // them in chunk order (strict comparisons keep the lower index on ties).
 // In batched plans they instead merge packed (value, index) 64-bit keys with
 // atomic min / max, which also keeps the lowest index on ties.
+//
+// Workgroup merge (FwdArgs::wg_merge).  The waves of a workgroup take the
+// same 64 R queries and consecutive chunks, and merge their results as the
+// same packed keys with LDS atomics; the workgroup then writes the final
+// values (or one partial per group of chunks).  The chip is filled as with
+// a global split of the same chunk count, but every query is read from HBM
+// once and no partial results go through HBM.
 #pragma once
 
 #include <array>
@@ -152,19 +159,20 @@ __device__ __forceinline__ void eval_group_rows(const FwdArgs &a,
     for (int r = 0; r < R; ++r) eval_group<D, DM, NORM>(v, qv[r], qm[r], big, hu[r], hl[r]);
 }
 
-// One wave's work: queries [64 R qblock, 64 R (qblock + 1)) against data
-// chunk `chunk`.  Outputs: final values (one chunk), chunk partials, or
-// packed (value, index) keys merged with atomics (a.keys != NULL).
+// One lane's scan of its R queries (q0 + 64 r + lane) over data chunk
+// `chunk` (non-empty): running min / max and the attaining indices.
 template <int D, int DM, int NORM>
-__device__ __forceinline__ void fwd_wave(const FwdArgs &a, int chunk, int64_t qblock)
+__device__ __forceinline__ void fwd_scan(const FwdArgs &a, int chunk, int64_t q0,
+                                         float (&hu)[FwdTraits<D, DM, NORM>::R],
+                                         float (&hl)[FwdTraits<D, DM, NORM>::R],
+                                         int (&au)[FwdTraits<D, DM, NORM>::R],
+                                         int (&al)[FwdTraits<D, DM, NORM>::R])
 {
     constexpr int S = Rec<D>::S;
     constexpr int R = FwdTraits<D, DM, NORM>::R;
     constexpr int kGroup = group_for_dim(D);
     constexpr int GS = kGroup * S;
     const int lane = threadIdx.x & 63;
-    const int64_t q0 = qblock * (64 * R);
-    if (q0 >= a.q) return;  // wave-uniform: no query of this wave exists
 
     const float big = opaque_inf();
     float qv[R][D];
@@ -185,7 +193,7 @@ __device__ __forceinline__ void fwd_wave(const FwdArgs &a, int chunk, int64_t qb
     const int tile = a.tile;
     const int gpt = tile / kGroup;  // groups per tile
 
-    float hu[R], hl[R], pu[R], pl[R];
+    float pu[R], pl[R];
     int tu[R], tl[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -227,7 +235,6 @@ __device__ __forceinline__ void fwd_wave(const FwdArgs &a, int chunk, int64_t qb
 
     // Re-scan the last improving tile of each query for the first index that
     // attains the final value (descending scan: the last hit is the lowest).
-    int au[R], al[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int64_t bu = (int64_t)tu[r] * tile, bl = (int64_t)tl[r] * tile;
@@ -254,6 +261,23 @@ __device__ __forceinline__ void fwd_wave(const FwdArgs &a, int chunk, int64_t qb
         al[r] = il;
     }
 
+}
+
+// One wave's work item of a batched plan: queries [64 R qblock, 64 R
+// (qblock + 1)) against data chunk `chunk`.  Outputs: final values (one
+// chunk) or packed (value, index) keys merged with atomics (a.keys).
+template <int D, int DM, int NORM>
+__device__ __forceinline__ void fwd_wave(const FwdArgs &a, int chunk, int64_t qblock)
+{
+    constexpr int R = FwdTraits<D, DM, NORM>::R;
+    const int lane = threadIdx.x & 63;
+    const int64_t q0 = qblock * (64 * R);
+    if (q0 >= a.q) return;  // wave-uniform: no query of this wave exists
+
+    float hu[R], hl[R];
+    int au[R], al[R];
+    fwd_scan<D, DM, NORM>(a, chunk, q0, hu, hl, au, al);
+
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int64_t qi = q0 + r * 64 + lane;
@@ -264,42 +288,105 @@ __device__ __forceinline__ void fwd_wave(const FwdArgs &a, int chunk, int64_t qb
             if (a.h_lo) a.h_lo[qi] = hl[r];
             if (a.arg_up) a.arg_up[qi] = au[r];
             if (a.arg_lo) a.arg_lo[qi] = al[r];
-        } else if (a.keys) {
-            // min of (key(value) << 32 | index) = min value, lowest index;
-            // max of (key(value) << 32 | ~index) = max value, lowest index,
-            // stored complemented so that both merges are atomic minima
-            // (one fill value initialises the whole key buffer)
-            const unsigned long long ku =
-                ((unsigned long long)f32_order_key(hu[r]) << 32) | (uint32_t)au[r];
-            const unsigned long long kl =
-                ((unsigned long long)f32_order_key(hl[r]) << 32) | (uint32_t)(~(uint32_t)al[r]);
-            atomicMin(a.keys + qi, ku);
-            atomicMin(a.keys + a.q + qi, ~kl);
         } else {
-            const int64_t o = (int64_t)chunk * a.q + qi;
-            const int64_t o2 = ((int64_t)a.n_chunks + chunk) * a.q + qi;
-            a.part_v[o] = hu[r];
-            a.part_i[o] = au[r];
-            a.part_v[o2] = hl[r];
-            a.part_i[o2] = al[r];
+            atomicMin(a.keys + qi, up_key(hu[r], au[r]));
+            atomicMin(a.keys + a.q + qi, lo_key(hl[r], al[r]));
+        }
+    }
+}
+
+// One workgroup of the single-set kernel.  Plain: wave w takes queries
+// [64 R qb, 64 R (qb + 1)) with qb = (b / n_chunks) waves + w and chunk
+// b % n_chunks of workgroup b.  Workgroup merge: workgroup b takes queries
+// [64 R (b / outer), 64 R (b / outer + 1)) and, with outer = n_chunks /
+// waves, wave w takes chunk oc waves + w of oc = b % outer (chunks past the
+// data are empty); with outer > 1 the merged result is partial number oc of
+// the combine kernel.  Both modes share one inlined scan.
+template <int D, int DM, int NORM>
+__device__ __forceinline__ void fwd_block(const FwdArgs &a)
+{
+    constexpr int R = FwdTraits<D, DM, NORM>::R;
+    __shared__ unsigned long long mk[2][64 * R];
+    // wave index is wave-uniform; readfirstlane lets the compiler keep every
+    // loop counter and address derived from it in SGPRs
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nw = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const bool merge = a.wg_merge != 0;
+    int chunk, oc = 0, outer = 1;
+    int64_t q0;
+    if (merge) {
+        outer = a.n_chunks / nw;
+        oc = (int)(blockIdx.x % (unsigned)outer);
+        q0 = (int64_t)(blockIdx.x / (unsigned)outer) * (64 * R);
+        chunk = oc * nw + wave;
+        if (q0 >= a.q) return;  // workgroup-uniform
+        for (int i = threadIdx.x; i < 2 * 64 * R; i += blockDim.x) (&mk[0][0])[i] = ~0ull;
+        __syncthreads();
+    } else {
+        chunk = (int)(blockIdx.x % (unsigned)a.n_chunks);
+        q0 = ((int64_t)(blockIdx.x / (unsigned)a.n_chunks) * nw + wave) * (64 * R);
+        if (q0 >= a.q) return;  // wave-uniform
+    }
+    const bool active = (int64_t)chunk * a.tiles_per_chunk < a.n_tiles;  // wave-uniform
+    float hu[R], hl[R];
+    int au[R], al[R];
+    if (active) fwd_scan<D, DM, NORM>(a, chunk, q0, hu, hl, au, al);
+    if (!merge) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t qi = q0 + r * 64 + lane;
+            if (qi >= a.q) continue;
+            if (a.n_chunks == 1) {
+                if (a.g) a.g[qi] = 0.5f * (hu[r] + hl[r]);
+                if (a.h_up) a.h_up[qi] = hu[r];
+                if (a.h_lo) a.h_lo[qi] = hl[r];
+                if (a.arg_up) a.arg_up[qi] = au[r];
+                if (a.arg_lo) a.arg_lo[qi] = al[r];
+            } else {
+                const int64_t o = (int64_t)chunk * a.q + qi;
+                const int64_t o2 = ((int64_t)a.n_chunks + chunk) * a.q + qi;
+                a.part_v[o] = hu[r];
+                a.part_i[o] = au[r];
+                a.part_v[o2] = hl[r];
+                a.part_i[o2] = al[r];
+            }
+        }
+        return;
+    }
+    if (active) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            atomicMin(&mk[0][r * 64 + lane], up_key(hu[r], au[r]));
+            atomicMin(&mk[1][r * 64 + lane], lo_key(hl[r], al[r]));
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 64 * R; i += blockDim.x) {
+        const int64_t qi = q0 + i;
+        if (qi >= a.q) break;
+        float vu, vl;
+        int iu, il;
+        decode_keys(mk[0][i], mk[1][i], vu, iu, vl, il);
+        if (outer == 1) {
+            if (a.g) a.g[qi] = 0.5f * (vu + vl);
+            if (a.h_up) a.h_up[qi] = vu;
+            if (a.h_lo) a.h_lo[qi] = vl;
+            if (a.arg_up) a.arg_up[qi] = iu;
+            if (a.arg_lo) a.arg_lo[qi] = il;
+        } else {
+            const int64_t o = (int64_t)oc * a.q + qi;
+            const int64_t o2 = ((int64_t)outer + oc) * a.q + qi;
+            a.part_v[o] = vu;
+            a.part_i[o] = iu;
+            a.part_v[o2] = vl;
+            a.part_i[o2] = il;
         }
     }
 }
 
 template <int D, int DM, int NORM>
-__device__ __forceinline__ void fwd_block(const FwdArgs &a)
-{
-    // wave index is wave-uniform; readfirstlane lets the compiler keep every
-    // loop counter and address derived from it in SGPRs
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int nw = blockDim.x >> 6;
-    const int chunk = blockIdx.x % a.n_chunks;
-    const int64_t qblock = (int64_t)(blockIdx.x / a.n_chunks) * nw + wave;
-    fwd_wave<D, DM, NORM>(a, chunk, qblock);
-}
-
-template <int D, int DM, int NORM>
-__global__ void __launch_bounds__(256) bounds_fwd_kernel(FwdArgs a)
+__global__ void __launch_bounds__(512) bounds_fwd_kernel(FwdArgs a)
 {
     fwd_block<D, DM, NORM>(a);
 }
@@ -309,7 +396,7 @@ __global__ void __launch_bounds__(256) bounds_fwd_kernel(FwdArgs a)
 // with its extra per-query sum spills): more waves to hide the latency of
 // the square roots and of the scalar loads.
 template <int D, int DM, int NORM>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
 bounds_fwd_kernel_o4(FwdArgs a)
 {
     fwd_block<D, DM, NORM>(a);

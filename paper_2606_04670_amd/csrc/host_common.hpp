@@ -14,6 +14,7 @@ namespace lip {
 
 constexpr int kMaxTile = 256;                 // largest argmin tile (records)
 constexpr int kMaxChunks = 64;                // largest data split
+constexpr int kMaxFwdWaves = 8;               // waves per workgroup of the bound kernel
 constexpr int64_t kMaxPartials = 1ll << 23;   // n_chunks * q cap (per bound)
 constexpr int64_t kMaxIndex = 2147483647ll;   // indices are int32
 
@@ -58,10 +59,20 @@ struct FwdPlan {
     int R = 0;
     int tile = 64;
     int waves = 4;
+    bool merge = false;      // workgroup merge (LIP_TILE_WG_MERGE)
     int64_t n_pad = 0, n_tiles = 0;
-    int tiles_per_chunk = 0, n_chunks = 1;
+    int tiles_per_chunk = 0;
+    int n_chunks = 1;        // chunks launched (merge: a multiple of waves, the last may be empty)
+    int part_chunks = 1;     // partial results per query the combine kernel reduces (1: none)
     int64_t grid = 0;
 };
+
+// Bytes of the split partials of a plan (values and indices of both bounds).
+inline size_t fwd_partial_bytes(const FwdPlan &p, int64_t q)
+{
+    if (p.part_chunks <= 1) return 0;
+    return 2 * align_up((size_t)p.part_chunks * (size_t)q * 2 * sizeof(float), 256);
+}
 
 // Tile parameters (tune.cpp): the tuning table's entry for the shape and
 // size class of (n, q), else an entry set for every size, else the default.

@@ -206,4 +206,31 @@ __device__ __forceinline__ uint32_t f32_order_key(float v)
     return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
 }
 
+// Packed keys of a result: min of (key(value) << 32 | index) is the smallest
+// value with the lowest index; the lower bound stores (key(value) << 32 |
+// ~index) complemented, so that its maximum with the lowest index is a
+// minimum too (one fill value initialises both).  Adding +0 maps -0 to +0,
+// so values that compare equal have equal keys.
+__device__ __forceinline__ unsigned long long up_key(float v, int idx)
+{
+    return ((unsigned long long)f32_order_key(v + 0.0f) << 32) | (uint32_t)idx;
+}
+__device__ __forceinline__ unsigned long long lo_key(float v, int idx)
+{
+    return ~(((unsigned long long)f32_order_key(v + 0.0f) << 32) | (uint32_t)(~(uint32_t)idx));
+}
+__device__ __forceinline__ float f32_from_order_key(uint32_t k)
+{
+    return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
+}
+__device__ __forceinline__ void decode_keys(unsigned long long ku, unsigned long long kl_stored,
+                                            float &hu, int &au, float &hl, int &al)
+{
+    const unsigned long long kl = ~kl_stored;
+    hu = f32_from_order_key((uint32_t)(ku >> 32));
+    hl = f32_from_order_key((uint32_t)(kl >> 32));
+    au = (int)(uint32_t)ku;
+    al = (int)(~(uint32_t)kl);
+}
+
 }  // namespace lip

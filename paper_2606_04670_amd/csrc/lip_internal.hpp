@@ -21,6 +21,7 @@ struct FwdArgs {
     int32_t tiles_per_chunk;
     int32_t n_chunks;
     int32_t l2_filter;       // l2 with monotone coordinates: root-free filter (bounds_fwd.hpp)
+    int32_t wg_merge;        // 1: the waves of a workgroup share queries, merge in LDS
     const float *xq;         // [q][D] row-major, untransformed
     int64_t q;
     Xform xf;                // query transform (same as the staging one)

@@ -65,10 +65,7 @@ extern "C" lip_status lip_fit_eval_noalloc(const lip_metric *metric, const float
     if (q == 0) return LIP_OK;
     lip_tile_cfg cfg = tune_lookup(mi.d, mi.dm, mi.norm, n, q);
     for (;;) {
-        const FwdPlan p = make_fwd_plan(mi, n, q, cfg);
-        const size_t part =
-            p.n_chunks > 1 ? 2 * align_up((size_t)p.n_chunks * (size_t)q * 2 * sizeof(float), 256)
-                           : 0;
+        const size_t part = fwd_partial_bytes(make_fwd_plan(mi, n, q, cfg), q);
         if (base + part <= kScratchBytes || cfg.split <= 1) break;
         cfg.split /= 2;
     }

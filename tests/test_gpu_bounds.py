@@ -114,8 +114,12 @@ def test_tiling_and_split_do_not_change_results(lf, norm):
                          local=True)
     ref = None
     try:
+        # flags: 1 = l2 filter, 2 = workgroup merge (with 8 waves and split 5
+        # the merge runs 5 waves; split 64 with 8 waves leaves 8 partials)
         for tile, split, waves, fl in [(64, 1, 4, 0), (8, 1, 1, 1), (256, 3, 2, 0), (32, 16, 4, 1),
-                                       (128, 64, 3, 1)]:
+                                       (128, 64, 3, 1), (32, 8, 8, 2), (16, 5, 8, 3),
+                                       (8, 64, 8, 2), (32, 3, 2, 3), (128, 1, 8, 2),
+                                       (64, 16, 4, 2)]:
             lf.tune_set(4, 2, norm, tile=tile, split=split, waves=waves, flags=fl)
             out = run(lf, p)
             if ref is None:
@@ -129,6 +133,37 @@ def test_tiling_and_split_do_not_change_results(lf, norm):
     out2 = run(lf, p)
     for k in ref:
         np.testing.assert_array_equal(out2[k], ref[k])
+
+
+@pytest.mark.parametrize("norm", [1, 2, 3])
+@pytest.mark.parametrize("d", [1, 2, 5, 7, 11, 16])
+def test_wg_merge_identical(lf, norm, d):
+    """The workgroup merge (LIP_TILE_WG_MERGE) gives the plain kernel's
+    values and indices at every dimension, including ties across chunks:
+    the data are 40 points repeated, so every candidate value occurs in
+    every chunk and the lowest index must win."""
+    g = W.rng_for(1900, d, norm)
+    mon = np.zeros(d, np.int8)
+    mon[::2] = 1
+    base = g.random((40, d)).astype(np.float32)
+    x = np.tile(base, (125, 1))
+    y = np.tile(g.standard_normal(40).astype(np.float32), 125)
+    xq = g.random((1700, d)).astype(np.float32)
+    xq[::9] = base[g.integers(0, 40, len(xq[::9]))]          # queries on data points
+    p = W.Problem("repeated", x, y, 1.25, None, xq, norm, mon, np.ones(d, np.float32))
+    dm = int(mon.sum())
+    outs = []
+    try:
+        for tile, split, waves, fl in [(8, 16, 4, 0), (8, 16, 8, 2), (16, 12, 4, 2), (8, 40, 8, 2)]:
+            lf.tune_set(d, dm, norm, tile=tile, split=split, waves=waves, flags=fl)
+            outs.append(run(lf, p))
+    finally:
+        lf.tune_set(d, dm, norm, clear=True)
+    for o in outs[1:]:
+        for k in o:
+            np.testing.assert_array_equal(o[k], outs[0][k], err_msg=k)
+    assert outs[0]["arg_up"].max() < 40 and outs[0]["arg_lo"].max() < 40
+    check_bounds(p, outs[1], label=f"merge d={d} norm={norm}")
 
 
 @pytest.mark.parametrize("norm", [1, 2, 3])
