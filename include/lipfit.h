@@ -385,7 +385,13 @@ lip_status lip_plan_destroy(lip_plan *plan);
 typedef struct {
     int32_t tile;         /* data points per argmin tile (multiple of 8, 8..256) */
     int32_t split;        /* number of data chunks (1..64; 1 = no split) */
-    int32_t waves;        /* waves per workgroup (1..8) */
+    int32_t waves;        /* waves per workgroup (1..8).  At d <= 8 the waves of a
+                           * workgroup take the same queries and consecutive
+                           * chunks and merge their results in LDS, so that
+                           * only split / waves partial results per query go
+                           * through HBM; at d >= 9 they take different
+                           * queries and at most 4 are used (lip_bounds,
+                           * lip_fit_eval; plans run one wave per work item) */
     int32_t flags;        /* LIP_TILE_* bits */
 } lip_tile_cfg;
 
@@ -395,13 +401,6 @@ typedef struct {
  * queries where some query could improve.  Identical results; faster when
  * few data compete for each query (default on for d <= 4). */
 #define LIP_TILE_L2_FILTER 1
-/* The waves of a workgroup evaluate the same queries against `waves`
- * consecutive data chunks and merge their minima / maxima (with the lowest
- * attaining index) in LDS; the workgroup writes the result, or one partial
- * result per group of `waves` chunks when split > waves.  Identical results;
- * each query is read from HBM once and fewer partial results are written
- * than with split chunks alone. */
-#define LIP_TILE_WG_MERGE 2
 
 /* The configuration the next call of these sizes will use: the table's
  * entry for the size class of (n, q), else the entry set for every size,
@@ -414,9 +413,9 @@ lip_status lip_tune_get(int32_t d, int32_t n_mon, int32_t norm, int64_t n, int64
  * entry.  Invalid values: LIP_E_VALUE. */
 lip_status lip_tune_set(int32_t d, int32_t n_mon, int32_t norm, int64_t n, int64_t q,
                         const lip_tile_cfg *cfg);
-/* Times every candidate (tile 16/32/64/128 x split 1..32 x {2 or 4 waves,
- * 4 or 8 waves with LIP_TILE_WG_MERGE}, and for l2 with monotone
- * coordinates with and without LIP_TILE_L2_FILTER) for
+/* Times every candidate (tile 16/32/64/128 x split 1..32 x 1, 2, 4 or 8
+ * waves up to the split, and for l2 with monotone coordinates with and
+ * without LIP_TILE_L2_FILTER) for
  * this shape class on synthetic data of the given sizes (allocates and frees
  * its own device memory, blocks), stores the fastest under the size class of
  * (n, q) and returns it; with LIPFIT_TUNE_CACHE set, the whole table is then

@@ -192,7 +192,7 @@ extern "C" lip_status lip_plan_create(lip_plan **plan, const lip_batch_desc *set
         const lip_tile_cfg cfg = tune_lookup(p.mi.d, p.mi.dm, p.mi.norm, d.n, d.q);
         p.R = rows_for_dim(p.mi.d);
         p.tile = cfg.tile;
-        p.flags = cfg.flags & LIP_TILE_L2_FILTER;  // the persistent kernel merges with keys
+        p.flags = cfg.flags;
         p.n_pad = (d.n + p.tile - 1) / p.tile * p.tile;
         p.n_tiles = p.n_pad / p.tile;
         int64_t chunk_records = kItemPairs / (64 * p.R);
@@ -467,14 +467,14 @@ extern "C" lip_status lip_autotune(int32_t d, int32_t n_mon, int32_t norm, int64
     lip_tile_cfg best_cfg = tune_lookup(d, n_mon, norm, n, q);
     const int tiles[] = {16, 32, 64, 128};
     const int splits[] = {1, 2, 4, 8, 16, 32};
-    // (waves per workgroup, workgroup merge)
-    const int shapes[][2] = {{2, 0}, {4, 0}, {4, LIP_TILE_WG_MERGE}, {8, LIP_TILE_WG_MERGE}};
+    const int waves[] = {1, 2, 4, 8};
     const int n_flags = (norm == LIP_L2 && n_mon > 0) ? 2 : 1;
     for (int fl = 0; fl < n_flags; ++fl)
     for (int t : tiles)
         for (int sp : splits)
-            for (const auto &w : shapes) {
-                lip_tile_cfg c{t, sp, w[0], (fl ? LIP_TILE_L2_FILTER : 0) | w[1]};
+            for (int w : waves) {
+                if (w > sp) continue;  // the same launch as w = sp
+                lip_tile_cfg c{t, sp, w, fl ? LIP_TILE_L2_FILTER : 0};
                 // warm-up, then the mean of 3 runs
                 st = run_bounds(mi, x, y, n, 1.0f, nullptr, xq, q, g, nullptr, nullptr, nullptr,
                                 nullptr, ws, ws_bytes, c, s);

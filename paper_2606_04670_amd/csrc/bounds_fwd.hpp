@@ -18,17 +18,20 @@
 // arithmetic (pair_bounds) finds it.  Ties therefore resolve to the lowest
 // index, as in the definition.
 //
-// Split chunks write per-chunk partial results; a combine kernel reduces
-// them in chunk order (strict comparisons keep the lower index on ties).
-// In batched plans they instead merge packed (value, index) 64-bit keys with
-// atomic min / max, which also keeps the lowest index on ties.
-//
-// Workgroup merge (FwdArgs::wg_merge).  The waves of a workgroup take the
-// same 64 R queries and consecutive chunks, and merge their results as the
-// same packed keys with LDS atomics; the workgroup then writes the final
-// values (or one partial per group of chunks).  The chip is filled as with
-// a global split of the same chunk count, but every query is read from HBM
-// once and no partial results go through HBM.
+// Chunks of one query block (d <= 8).  The waves of a workgroup take the
+// same 64 R queries and consecutive data chunks, and merge their results as
+// packed (value, index) 64-bit keys with LDS atomic minima (lowest index on
+// ties); the workgroup writes the final values, or, when the data are split
+// into more chunks than it has waves, one partial result per group of
+// chunks, which a combine kernel reduces in group order (strict comparisons
+// keep the lower index on ties).  More waves per workgroup fill the chip like
+// a global split of the same chunk count, but read each query from HBM once
+// and write no partials.  At d >= 9 the records of two scalar-load groups
+// leave no scalar registers for the merge's state, so there the waves of a
+// workgroup take different query blocks of one chunk and every chunk writes
+// partials.  Batched plans merge the chunks of a set with global atomics on
+// the same keys.
+
 #pragma once
 
 #include <array>
@@ -160,13 +163,11 @@ __device__ __forceinline__ void eval_group_rows(const FwdArgs &a,
 }
 
 // One lane's scan of its R queries (q0 + 64 r + lane) over data chunk
-// `chunk` (non-empty): running min / max and the attaining indices.
-template <int D, int DM, int NORM>
-__device__ __forceinline__ void fwd_scan(const FwdArgs &a, int chunk, int64_t q0,
-                                         float (&hu)[FwdTraits<D, DM, NORM>::R],
-                                         float (&hl)[FwdTraits<D, DM, NORM>::R],
-                                         int (&au)[FwdTraits<D, DM, NORM>::R],
-                                         int (&al)[FwdTraits<D, DM, NORM>::R])
+// `chunk` (non-empty): running min / max and the attaining indices, handed
+// to emit(hu, hl, au, al).  The arrays stay local to the scan: passing them
+// out by reference cost registers in the main loop at d >= 9.
+template <int D, int DM, int NORM, class Emit>
+__device__ __forceinline__ void fwd_scan(const FwdArgs &a, int chunk, int64_t q0, Emit &&emit)
 {
     constexpr int S = Rec<D>::S;
     constexpr int R = FwdTraits<D, DM, NORM>::R;
@@ -193,7 +194,7 @@ __device__ __forceinline__ void fwd_scan(const FwdArgs &a, int chunk, int64_t q0
     const int tile = a.tile;
     const int gpt = tile / kGroup;  // groups per tile
 
-    float pu[R], pl[R];
+    float hu[R], hl[R], pu[R], pl[R];
     int tu[R], tl[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -235,6 +236,7 @@ __device__ __forceinline__ void fwd_scan(const FwdArgs &a, int chunk, int64_t q0
 
     // Re-scan the last improving tile of each query for the first index that
     // attains the final value (descending scan: the last hit is the lowest).
+    int au[R], al[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int64_t bu = (int64_t)tu[r] * tile, bl = (int64_t)tl[r] * tile;
@@ -260,7 +262,7 @@ __device__ __forceinline__ void fwd_scan(const FwdArgs &a, int chunk, int64_t q0
         au[r] = iu;
         al[r] = il;
     }
-
+    emit(hu, hl, au, al);
 }
 
 // One wave's work item of a batched plan: queries [64 R qblock, 64 R
@@ -274,65 +276,45 @@ __device__ __forceinline__ void fwd_wave(const FwdArgs &a, int chunk, int64_t qb
     const int64_t q0 = qblock * (64 * R);
     if (q0 >= a.q) return;  // wave-uniform: no query of this wave exists
 
-    float hu[R], hl[R];
-    int au[R], al[R];
-    fwd_scan<D, DM, NORM>(a, chunk, q0, hu, hl, au, al);
-
+    fwd_scan<D, DM, NORM>(a, chunk, q0, [&](const float(&hu)[R], const float(&hl)[R], const int(&au)[R], const int(&al)[R]) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int64_t qi = q0 + r * 64 + lane;
-        if (qi >= a.q) continue;
-        if (a.n_chunks == 1) {
-            if (a.g) a.g[qi] = 0.5f * (hu[r] + hl[r]);
-            if (a.h_up) a.h_up[qi] = hu[r];
-            if (a.h_lo) a.h_lo[qi] = hl[r];
-            if (a.arg_up) a.arg_up[qi] = au[r];
-            if (a.arg_lo) a.arg_lo[qi] = al[r];
-        } else {
-            atomicMin(a.keys + qi, up_key(hu[r], au[r]));
-            atomicMin(a.keys + a.q + qi, lo_key(hl[r], al[r]));
+        for (int r = 0; r < R; ++r) {
+            const int64_t qi = q0 + r * 64 + lane;
+            if (qi >= a.q) continue;
+            if (a.n_chunks == 1) {
+                if (a.g) a.g[qi] = 0.5f * (hu[r] + hl[r]);
+                if (a.h_up) a.h_up[qi] = hu[r];
+                if (a.h_lo) a.h_lo[qi] = hl[r];
+                if (a.arg_up) a.arg_up[qi] = au[r];
+                if (a.arg_lo) a.arg_lo[qi] = al[r];
+            } else {
+                atomicMin(a.keys + qi, up_key(hu[r], au[r]));
+                atomicMin(a.keys + a.q + qi, lo_key(hl[r], al[r]));
+            }
         }
-    }
+    });
 }
 
-// One workgroup of the single-set kernel.  Plain: wave w takes queries
-// [64 R qb, 64 R (qb + 1)) with qb = (b / n_chunks) waves + w and chunk
-// b % n_chunks of workgroup b.  Workgroup merge: workgroup b takes queries
-// [64 R (b / outer), 64 R (b / outer + 1)) and, with outer = n_chunks /
-// waves, wave w takes chunk oc waves + w of oc = b % outer (chunks past the
+// One workgroup of the single-set kernel, d <= 8: workgroup b takes
+// queries [64 R (b / outer), 64 R (b / outer + 1)) and, with outer = n_chunks
+// / waves, wave w takes chunk oc waves + w of oc = b % outer (chunks past the
 // data are empty); with outer > 1 the merged result is partial number oc of
-// the combine kernel.  Both modes share one inlined scan.
+// the combine kernel.  d >= 9: wave w takes queries [64 R qb, 64 R (qb + 1))
+// with qb = (b / n_chunks) waves + w and chunk b % n_chunks, and writes that
+// chunk's partials (or the final values with one chunk).
+constexpr bool fwd_merges(int D) { return D <= kFwdMergeMaxDim; }
+
 template <int D, int DM, int NORM>
-__device__ __forceinline__ void fwd_block(const FwdArgs &a)
+__device__ __forceinline__ void fwd_block_plain(const FwdArgs &a)
 {
     constexpr int R = FwdTraits<D, DM, NORM>::R;
-    __shared__ unsigned long long mk[2][64 * R];
-    // wave index is wave-uniform; readfirstlane lets the compiler keep every
-    // loop counter and address derived from it in SGPRs
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nw = blockDim.x >> 6;
     const int lane = threadIdx.x & 63;
-    const bool merge = a.wg_merge != 0;
-    int chunk, oc = 0, outer = 1;
-    int64_t q0;
-    if (merge) {
-        outer = a.n_chunks / nw;
-        oc = (int)(blockIdx.x % (unsigned)outer);
-        q0 = (int64_t)(blockIdx.x / (unsigned)outer) * (64 * R);
-        chunk = oc * nw + wave;
-        if (q0 >= a.q) return;  // workgroup-uniform
-        for (int i = threadIdx.x; i < 2 * 64 * R; i += blockDim.x) (&mk[0][0])[i] = ~0ull;
-        __syncthreads();
-    } else {
-        chunk = (int)(blockIdx.x % (unsigned)a.n_chunks);
-        q0 = ((int64_t)(blockIdx.x / (unsigned)a.n_chunks) * nw + wave) * (64 * R);
-        if (q0 >= a.q) return;  // wave-uniform
-    }
-    const bool active = (int64_t)chunk * a.tiles_per_chunk < a.n_tiles;  // wave-uniform
-    float hu[R], hl[R];
-    int au[R], al[R];
-    if (active) fwd_scan<D, DM, NORM>(a, chunk, q0, hu, hl, au, al);
-    if (!merge) {
+    const int chunk = (int)(blockIdx.x % (unsigned)a.n_chunks);
+    const int64_t q0 = ((int64_t)(blockIdx.x / (unsigned)a.n_chunks) * nw + wave) * (64 * R);
+    if (q0 >= a.q) return;  // wave-uniform
+    fwd_scan<D, DM, NORM>(a, chunk, q0, [&](const float(&hu)[R], const float(&hl)[R], const int(&au)[R], const int(&al)[R]) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int64_t qi = q0 + r * 64 + lane;
@@ -352,14 +334,34 @@ __device__ __forceinline__ void fwd_block(const FwdArgs &a)
                 a.part_i[o2] = al[r];
             }
         }
-        return;
-    }
-    if (active) {
+    });
+}
+
+template <int D, int DM, int NORM>
+__device__ __forceinline__ void fwd_block_merge(const FwdArgs &a)
+{
+    constexpr int R = FwdTraits<D, DM, NORM>::R;
+    __shared__ unsigned long long mk[2][64 * R];
+    // wave index is wave-uniform; readfirstlane lets the compiler keep every
+    // loop counter and address derived from it in SGPRs
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nw = blockDim.x >> 6;
+    const int outer = a.n_chunks / nw;
+    const int oc = (int)(blockIdx.x % (unsigned)outer);
+    const int64_t q0 = (int64_t)(blockIdx.x / (unsigned)outer) * (64 * R);
+    if (q0 >= a.q) return;  // workgroup-uniform
+    for (int i = threadIdx.x; i < 2 * 64 * R; i += blockDim.x) (&mk[0][0])[i] = ~0ull;
+    __syncthreads();
+    const int chunk = oc * nw + wave;
+    if ((int64_t)chunk * a.tiles_per_chunk < a.n_tiles) {  // wave-uniform
+        fwd_scan<D, DM, NORM>(a, chunk, q0, [&](const float(&hu)[R], const float(&hl)[R], const int(&au)[R], const int(&al)[R]) {
+            const int lane = threadIdx.x & 63;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            atomicMin(&mk[0][r * 64 + lane], up_key(hu[r], au[r]));
-            atomicMin(&mk[1][r * 64 + lane], lo_key(hl[r], al[r]));
-        }
+            for (int r = 0; r < R; ++r) {
+                atomicMin(&mk[0][r * 64 + lane], up_key(hu[r], au[r]));
+                atomicMin(&mk[1][r * 64 + lane], lo_key(hl[r], al[r]));
+            }
+        });
     }
     __syncthreads();
     for (int i = threadIdx.x; i < 64 * R; i += blockDim.x) {
@@ -386,7 +388,19 @@ __device__ __forceinline__ void fwd_block(const FwdArgs &a)
 }
 
 template <int D, int DM, int NORM>
-__global__ void __launch_bounds__(512) bounds_fwd_kernel(FwdArgs a)
+__device__ __forceinline__ void fwd_block(const FwdArgs &a)
+{
+    if constexpr (fwd_merges(D))
+        fwd_block_merge<D, DM, NORM>(a);
+    else
+        fwd_block_plain<D, DM, NORM>(a);
+}
+
+// Workgroups of up to 8 waves where chunks merge, else up to 4.
+constexpr int fwd_max_threads(int D) { return fwd_merges(D) ? 512 : 64 * kFwdPlainMaxWaves; }
+
+template <int D, int DM, int NORM>
+__global__ void __launch_bounds__(fwd_max_threads(D)) bounds_fwd_kernel(FwdArgs a)
 {
     fwd_block<D, DM, NORM>(a);
 }
@@ -396,13 +410,25 @@ __global__ void __launch_bounds__(512) bounds_fwd_kernel(FwdArgs a)
 // with its extra per-query sum spills): more waves to hide the latency of
 // the square roots and of the scalar loads.
 template <int D, int DM, int NORM>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(fwd_max_threads(D)) __attribute__((amdgpu_waves_per_eu(4)))
 bounds_fwd_kernel_o4(FwdArgs a)
 {
     fwd_block<D, DM, NORM>(a);
 }
 
 constexpr bool fwd_use_o4(int D, int NORM) { return NORM != kNormL1 && D >= 3 && D <= 8; }
+
+// d >= 9 (4 rows per lane) held to 168 VGPRs, 3 waves per SIMD: the
+// unconstrained allocation takes a few registers more than that at some
+// dimensions (d = 15 keeps it: under the cap it spills to scratch).
+template <int D, int DM, int NORM>
+__global__ void __launch_bounds__(fwd_max_threads(D)) __attribute__((amdgpu_waves_per_eu(3)))
+bounds_fwd_kernel_o3(FwdArgs a)
+{
+    fwd_block<D, DM, NORM>(a);
+}
+
+constexpr bool fwd_use_o3(int D) { return D >= 9 && D != 15; }
 
 // Persistent kernel for many independent data sets of one shape class
 // (d, monotone count, norm): every wave repeatedly takes the next work item
@@ -429,6 +455,8 @@ void launch_fwd(const FwdArgs &a, dim3 grid, dim3 block, hipStream_t s)
 {
     if constexpr (fwd_use_o4(D, NORM))
         hipLaunchKernelGGL((bounds_fwd_kernel_o4<D, DM, NORM>), grid, block, 0, s, a);
+    else if constexpr (fwd_use_o3(D))
+        hipLaunchKernelGGL((bounds_fwd_kernel_o3<D, DM, NORM>), grid, block, 0, s, a);
     else
         hipLaunchKernelGGL((bounds_fwd_kernel<D, DM, NORM>), grid, block, 0, s, a);
 }

@@ -58,11 +58,10 @@ lip_status parse_metric(const lip_metric *m, MetricInfo *out, bool allow_regiona
 struct FwdPlan {
     int R = 0;
     int tile = 64;
-    int waves = 4;
-    bool merge = false;      // workgroup merge (LIP_TILE_WG_MERGE)
+    int waves = 4;           // waves per workgroup (d <= 8: chunks merged in LDS)
     int64_t n_pad = 0, n_tiles = 0;
     int tiles_per_chunk = 0;
-    int n_chunks = 1;        // chunks launched (merge: a multiple of waves, the last may be empty)
+    int n_chunks = 1;        // chunks launched (a multiple of waves, the last ones may be empty)
     int part_chunks = 1;     // partial results per query the combine kernel reduces (1: none)
     int64_t grid = 0;
 };

@@ -11,6 +11,11 @@ namespace lip {
 
 // Queries per lane for a dimension: keeps R (D + 7) around 80-100 VGPRs.
 constexpr int rows_for_dim(int D) { return D <= 2 ? 12 : (D <= 4 ? 8 : (D <= 6 ? 6 : 4)); }
+// Largest dimension whose single-set bound kernel merges the chunks of a
+// workgroup in LDS (bounds_fwd.hpp).
+constexpr int kFwdMergeMaxDim = 8;
+// Waves per workgroup above that dimension (the kernel's launch bound).
+constexpr int kFwdPlainMaxWaves = 4;
 
 // Arguments of the fused bound kernel (see bounds_fwd.hpp).
 struct FwdArgs {
@@ -19,16 +24,16 @@ struct FwdArgs {
     int64_t n_tiles;         // n_pad / tile
     int32_t tile;            // records per argmin tile (multiple of 8)
     int32_t tiles_per_chunk;
-    int32_t n_chunks;
+    int32_t n_chunks;        // chunks launched (d <= 8: a multiple of the waves per workgroup)
     int32_t l2_filter;       // l2 with monotone coordinates: root-free filter (bounds_fwd.hpp)
-    int32_t wg_merge;        // 1: the waves of a workgroup share queries, merge in LDS
     const float *xq;         // [q][D] row-major, untransformed
     int64_t q;
     Xform xf;                // query transform (same as the staging one)
     float *g, *h_up, *h_lo;  // outputs (n_chunks == 1), any may be NULL
     int32_t *arg_up, *arg_lo;
-    float *part_v;           // [2][n_chunks][q] partial values (n_chunks > 1)
-    int32_t *part_i;         // [2][n_chunks][q] partial indices
+    float *part_v;           // [2][parts][q] partial values (parts = n_chunks / waves at
+                             // d <= 8, else n_chunks; parts > 1)
+    int32_t *part_i;         // [2][parts][q] partial indices
     unsigned long long *keys;  // [2][q] packed keys (batched plans, n_chunks > 1)
 };
 

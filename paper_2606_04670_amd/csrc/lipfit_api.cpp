@@ -124,10 +124,6 @@ lip_tile_cfg default_tile_cfg(int d, int dm, int norm, int64_t n, int64_t q)
     // the root-free l2 filter paid on the d = 4 workload (two monotone
     // coordinates) and was neutral to slower on loose bounds at d >= 8
     c.flags = (norm == LIP_L2 && dm > 0 && d <= 4) ? LIP_TILE_L2_FILTER : 0;
-    // workgroup merge of 4 chunks: as fast as the plain split of the same
-    // chunk count (1% faster on the d = 4 workload) with a quarter of its
-    // query reads and partial results
-    if (split >= c.waves) c.flags |= LIP_TILE_WG_MERGE;
     return c;
 }
 
@@ -146,17 +142,17 @@ FwdPlan make_fwd_plan(const MetricInfo &mi, int64_t n, int64_t q, const lip_tile
     p.tiles_per_chunk = (int)((p.n_tiles + split - 1) / split);
     p.n_chunks = (int)((p.n_tiles + p.tiles_per_chunk - 1) / p.tiles_per_chunk);
     const int64_t qwaves = (q + 64 * p.R - 1) / (64 * p.R);
-    p.merge = (cfg.flags & LIP_TILE_WG_MERGE) != 0;
-    if (p.merge) {
-        // one workgroup per (query block, group of `waves` chunks)
+    if (mi.d <= kFwdMergeMaxDim) {
+        // one workgroup per (query block, group of `waves` consecutive chunks)
         if (p.waves > p.n_chunks) p.waves = p.n_chunks;
         p.part_chunks = (p.n_chunks + p.waves - 1) / p.waves;
         p.n_chunks = p.part_chunks * p.waves;
         p.grid = qwaves * p.part_chunks;
     } else {
-        const int64_t qblocks = (qwaves + p.waves - 1) / p.waves;
+        // one workgroup per (`waves` query blocks, chunk), at most 4 waves
+        if (p.waves > kFwdPlainMaxWaves) p.waves = kFwdPlainMaxWaves;
         p.part_chunks = p.n_chunks;
-        p.grid = qblocks * p.n_chunks;
+        p.grid = (qwaves + p.waves - 1) / p.waves * p.n_chunks;
     }
     return p;
 }
@@ -213,7 +209,6 @@ lip_status run_bounds(const MetricInfo &mi, const float *x, const float *y, int6
     a.tiles_per_chunk = p.tiles_per_chunk;
     a.n_chunks = p.n_chunks;
     a.l2_filter = (cfg.flags & LIP_TILE_L2_FILTER) ? 1 : 0;
-    a.wg_merge = p.merge ? 1 : 0;
     a.xq = xq;
     a.q = q;
     a.xf = xf;

@@ -148,24 +148,19 @@ def test_tuning_table(L):
     assert cfg.tile % 8 == 0 and cfg.split >= 1 and cfg.waves >= 1
     bad = L.LipTileCfg(12, 1, 4, 0)
     assert lib.lip_tune_set(4, 2, 1, 0, 0, ctypes.byref(bad)) == L.LIP_E_VALUE
-    bad_flags = L.LipTileCfg(32, 1, 4, 4)
+    bad_flags = L.LipTileCfg(32, 1, 4, 2)
     assert lib.lip_tune_set(4, 2, 1, 0, 0, ctypes.byref(bad_flags)) == L.LIP_E_VALUE
-    bad_waves = L.LipTileCfg(32, 1, 9, 2)
+    bad_waves = L.LipTileCfg(32, 1, 9, 0)
     assert lib.lip_tune_set(4, 2, 1, 0, 0, ctypes.byref(bad_waves)) == L.LIP_E_VALUE
-    merge8 = L.LipTileCfg(32, 8, 8, L.LIP_TILE_WG_MERGE | L.LIP_TILE_L2_FILTER)
-    assert lib.lip_tune_set(4, 2, 1, 0, 0, ctypes.byref(merge8)) == L.LIP_OK
+    eight = L.LipTileCfg(32, 8, 8, L.LIP_TILE_L2_FILTER)
+    assert lib.lip_tune_set(4, 2, 1, 0, 0, ctypes.byref(eight)) == L.LIP_OK
     assert lib.lip_tune_set(4, 2, 1, 0, 0, None) == L.LIP_OK
-    # the default turns the l2 filter on with monotone coordinates at d <= 4
-    # only, and the workgroup merge on when the data are split in at least
-    # as many chunks as a workgroup has waves
+    # the default turns the l2 filter on with monotone coordinates at d <= 4 only
     for d, m, norm, want in ((4, 2, 2, 1), (4, 0, 2, 0), (8, 4, 2, 0), (4, 2, 1, 0), (2, 1, 2, 1)):
         lib.lip_tune_get(d, m, norm, 1000, 1000, ctypes.byref(cfg))
-        assert cfg.flags & L.LIP_TILE_L2_FILTER == want, (d, m, norm)
-        assert bool(cfg.flags & L.LIP_TILE_WG_MERGE) == (cfg.split >= cfg.waves), (d, m, norm)
+        assert cfg.flags == want, (d, m, norm)
     lib.lip_tune_get(4, 2, 2, 100000, 1000000, ctypes.byref(cfg))
-    assert (cfg.split, cfg.waves, cfg.flags) == (8, 4, L.LIP_TILE_L2_FILTER | L.LIP_TILE_WG_MERGE)
-    lib.lip_tune_get(4, 2, 2, 100000, 10_000_000, ctypes.byref(cfg))
-    assert cfg.split == 1 and cfg.flags == L.LIP_TILE_L2_FILTER
+    assert (cfg.split, cfg.waves, cfg.flags) == (8, 4, L.LIP_TILE_L2_FILTER)
     assert lib.lip_tune_set(4, 2, 1, 10, 0, ctypes.byref(bad)) == L.LIP_E_SHAPE
     # an entry for every size
     good = L.LipTileCfg(128, 2, 2, 0)

@@ -114,12 +114,14 @@ def test_tiling_and_split_do_not_change_results(lf, norm):
                          local=True)
     ref = None
     try:
-        # flags: 1 = l2 filter, 2 = workgroup merge (with 8 waves and split 5
-        # the merge runs 5 waves; split 64 with 8 waves leaves 8 partials)
+        # flags: 1 = l2 filter.  A workgroup's waves merge consecutive chunks:
+        # with 8 waves and split 5 it runs 5 waves, split 64 with 8 waves
+        # leaves 8 partials, 3 waves of split 64 leave 22 (the last group
+        # partly empty)
         for tile, split, waves, fl in [(64, 1, 4, 0), (8, 1, 1, 1), (256, 3, 2, 0), (32, 16, 4, 1),
-                                       (128, 64, 3, 1), (32, 8, 8, 2), (16, 5, 8, 3),
-                                       (8, 64, 8, 2), (32, 3, 2, 3), (128, 1, 8, 2),
-                                       (64, 16, 4, 2)]:
+                                       (128, 64, 3, 1), (32, 8, 8, 0), (16, 5, 8, 1),
+                                       (8, 64, 8, 0), (32, 3, 2, 1), (128, 1, 8, 0),
+                                       (64, 16, 1, 0)]:
             lf.tune_set(4, 2, norm, tile=tile, split=split, waves=waves, flags=fl)
             out = run(lf, p)
             if ref is None:
@@ -136,12 +138,13 @@ def test_tiling_and_split_do_not_change_results(lf, norm):
 
 
 @pytest.mark.parametrize("norm", [1, 2, 3])
-@pytest.mark.parametrize("d", [1, 2, 5, 7, 11, 16])
-def test_wg_merge_identical(lf, norm, d):
-    """The workgroup merge (LIP_TILE_WG_MERGE) gives the plain kernel's
-    values and indices at every dimension, including ties across chunks:
-    the data are 40 points repeated, so every candidate value occurs in
-    every chunk and the lowest index must win."""
+@pytest.mark.parametrize("d", [1, 2, 5, 7, 8, 9, 11, 15, 16])
+def test_chunk_merge_identical(lf, norm, d):
+    """Chunks merged in a workgroup (LDS keys, d <= 8), per-chunk partials
+    through the combine kernel and both together give the same values and
+    indices, including ties across chunks: the data are 40 points repeated,
+    so every candidate value occurs in every chunk and the lowest index must
+    win (at d >= 9 the waves take different queries instead)."""
     g = W.rng_for(1900, d, norm)
     mon = np.zeros(d, np.int8)
     mon[::2] = 1
@@ -154,8 +157,8 @@ def test_wg_merge_identical(lf, norm, d):
     dm = int(mon.sum())
     outs = []
     try:
-        for tile, split, waves, fl in [(8, 16, 4, 0), (8, 16, 8, 2), (16, 12, 4, 2), (8, 40, 8, 2)]:
-            lf.tune_set(d, dm, norm, tile=tile, split=split, waves=waves, flags=fl)
+        for tile, split, waves in [(8, 16, 1), (8, 16, 8), (16, 12, 4), (8, 40, 8), (8, 1, 4)]:
+            lf.tune_set(d, dm, norm, tile=tile, split=split, waves=waves)
             outs.append(run(lf, p))
     finally:
         lf.tune_set(d, dm, norm, clear=True)
@@ -163,7 +166,7 @@ def test_wg_merge_identical(lf, norm, d):
         for k in o:
             np.testing.assert_array_equal(o[k], outs[0][k], err_msg=k)
     assert outs[0]["arg_up"].max() < 40 and outs[0]["arg_lo"].max() < 40
-    check_bounds(p, outs[1], label=f"merge d={d} norm={norm}")
+    check_bounds(p, outs[1], label=f"chunks d={d} norm={norm}")
 
 
 @pytest.mark.parametrize("norm", [1, 2, 3])
