@@ -154,6 +154,8 @@ void orc_candidates(int d, int norm, const double *w, const signed char *mon,
  * For each requested row i (all rows when rows == NULL), over k != i:
  *   t_up(i,k) = (y_k + M_k dist_up(x^i, x^k)) - y_i    (>= 0 when consistent)
  *   t_lo(i,k) = y_i - (y_k - M_k dist_lo(x^i, x^k))    (>= 0 when consistent)
+ * evaluated in FP64 with the bound y_k +- M_k dist as one fused multiply-add
+ * (one rounding) and then the difference with y_i.
  * slack_up[r] = min_k t_up, slack_lo[r] = min_k t_lo (lowest k on ties),
  * viol_up[r] / viol_lo[r] = number of k with t < -tol.
  * Equality |y_i - y_k| = M d is consistent (the condition is "<=").
@@ -177,8 +179,8 @@ void orc_consistency(int d, int norm, const double *w, const signed char *mon,
             double du, dl;
             dist_pair(d, norm, w, mon, xi, x + k * (long)d, &du, &dl, NULL, NULL);
             double mk = m_of(Mk, M, k);
-            double tu = ((double)y[k] + mk * du) - yi;
-            double tl = yi - ((double)y[k] - mk * dl);
+            double tu = fma(mk, du, (double)y[k]) - yi;
+            double tl = yi - fma(-mk, dl, (double)y[k]);
             if (tu < su) { su = tu; pu = k; }
             if (tl < sl) { sl = tl; pl = k; }
             if (tu < -tol) ++cu;

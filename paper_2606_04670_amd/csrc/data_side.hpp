@@ -114,6 +114,19 @@ __device__ __forceinline__ double max2(double a, double b)
     asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
     return r;
 }
+// max(s, |v|) and max(s, -v), s >= 0 (same conventions).
+__device__ __forceinline__ double max_abs(double s, double v)
+{
+    double r;
+    asm("v_max_f64 %0, %1, |%2|" : "=v"(r) : "v"(s), "v"(v));
+    return r;
+}
+__device__ __forceinline__ double max_neg(double s, double v)
+{
+    double r;
+    asm("v_max_f64 %0, %1, -%2" : "=v"(r) : "v"(s), "v"(v));
+    return r;
+}
 
 // The running norm value after the first component c (FIRST) or after
 // adding one more component to s.  Starting from c instead of 0 + c
@@ -213,6 +226,58 @@ __device__ __forceinline__ void ds_dist_group(const DsArgs &A, cdouble_ptr X, in
                                               double (&su)[kDsGroup][R],
                                               double (&sl)[kDsGroup][R])
 {
+    if constexpr (NORM == 3 && MON && FM >= 0) {
+        // linf with the kinds known: a maximum is exact in any order, so the
+        // free coordinates go first into f = max |w d| (>= 0, 0 without free
+        // coordinates), shared by both distances; then, since f >= 0,
+        // max(s, w (d)_+) = max(s, w d) and max(s, w (-d)_+) = max(s, -w d)
+        // for each monotone coordinate: one maximum per free coordinate and
+        // two per monotone one instead of two and four, with the
+        // definition's values (up to the sign of a zero).
+        double f[kDsGroup][R];
+#pragma unroll
+        for (int c = 0; c < kDsGroup; ++c)
+#pragma unroll
+            for (int r = 0; r < R; ++r) f[c][r] = 0.0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            if (!((FM >> i) & 1)) continue;
+            double xc[kDsGroup];
+#pragma unroll
+            for (int c = 0; c < kDsGroup; ++c) xc[c] = X[(int64_t)i * A.npad + g0 + c];
+            const double w = A.w[i];
+#pragma unroll
+            for (int c = 0; c < kDsGroup; ++c)
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    double e = xr[r][i] - xc[c];
+                    if (HASW) e = w * e;
+                    f[c][r] = max_abs(f[c][r], e);
+                }
+        }
+#pragma unroll
+        for (int c = 0; c < kDsGroup; ++c)
+#pragma unroll
+            for (int r = 0; r < R; ++r) su[c][r] = sl[c][r] = f[c][r];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            if ((FM >> i) & 1) continue;
+            double xc[kDsGroup];
+#pragma unroll
+            for (int c = 0; c < kDsGroup; ++c) xc[c] = X[(int64_t)i * A.npad + g0 + c];
+            const double w = A.w[i];
+#pragma unroll
+            for (int c = 0; c < kDsGroup; ++c)
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    double e = xr[r][i] - xc[c];
+                    if (HASW) e = w * e;
+                    su[c][r] = max2(su[c][r], e);
+                    sl[c][r] = max_neg(sl[c][r], e);
+                }
+        }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < D; ++i) {
         double xc[kDsGroup];
@@ -293,8 +358,8 @@ __device__ __forceinline__ void cons_group(const DsArgs &A, cdouble_ptr X, int64
                 du = sqrt(du);
                 dl = MON ? sqrt(dl) : du;
             }
-            double tu = (yk[c] + mk[c] * du) - yr[r];
-            double tl = yr[r] - (yk[c] - mk[c] * dl);
+            double tu = fma(mk[c], du, yk[c]) - yr[r];
+            double tl = yr[r] - fma(-mk[c], dl, yk[c]);
             if (MASK) {
                 const int64_t k = g0 + c;
                 const bool ok = k < A.n && k != ir[r];
@@ -322,8 +387,8 @@ __device__ __forceinline__ void cons_pair(const DsArgs &A, const double (&xr)[D]
     double du, dl;
     ds_dist1<D, NORM, HASW, MON>(A, xr, k, du, dl);
     const double yk = A.X[(int64_t)D * A.npad + k], mk = A.X[(int64_t)(D + 1) * A.npad + k];
-    tu = (yk + mk * du) - yr;
-    tl = yr - (yk - mk * dl);
+    tu = fma(mk, du, yk) - yr;
+    tl = yr - fma(-mk, dl, yk);
 }
 
 template <int D, int NORM, bool HASW, bool MON, int FM = -1>
