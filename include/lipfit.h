@@ -240,7 +240,7 @@ lip_status lip_estimate_M(const lip_metric *metric, const float *x, const float 
  * Candidates are FP32 as in lip_fit_eval (k = 1 with wk = {1} gives its
  * h_up / h_lo bit for bit); the k values are a multiset, so no index rule.
  * Needs ws. */
-#define LIP_MAX_K 4
+#define LIP_MAX_K 32
 lip_status lip_fit_eval_k(const lip_metric *metric, const float *x, const float *y, int64_t n,
                           float M, const float *Mk, int32_t k, const float *wk, const float *xq,
                           int64_t q, float *g, float *h_up, float *h_lo, void *ws,

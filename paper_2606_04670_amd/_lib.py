@@ -21,7 +21,7 @@ LIP_FLAG_CHECK_FINITE = 1 << 0
 LIP_FLAG_BF16 = 1 << 1
 LIP_FLAG_DETERMINISTIC = 1 << 2
 LIP_M_GLOBAL, LIP_M_LOCAL_KNN = 0, 1
-LIP_MAX_DIM, LIP_MAX_KNN, LIP_MAX_KNOTS, LIP_MAX_K = 16, 32, 8, 4
+LIP_MAX_DIM, LIP_MAX_KNN, LIP_MAX_KNOTS, LIP_MAX_K = 16, 32, 8, 32
 LIP_MON_CASE_I, LIP_MON_CASE_II, LIP_MON_CASE_III, LIP_MON_CASE_IV = 2, 3, 4, 5
 LIP_TILE_L2_FILTER = 1
 

@@ -5,42 +5,55 @@
 //
 // Same work decomposition and pair arithmetic as the fused bound kernel
 // (pair_bounds on the staged records, queries in VGPRs, records from SGPRs).
-// Each query keeps its kTopK best values per bound in registers, sorted.  A
-// candidate enters only if it beats the current kTopK-th value; the test is
-// one compare per bound and pair, and the insertion (a min into the last slot
-// and one compare-exchange pass) runs per candidate only when some lane of
-// the wave improves one of its two lists (a wave-uniform branch: after the
-// first data, few candidates improve any list).  The k values form a multiset, so no index rule is needed; records past
-// n (the staging's padding repeats the last datum) are masked, so every datum
-// counts once.  Split chunks write their sorted lists; a merge kernel takes
-// the kTopK smallest / largest of all of them.
+// Each query keeps its KL best values per bound in registers, sorted, with
+// the list length KL the smallest of 4, 8, 16, 32 that holds k (so k <=
+// kTopKMax).  A candidate enters only if it beats the current KL-th value;
+// the test is one compare per bound and pair, and the insertion (a min into
+// the last slot and one compare-exchange pass) runs per candidate only when
+// some lane of the wave improves one of its two lists (a wave-uniform branch:
+// after the first data, few candidates improve any list; the number of
+// insertions per query grows like KL log(n / KL)).  The k values form a
+// multiset, so no index rule is needed; records past n (the staging's
+// padding repeats the last datum) are masked, so every datum counts once.
+// Split chunks write their sorted lists; a merge kernel takes the KL
+// smallest / largest of all of them.  Longer lists would leave too few
+// registers for the queries; larger k would take a threshold pass (the k-th
+// value of a subset bounds the k-th value of all data), a pass collecting
+// the candidates beyond it, and a sort per query.
 #pragma once
 
 #include "bounds_fwd.hpp"
 
 namespace lip {
 
-constexpr int kTopK = 4;
+constexpr int kTopKMax = 32;
 
-// Queries per lane: half of the fused kernel's, since each query also holds
-// its two sorted lists of kTopK values.
-constexpr int topk_rows(int D) { return rows_for_dim(D) / 2 > 0 ? rows_for_dim(D) / 2 : 1; }
+// List length for k: 4, 8, 16 or 32.
+constexpr int topk_list_len(int k) { return k <= 4 ? 4 : (k <= 8 ? 8 : (k <= 16 ? 16 : 32)); }
+
+// Queries per lane: the fused kernel's rows divided by KL / 2, at least one,
+// since each query also holds its two sorted lists of KL values.
+constexpr int topk_rows(int D, int KL)
+{
+    return rows_for_dim(D) * 2 / KL > 0 ? rows_for_dim(D) * 2 / KL : 1;
+}
 
 struct TopkArgs {
-    FwdArgs f;            // staged records, n, queries, transform, outputs g / h_up / h_lo
+    FwdArgs f;             // staged records, n, queries, transform, outputs g / h_up / h_lo
     int32_t k;
-    float wk[kTopK];      // weights, zero past k
-    int64_t chunk_recs;   // records per chunk (multiple of the group size)
-    float *part;          // [2][n_chunks][q][kTopK] sorted partial lists (n_chunks > 1)
+    float wk[kTopKMax];    // weights, zero past k
+    int64_t chunk_recs;    // records per chunk (multiple of the group size)
+    float *part;           // [2][n_chunks][q][KL] sorted partial lists (n_chunks > 1)
 };
 
 // Ascending list: the new value replaces the last slot if smaller, then one
 // compare-exchange pass from the end restores the order.
-__device__ __forceinline__ void topk_insert_up(float (&s)[kTopK], float v)
+template <int KL>
+__device__ __forceinline__ void topk_insert_up(float (&s)[KL], float v)
 {
-    s[kTopK - 1] = fminf(s[kTopK - 1], v);
+    s[KL - 1] = fminf(s[KL - 1], v);
 #pragma unroll
-    for (int j = kTopK - 1; j > 0; --j) {
+    for (int j = KL - 1; j > 0; --j) {
         const float a = fminf(s[j - 1], s[j]), b = fmaxf(s[j - 1], s[j]);
         s[j - 1] = a;
         s[j] = b;
@@ -48,22 +61,23 @@ __device__ __forceinline__ void topk_insert_up(float (&s)[kTopK], float v)
 }
 
 // Descending list, the mirror.
-__device__ __forceinline__ void topk_insert_lo(float (&s)[kTopK], float v)
+template <int KL>
+__device__ __forceinline__ void topk_insert_lo(float (&s)[KL], float v)
 {
-    s[kTopK - 1] = fmaxf(s[kTopK - 1], v);
+    s[KL - 1] = fmaxf(s[KL - 1], v);
 #pragma unroll
-    for (int j = kTopK - 1; j > 0; --j) {
+    for (int j = KL - 1; j > 0; --j) {
         const float a = fmaxf(s[j - 1], s[j]), b = fminf(s[j - 1], s[j]);
         s[j - 1] = a;
         s[j] = b;
     }
 }
 
-template <int D, int DM, int NORM>
+template <int D, int DM, int NORM, int KL>
 __global__ void __launch_bounds__(256) bounds_topk_kernel(TopkArgs A)
 {
     constexpr int S = Rec<D>::S;
-    constexpr int R = topk_rows(D);
+    constexpr int R = topk_rows(D, KL);
     constexpr int G = group_for_dim(D);
     const FwdArgs &a = A.f;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -74,7 +88,7 @@ __global__ void __launch_bounds__(256) bounds_topk_kernel(TopkArgs A)
     if (q0 >= a.q) return;
 
     const float big = opaque_inf();
-    float qv[R][D], qm[R], U[R][kTopK], L[R][kTopK];
+    float qv[R][D], qm[R], U[R][KL], L[R][KL];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         int64_t qi = q0 + r * 64 + lane;
@@ -83,7 +97,7 @@ __global__ void __launch_bounds__(256) bounds_topk_kernel(TopkArgs A)
         for (int j = 0; j < D; ++j) qv[r][j] = xf_coord(a.xf, a.xq + qi * D, j);
         qm[r] = query_mon_sum<D, DM>(qv[r]);
 #pragma unroll
-        for (int j = 0; j < kTopK; ++j) {
+        for (int j = 0; j < KL; ++j) {
             U[r][j] = __builtin_inff();
             L[r][j] = -__builtin_inff();
         }
@@ -109,9 +123,9 @@ __global__ void __launch_bounds__(256) bounds_topk_kernel(TopkArgs A)
                                          v[c * S + Rec<D>::M], v[c * S + Rec<D>::YU], big, u, l);
                 // insert only where some lane of the wave improves a list
                 // (an insertion that improves nothing leaves the list as it is)
-                if (__builtin_amdgcn_ballot_w64(u < U[r][kTopK - 1] || l > L[r][kTopK - 1]) != 0) {
-                    topk_insert_up(U[r], u);
-                    topk_insert_lo(L[r], l);
+                if (__builtin_amdgcn_ballot_w64(u < U[r][KL - 1] || l > L[r][KL - 1]) != 0) {
+                    topk_insert_up<KL>(U[r], u);
+                    topk_insert_lo<KL>(L[r], l);
                 }
             }
         }
@@ -123,7 +137,7 @@ __global__ void __launch_bounds__(256) bounds_topk_kernel(TopkArgs A)
         if (a.n_chunks == 1) {
             float hu = 0.0f, hl = 0.0f;
 #pragma unroll
-            for (int j = 0; j < kTopK; ++j) {
+            for (int j = 0; j < KL; ++j) {
                 if (j < A.k) {
                     hu = fmaf(A.wk[j], U[r][j], hu);
                     hl = fmaf(A.wk[j], L[r][j], hl);
@@ -133,10 +147,10 @@ __global__ void __launch_bounds__(256) bounds_topk_kernel(TopkArgs A)
             if (a.h_up) a.h_up[qi] = hu;
             if (a.h_lo) a.h_lo[qi] = hl;
         } else {
-            float *pu = A.part + (((int64_t)chunk * a.q + qi) * kTopK);
-            float *pl = A.part + ((((int64_t)a.n_chunks + chunk) * a.q + qi) * kTopK);
+            float *pu = A.part + (((int64_t)chunk * a.q + qi) * KL);
+            float *pl = A.part + ((((int64_t)a.n_chunks + chunk) * a.q + qi) * KL);
 #pragma unroll
-            for (int j = 0; j < kTopK; ++j) {
+            for (int j = 0; j < KL; ++j) {
                 pu[j] = U[r][j];
                 pl[j] = L[r][j];
             }
@@ -146,27 +160,27 @@ __global__ void __launch_bounds__(256) bounds_topk_kernel(TopkArgs A)
 
 typedef void (*TopkLaunch)(const TopkArgs &, dim3, dim3, hipStream_t);
 
-template <int NORM, int D, int DM>
+template <int NORM, int KL, int D, int DM>
 void launch_topk(const TopkArgs &a, dim3 g, dim3 b, hipStream_t s)
 {
-    hipLaunchKernelGGL((bounds_topk_kernel<D, DM, NORM>), g, b, 0, s, a);
+    hipLaunchKernelGGL((bounds_topk_kernel<D, DM, NORM, KL>), g, b, 0, s, a);
 }
 
-template <int NORM, int D, int... DMs>
+template <int NORM, int KL, int D, int... DMs>
 constexpr std::array<TopkLaunch, D + 1> topk_row(std::integer_sequence<int, DMs...>)
 {
-    return {{&launch_topk<NORM, D, DMs>...}};
+    return {{&launch_topk<NORM, KL, D, DMs>...}};
 }
 
-template <int NORM>
+template <int NORM, int KL>
 TopkLaunch topk_table(int d, int dm)
 {
     if (dm < 0 || dm > d) return nullptr;
     switch (d) {
-#define LIP_TK_CASE(DD)                                                                    \
-    case DD: {                                                                             \
-        constexpr auto row = topk_row<NORM, DD>(std::make_integer_sequence<int, DD + 1>{}); \
-        return row[dm];                                                                    \
+#define LIP_TK_CASE(DD)                                                                        \
+    case DD: {                                                                                 \
+        constexpr auto row = topk_row<NORM, KL, DD>(std::make_integer_sequence<int, DD + 1>{}); \
+        return row[dm];                                                                        \
     }
         LIP_TK_CASE(1) LIP_TK_CASE(2) LIP_TK_CASE(3) LIP_TK_CASE(4)
         LIP_TK_CASE(5) LIP_TK_CASE(6) LIP_TK_CASE(7) LIP_TK_CASE(8)
@@ -177,8 +191,21 @@ TopkLaunch topk_table(int d, int dm)
     }
 }
 
-TopkLaunch topk_l1(int d, int dm);
-TopkLaunch topk_l2(int d, int dm);
-TopkLaunch topk_linf(int d, int dm);
+// The kernel for list length kl (4, 8, 16, 32), else NULL.
+template <int NORM>
+TopkLaunch topk_table_kl(int d, int dm, int kl)
+{
+    switch (kl) {
+    case 4: return topk_table<NORM, 4>(d, dm);
+    case 8: return topk_table<NORM, 8>(d, dm);
+    case 16: return topk_table<NORM, 16>(d, dm);
+    case 32: return topk_table<NORM, 32>(d, dm);
+    default: return nullptr;
+    }
+}
+
+TopkLaunch topk_l1(int d, int dm, int kl);
+TopkLaunch topk_l2(int d, int dm, int kl);
+TopkLaunch topk_linf(int d, int dm, int kl);
 
 }  // namespace lip

@@ -1,9 +1,9 @@
-// Instantiation unit of the k-best bound kernel for one norm (all d and
-// monotone counts).
+// Instantiation unit of the k-best bound kernel for one norm (all d,
+// monotone counts and list lengths).
 #include "bounds_topk.hpp"
 
 namespace lip {
 
-TopkLaunch topk_linf(int d, int dm) { return topk_table<3>(d, dm); }
+TopkLaunch topk_linf(int d, int dm, int kl) { return topk_table_kl<3>(d, dm, kl); }
 
 }  // namespace lip

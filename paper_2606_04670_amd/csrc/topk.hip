@@ -8,54 +8,74 @@ namespace lip {
 
 namespace {
 
-// Merge of the chunks' sorted lists: the kTopK smallest upper and largest
+// Merge of the chunks' sorted lists: the KL smallest upper and largest
 // lower values over all chunks, then the weighted sums.
+template <int KL>
 __global__ void topk_merge_kernel(TopkArgs A)
 {
     const FwdArgs &a = A.f;
     const int64_t qi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (qi >= a.q) return;
-    float U[kTopK], L[kTopK];
-    for (int j = 0; j < kTopK; ++j) {
+    float U[KL], L[KL];
+#pragma unroll
+    for (int j = 0; j < KL; ++j) {
         U[j] = __builtin_inff();
         L[j] = -__builtin_inff();
     }
     for (int c = 0; c < a.n_chunks; ++c) {
-        const float *pu = A.part + (((int64_t)c * a.q + qi) * kTopK);
-        const float *pl = A.part + ((((int64_t)a.n_chunks + c) * a.q + qi) * kTopK);
-        for (int j = 0; j < kTopK; ++j) {
-            topk_insert_up(U, pu[j]);
-            topk_insert_lo(L, pl[j]);
+        const float *pu = A.part + (((int64_t)c * a.q + qi) * KL);
+        const float *pl = A.part + ((((int64_t)a.n_chunks + c) * a.q + qi) * KL);
+#pragma unroll
+        for (int j = 0; j < KL; ++j) {
+            topk_insert_up<KL>(U, pu[j]);
+            topk_insert_lo<KL>(L, pl[j]);
         }
     }
     float hu = 0.0f, hl = 0.0f;
-    for (int j = 0; j < A.k; ++j) {
-        hu = fmaf(A.wk[j], U[j], hu);
-        hl = fmaf(A.wk[j], L[j], hl);
+#pragma unroll
+    for (int j = 0; j < KL; ++j) {
+        if (j < A.k) {
+            hu = fmaf(A.wk[j], U[j], hu);
+            hl = fmaf(A.wk[j], L[j], hl);
+        }
     }
     if (a.g) a.g[qi] = 0.5f * (hu + hl);
     if (a.h_up) a.h_up[qi] = hu;
     if (a.h_lo) a.h_lo[qi] = hl;
 }
 
-TopkLaunch get_topk(int norm, int d, int dm)
+TopkLaunch get_topk(int norm, int d, int dm, int kl)
 {
     switch (norm) {
-    case LIP_L1: return topk_l1(d, dm);
-    case LIP_L2: return topk_l2(d, dm);
-    case LIP_LINF: return topk_linf(d, dm);
+    case LIP_L1: return topk_l1(d, dm, kl);
+    case LIP_L2: return topk_l2(d, dm, kl);
+    case LIP_LINF: return topk_linf(d, dm, kl);
     default: return nullptr;
     }
 }
 
-constexpr int kTopkMaxChunks = 16;
+void launch_topk_merge(int kl, const TopkArgs &A, hipStream_t s)
+{
+    const dim3 g((unsigned)((A.f.q + 255) / 256)), b(256);
+    switch (kl) {
+    case 4: hipLaunchKernelGGL(topk_merge_kernel<4>, g, b, 0, s, A); break;
+    case 8: hipLaunchKernelGGL(topk_merge_kernel<8>, g, b, 0, s, A); break;
+    case 16: hipLaunchKernelGGL(topk_merge_kernel<16>, g, b, 0, s, A); break;
+    default: hipLaunchKernelGGL(topk_merge_kernel<32>, g, b, 0, s, A); break;
+    }
+}
+
+// Data chunks x list length of the split partials: 16 chunks of 4-lists,
+// fewer chunks of longer lists (which also hold fewer queries per lane, so
+// the queries alone fill more of the chip).
+constexpr int kTopkMaxPartial = 64;
 
 }  // namespace
 
 size_t topk_ws_bytes(int64_t n, int64_t q, int d)
 {
     return kOriginBytes + staged_bytes(n, d) +
-           align_up((size_t)2 * kTopkMaxChunks * (size_t)q * kTopK * 4, 256) + 256;
+           align_up((size_t)2 * kTopkMaxPartial * (size_t)q * 4, 256) + 256;
 }
 
 }  // namespace lip
@@ -74,7 +94,7 @@ extern "C" lip_status lip_fit_eval_k(const lip_metric *metric, const float *x, c
     if (flags & LIP_FLAG_BF16) return LIP_E_UNSUPPORTED;
     if (flags & ~LIP_FLAG_CHECK_FINITE) return LIP_E_ARG;
     if (n <= 0 || q < 0 || n > kMaxIndex - kMaxTile || q > kMaxIndex) return LIP_E_SHAPE;
-    if (k < 1 || k > kTopK || k > n) return LIP_E_SHAPE;
+    if (k < 1 || k > kTopKMax || k > n) return LIP_E_SHAPE;
     if (!x || !y || !wk || (q > 0 && !xq)) return LIP_E_ARG;
     if (!Mk && (!(M >= 0.0f) || !__builtin_isfinite(M))) return LIP_E_VALUE;
     for (int j = 0; j < k; ++j)
@@ -88,7 +108,8 @@ extern "C" lip_status lip_fit_eval_k(const lip_metric *metric, const float *x, c
         st = check_finite(arr, cnt, 4, ws, s);
         if (st != LIP_OK) return st;
     }
-    TopkLaunch launch = get_topk(mi.norm, mi.d, mi.dm);
+    const int kl = topk_list_len(k);
+    TopkLaunch launch = get_topk(mi.norm, mi.d, mi.dm, kl);
     if (!launch) return LIP_E_UNSUPPORTED;
     const int64_t n_pad = (n + 7) / 8 * 8;
     Xform xf = mi.xf;
@@ -117,12 +138,13 @@ extern "C" lip_status lip_fit_eval_k(const lip_metric *metric, const float *x, c
     A.f.h_up = h_up;
     A.f.h_lo = h_lo;
     A.k = k;
-    for (int j = 0; j < kTopK; ++j) A.wk[j] = j < k ? wk[j] : 0.0f;
+    for (int j = 0; j < kTopKMax; ++j) A.wk[j] = j < k ? wk[j] : 0.0f;
     // data split when the queries alone do not fill the chip
-    const int R = topk_rows(mi.d);
+    const int R = topk_rows(mi.d, kl);
     const int64_t qwaves = (q + 64 * R - 1) / (64 * R);
     int nc = 1;
-    while (nc < kTopkMaxChunks && qwaves * nc < 16384 && n >= (int64_t)nc * 2 * 64) nc *= 2;
+    const int nc_max = kTopkMaxPartial / kl;
+    while (nc < nc_max && qwaves * nc < 16384 && n >= (int64_t)nc * 2 * 64) nc *= 2;
     int64_t recs = (n + nc - 1) / nc;
     recs = (recs + 7) / 8 * 8;
     A.chunk_recs = recs;
@@ -131,8 +153,6 @@ extern "C" lip_status lip_fit_eval_k(const lip_metric *metric, const float *x, c
     const unsigned grid = (unsigned)(((qwaves + 3) / 4) * A.f.n_chunks);
     launch(A, dim3(grid), dim3(256), s);
     if (hipGetLastError() != hipSuccess) return LIP_E_DEVICE;
-    if (A.f.n_chunks > 1)
-        hipLaunchKernelGGL(topk_merge_kernel, dim3((unsigned)((q + 255) / 256)), dim3(256), 0, s,
-                           A);
+    if (A.f.n_chunks > 1) launch_topk_merge(kl, A, s);
     return dev_status(hipGetLastError());
 }

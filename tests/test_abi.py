@@ -323,7 +323,7 @@ def test_fit_eval_k_validation(L):
         return lib.lip_fit_eval_k(ctypes.byref(m), FAKE, FAKE, n, 1.0, None, k, pp(w), FAKE, q,
                                   FAKE, None, None, FAKE, ws_bytes, flags, None)
     assert ev(k=0) == L.LIP_E_SHAPE
-    assert ev(k=5) == L.LIP_E_SHAPE
+    assert ev(k=L.LIP_MAX_K + 1, n=100) == L.LIP_E_SHAPE
     assert ev(n=1, k=2) == L.LIP_E_SHAPE
     assert ev(w=neg) == L.LIP_E_VALUE
     assert ev(flags=L.LIP_FLAG_BF16) == L.LIP_E_UNSUPPORTED

@@ -60,6 +60,31 @@ def test_fit_eval_k_parity(lf, norm, seed, n, q, d, mon, wk, local):
         assert ok.all(), f"{name}: max err {err.max():g} at {np.argmax(err)}"
 
 
+def _wk(k):
+    w = 1.0 / np.arange(1, k + 1)
+    return (w / w.sum()).tolist()
+
+
+# k above 4: lists of 8, 16 and 32 values, with split chunks (few queries)
+# and k = n
+BIG_K = [
+    # (seed, n, q, d, mon, k, local)
+    (11, 3000, 900, 4, [1, 0, 1, 0], 5, True),
+    (12, 2000, 700, 2, [0, 0], 8, False),
+    (13, 4097, 500, 3, [1, 0, -1], 13, True),
+    (14, 1500, 300, 8, [1, 0] * 4, 16, False),
+    (15, 2500, 400, 4, [0, 0, 0, 0], 17, True),
+    (16, 5000, 300, 16, [0, 1] * 8, 32, False),
+    (17, 32, 100, 2, [1, 0], 32, True),
+]
+
+
+@pytest.mark.parametrize("norm", [1, 2, 3])
+@pytest.mark.parametrize("seed,n,q,d,mon,k,local", BIG_K)
+def test_fit_eval_k_large_k(lf, norm, seed, n, q, d, mon, k, local):
+    test_fit_eval_k_parity(lf, norm, seed, n, q, d, mon, _wk(k), local)
+
+
 @pytest.mark.parametrize("norm", [1, 2, 3])
 def test_k1_equals_fit_eval_bitwise(lf, norm):
     p = W.random_problem(750 + norm, n=5000, q=3000, d=4, norm=norm,
