@@ -210,3 +210,55 @@ def test_prune_gradient_matches_finite_differences(norm):
         fd[i] = (oracle.smooth(x, y, ep, norm, Mk=Mk, p=1.5, mon=mon, prune=1 / 3)[0]
                  - oracle.smooth(x, y, em, norm, Mk=Mk, p=1.5, mon=mon, prune=1 / 3)[0]) / (2 * h)
     np.testing.assert_allclose(g, fd, rtol=1e-5, atol=1e-6)
+
+
+def _directional_numpy(x, mon, w, norm):
+    """All ordered pairs' directional distances (rows i, columns k) from
+    numpy broadcasting: c_up / c_lo per coordinate as in Eq. (4) and its
+    mirror (free: |d|), weighted, then the norm."""
+    diff = x[:, None, :].astype(np.float64) - x[None, :, :].astype(np.float64)
+    pos, neg = np.maximum(diff, 0.0), np.maximum(-diff, 0.0)
+    m = np.asarray(mon)[None, None, :]
+    cu = np.where(m == 0, np.abs(diff), np.where(m > 0, pos, neg)) * w
+    cl = np.where(m == 0, np.abs(diff), np.where(m > 0, neg, pos)) * w
+    f = {oracle.L1: lambda c: c.sum(-1), oracle.L2: lambda c: np.sqrt((c * c).sum(-1)),
+         oracle.LINF: lambda c: c.max(-1)}[norm]
+    return f(cu), f(cl)
+
+
+@pytest.mark.parametrize("norm", NORMS)
+@pytest.mark.parametrize("prune", [0.0, 1.0 / 3.0])
+def test_smooth_scale_brute_force(norm, prune):
+    """The error scale of Eq. (7) used by the GPU tolerances: A = sum of the
+    positive parts of a_ik and b_ik over the kept ordered pairs, row_abs[i] =
+    sum of 2 (t)_+ over the four terms that move eps_i, row_cnt[i] = number
+    of them above -tau, from an independent numpy evaluation; plus the
+    identities sum(row_abs) = 4 A and sum(row_cnt) = 2 x (terms above -tau)."""
+    x, y, rng = _data(77, 37, 3)
+    mon = np.array([1, 0, -1], np.int8)
+    w = np.array([1.0, 0.5, 2.0])
+    Mk = rng.uniform(0.3, 1.5, len(y)).astype(np.float32)
+    eps = 0.2 * rng.standard_normal(len(y))
+    tau = 0.05
+    A, ra, rc = oracle.smooth_scale(x, y, eps, norm, tau, Mk=Mk, mon=mon, w=w, prune=prune)
+    du, dl = _directional_numpy(x, mon, w, norm)
+    yd, mk = y.astype(np.float64), Mk.astype(np.float64)[None, :]
+    z = yd + eps
+    off = ~np.eye(len(y), dtype=bool)
+    keep = off.copy()
+    if prune > 0:
+        dy = yd[:, None] - yd[None, :]
+        keep &= ~((dy <= prune * mk * du) & (-dy <= prune * mk * dl))
+    dz = z[:, None] - z[None, :]
+    t = np.stack([dz - mk * du, -dz - mk * dl])           # a_ik, b_ik
+    v = np.where(keep, np.maximum(t, 0.0), 0.0)
+    above = keep & (t > -tau)
+    want_A = v.sum()
+    want_ra = 2 * v.sum(axis=(0, 2)) + 2 * v.sum(axis=(0, 1))
+    want_rc = above.sum(axis=(0, 2)) + above.sum(axis=(0, 1))
+    assert want_A > 0
+    assert A == pytest.approx(want_A, rel=1e-12)
+    np.testing.assert_allclose(ra, want_ra, rtol=1e-12, atol=1e-14)
+    np.testing.assert_array_equal(rc, want_rc)
+    assert ra.sum() == pytest.approx(4 * A, rel=1e-12)
+    assert rc.sum() == 2 * above.sum()
