@@ -182,7 +182,9 @@ lip_status lip_fit_backward(const lip_metric *metric, const float *x, const floa
  *   t_up(i,k) = (y_k + M_k dist_up(x^i, x^k)) - y_i
  *   t_lo(i,k) = y_i - (y_k - M_k dist_lo(x^i, x^k))
  * all evaluated in double precision from the FP32 inputs, in this order,
- * coordinates accumulated in index order, correctly rounded operations.
+ * coordinates accumulated in index order, the bound y_k +- M_k dist as one
+ * fused multiply-add, correctly rounded operations (an l-infinity distance,
+ * a maximum, is exact in any order).
  *   counts [2] (int64, required)  number of ordered pairs with t_up < -tol
  *                                 and with t_lo < -tol (overwritten)
  *   worst_slack [1] (FP64), worst_pair [2] (int64), optional: the smallest
