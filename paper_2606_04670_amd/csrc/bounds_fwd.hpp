@@ -84,6 +84,13 @@ __device__ __forceinline__ void eval_group(const float (&v)[group_for_dim(D) * R
     }
 }
 
+// A wave-uniform value computed by the vector unit, read into a scalar
+// register.
+__device__ __forceinline__ float uniform_f32(float v)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
 // l2 with monotone coordinates, filtered: the exact candidates need two
 // square roots per pair (v_sqrt_f32 issues at a quarter of the VALU rate and
 // takes about half of the pair's time), but few records can change a row's
@@ -97,14 +104,20 @@ __device__ __forceinline__ void eval_group(const float (&v)[group_for_dim(D) * R
 //     monotone), which is >= c_max^2 (1 - 2^-24) when c_max >= 2^-60 (no
 //     underflow); v_sqrt_f32 errs by far less than 2^-21 relative (taken as
 //     its bound), so the exact root s >= c_max (1 - 2^-20);
-//   * t = fl(c_max (1 - 2^-19) - 2^-60) is below c_max (1 - 2^-20) for
-//     c_max >= 2^-60 and negative below that, so t <= s always; fma is
-//     monotone in its middle argument for M >= 0, hence
-//     fma(M, t, y) <= fma(M, s, y) = u (and fma(-M, t', y) >= l likewise);
+//   * per record, Ms = fl(M (1 - 2^-19)) <= M (1 - 2^-19 + 2^-24) and
+//     Ms c_max <= M s; with t = max(|y| 2^-23, M 2^-58, 2^-126) (>= ulp(y),
+//     so fl(y - t) <= y - 0.49 t <= y - M 2^-60), ylo = fl(y - t) and
+//     yhi = fl(y + t): for c_max >= 2^-60, Ms c_max + ylo <= M s + y; for
+//     c_max < 2^-60 (s may be 0), Ms c_max + ylo <= M 2^-60 + y - M 2^-60 <= y;
+//     fma is monotone, hence fma(Ms, c_max, ylo) <= fma(M, s, y) = u, and
+//     fma(-Ms, c'_max, yhi) >= l likewise;
 //   * a record is skipped for a row only when every lane's bound is >= its
 //     running minimum and <= its running maximum, so its exact candidates
 //     could not have changed either (ties included: a tie leaves the running
 //     value as it is, and the attaining index comes from the re-scan).
+// The per-record values are a few VALU operations shared by all R rows (read
+// into scalar registers); per pair the filter is 4 differences, 3 maxima,
+// 2 FMA and 2 compares.
 template <int D, int DM, int R>
 __device__ __forceinline__ void eval_group_l2f(const float (&v)[group_for_dim(D) * Rec<D>::S],
                                                const float (&q)[R][D], float big,
@@ -113,13 +126,17 @@ __device__ __forceinline__ void eval_group_l2f(const float (&v)[group_for_dim(D)
     constexpr int S = Rec<D>::S;
     constexpr int kGroup = group_for_dim(D);
     constexpr int DF = D - DM;
-    const float shrink = 1.0f - 0x1p-19f, tiny = -0x1p-60f;
 #pragma unroll
     for (int g = 0; g < kGroup; ++g) {
         float xk[D];
 #pragma unroll
         for (int j = 0; j < D; ++j) xk[j] = v[g * S + j];
         const float yk = v[g * S + Rec<D>::Y], mk = v[g * S + Rec<D>::M];
+        // wave-uniform values, moved to scalar registers so that the rows
+        // share them without holding vector registers
+        const float ms = uniform_f32(mk * (1.0f - 0x1p-19f));
+        const float t = fmaxf(fmaxf(fabsf(yk) * 0x1p-23f, mk * 0x1p-58f), 0x1p-126f);
+        const float ylo = uniform_f32(yk - t), yhi = uniform_f32(yk + t);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             float f = 0.0f;
@@ -132,13 +149,13 @@ __device__ __forceinline__ void eval_group_l2f(const float (&v)[group_for_dim(D)
                 su = fmaxf(su, dl);
                 sl = fmaxf(sl, -dl);
             }
-            const float ulb = fmaf(mk, fmaf(su, shrink, tiny), yk);
-            const float lub = fmaf(-mk, fmaf(sl, shrink, tiny), yk);
+            const float ulb = fmaf(ms, su, ylo);
+            const float lub = fmaf(-ms, sl, yhi);
             if (__builtin_amdgcn_ballot_w64((ulb < hu[r]) | (lub > hl[r]))) {
                 float u, l;
                 pair_bounds<D, DM, kNormL2>(q[r], 0.0f, xk, yk, mk, yk, big, u, l);
-                hu[r] = fminf(hu[r], u);
-                hl[r] = fmaxf(hl[r], l);
+                hu[r] = __builtin_amdgcn_fmed3f(hu[r], u, -big);  // min, no canonicalisation
+                hl[r] = __builtin_amdgcn_fmed3f(hl[r], l, big);   // max
             }
         }
     }

@@ -184,8 +184,11 @@ __device__ __forceinline__ void pair_bounds(const float (&q)[D], float qm, const
 #pragma unroll
             for (int i = DF; i < D; ++i) {
                 const float dl = q[i] - xk[i];
-                const float pp = fmaxf(dl, 0.0f);
-                const float nn = fminf(dl, 0.0f);
+                // max(dl, 0) and min(dl, 0) as medians (no operand
+                // canonicalisation; the same values up to the sign of a
+                // zero, which the squares drop)
+                const float pp = __builtin_amdgcn_fmed3f(dl, 0.0f, big);
+                const float nn = __builtin_amdgcn_fmed3f(dl, 0.0f, -big);
                 a = fmaf(pp, pp, a);
                 b = fmaf(nn, nn, b);
             }
