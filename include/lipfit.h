@@ -403,6 +403,12 @@ typedef struct {
  * queries where some query could improve.  Identical results; faster when
  * few data compete for each query (default on for d <= 4). */
 #define LIP_TILE_L2_FILTER 1
+/* Visit the queries in Morton order (a sort of the queries' codes per call,
+ * in the workspace): a wave's queries are then close to each other, so the
+ * l2 filter's decisions, taken for 64 queries at a time, are coherent.
+ * Identical results (lip_bounds, lip_fit_eval; ignored by plans and by
+ * lip_fit_eval_noalloc; default on with the filter for q >= 65536). */
+#define LIP_TILE_QUERY_ORDER 2
 
 /* The configuration the next call of these sizes will use: the table's
  * entry for the size class of (n, q), else the entry set for every size,
@@ -416,8 +422,8 @@ lip_status lip_tune_get(int32_t d, int32_t n_mon, int32_t norm, int64_t n, int64
 lip_status lip_tune_set(int32_t d, int32_t n_mon, int32_t norm, int64_t n, int64_t q,
                         const lip_tile_cfg *cfg);
 /* Times every candidate (tile 16/32/64/128 x split 1..32 x 1, 2, 4 or 8
- * waves up to the split, and for l2 with monotone coordinates with and
- * without LIP_TILE_L2_FILTER) for
+ * waves up to the split, and for l2 with monotone coordinates without
+ * flags, with LIP_TILE_L2_FILTER and with it and LIP_TILE_QUERY_ORDER) for
  * this shape class on synthetic data of the given sizes (allocates and frees
  * its own device memory, blocks), stores the fastest under the size class of
  * (n, q) and returns it; with LIPFIT_TUNE_CACHE set, the whole table is then

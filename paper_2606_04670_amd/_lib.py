@@ -24,6 +24,7 @@ LIP_M_GLOBAL, LIP_M_LOCAL_KNN = 0, 1
 LIP_MAX_DIM, LIP_MAX_KNN, LIP_MAX_KNOTS, LIP_MAX_K = 16, 32, 8, 32
 LIP_MON_CASE_I, LIP_MON_CASE_II, LIP_MON_CASE_III, LIP_MON_CASE_IV = 2, 3, 4, 5
 LIP_TILE_L2_FILTER = 1
+LIP_TILE_QUERY_ORDER = 2
 
 P = ctypes.c_void_p
 i32, i64, u32, f32, f64, sz = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_float,

@@ -515,7 +515,7 @@ def tune_get(d, n_mon, norm, n, q):
 def tune_set(d, n_mon, norm, tile=None, split=None, waves=None, clear=False, n=0, q=0,
              flags=0):
     """Tile parameters for the size class of (n, q), or every size (n = q = 0);
-    flags: LIP_TILE_* bits (1: the root-free l2 filter)."""
+    flags: LIP_TILE_* bits (1: the root-free l2 filter, 2: queries in Morton order)."""
     lib = L.load()
     if clear:
         L.check("lip_tune_set", lib.lip_tune_set(d, n_mon, NORMS[norm], n, q, None))

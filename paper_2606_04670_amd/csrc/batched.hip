@@ -192,7 +192,7 @@ extern "C" lip_status lip_plan_create(lip_plan **plan, const lip_batch_desc *set
         const lip_tile_cfg cfg = tune_lookup(p.mi.d, p.mi.dm, p.mi.norm, d.n, d.q);
         p.R = rows_for_dim(p.mi.d);
         p.tile = cfg.tile;
-        p.flags = cfg.flags;
+        p.flags = cfg.flags & LIP_TILE_L2_FILTER;  // plans visit queries in index order
         p.n_pad = (d.n + p.tile - 1) / p.tile * p.tile;
         p.n_tiles = p.n_pad / p.tile;
         int64_t chunk_records = kItemPairs / (64 * p.R);
@@ -468,13 +468,16 @@ extern "C" lip_status lip_autotune(int32_t d, int32_t n_mon, int32_t norm, int64
     const int tiles[] = {16, 32, 64, 128};
     const int splits[] = {1, 2, 4, 8, 16, 32};
     const int waves[] = {1, 2, 4, 8};
-    const int n_flags = (norm == LIP_L2 && n_mon > 0) ? 2 : 1;
+    // flag sets: none; for l2 with monotone coordinates also the filter, and
+    // the filter with the query order
+    const int flag_sets[] = {0, LIP_TILE_L2_FILTER, LIP_TILE_L2_FILTER | LIP_TILE_QUERY_ORDER};
+    const int n_flags = (norm == LIP_L2 && n_mon > 0) ? 3 : 1;
     for (int fl = 0; fl < n_flags; ++fl)
     for (int t : tiles)
         for (int sp : splits)
             for (int w : waves) {
                 if (w > sp) continue;  // the same launch as w = sp
-                lip_tile_cfg c{t, sp, w, fl ? LIP_TILE_L2_FILTER : 0};
+                lip_tile_cfg c{t, sp, w, flag_sets[fl]};
                 // warm-up, then the mean of 3 runs
                 st = run_bounds(mi, x, y, n, 1.0f, nullptr, xq, q, g, nullptr, nullptr, nullptr,
                                 nullptr, ws, ws_bytes, c, s);

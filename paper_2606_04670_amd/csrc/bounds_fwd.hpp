@@ -199,6 +199,7 @@ __device__ __forceinline__ void fwd_scan(const FwdArgs &a, int chunk, int64_t q0
     for (int r = 0; r < R; ++r) {
         int64_t qi = q0 + r * 64 + lane;
         qi = qi < a.q ? qi : a.q - 1;
+        if (a.qorder) qi = (int64_t)(uint32_t)a.qorder[qi];
         const float *src = a.xq + qi * D;
 #pragma unroll
         for (int j = 0; j < D; ++j) qv[r][j] = xf_coord(a.xf, src, j);
@@ -337,11 +338,12 @@ __device__ __forceinline__ void fwd_block_plain(const FwdArgs &a)
             const int64_t qi = q0 + r * 64 + lane;
             if (qi >= a.q) continue;
             if (a.n_chunks == 1) {
-                if (a.g) a.g[qi] = 0.5f * (hu[r] + hl[r]);
-                if (a.h_up) a.h_up[qi] = hu[r];
-                if (a.h_lo) a.h_lo[qi] = hl[r];
-                if (a.arg_up) a.arg_up[qi] = au[r];
-                if (a.arg_lo) a.arg_lo[qi] = al[r];
+                const int64_t qo = a.qorder ? (int64_t)(uint32_t)a.qorder[qi] : qi;
+                if (a.g) a.g[qo] = 0.5f * (hu[r] + hl[r]);
+                if (a.h_up) a.h_up[qo] = hu[r];
+                if (a.h_lo) a.h_lo[qo] = hl[r];
+                if (a.arg_up) a.arg_up[qo] = au[r];
+                if (a.arg_lo) a.arg_lo[qo] = al[r];
             } else {
                 const int64_t o = (int64_t)chunk * a.q + qi;
                 const int64_t o2 = ((int64_t)a.n_chunks + chunk) * a.q + qi;
@@ -388,11 +390,12 @@ __device__ __forceinline__ void fwd_block_merge(const FwdArgs &a)
         int iu, il;
         decode_keys(mk[0][i], mk[1][i], vu, iu, vl, il);
         if (outer == 1) {
-            if (a.g) a.g[qi] = 0.5f * (vu + vl);
-            if (a.h_up) a.h_up[qi] = vu;
-            if (a.h_lo) a.h_lo[qi] = vl;
-            if (a.arg_up) a.arg_up[qi] = iu;
-            if (a.arg_lo) a.arg_lo[qi] = il;
+            const int64_t qo = a.qorder ? (int64_t)(uint32_t)a.qorder[qi] : qi;
+            if (a.g) a.g[qo] = 0.5f * (vu + vl);
+            if (a.h_up) a.h_up[qo] = vu;
+            if (a.h_lo) a.h_lo[qo] = vl;
+            if (a.arg_up) a.arg_up[qo] = iu;
+            if (a.arg_lo) a.arg_lo[qo] = il;
         } else {
             const int64_t o = (int64_t)oc * a.q + qi;
             const int64_t o2 = ((int64_t)outer + oc) * a.q + qi;

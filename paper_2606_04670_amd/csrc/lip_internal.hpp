@@ -35,6 +35,10 @@ struct FwdArgs {
                              // d <= 8, else n_chunks; parts > 1)
     int32_t *part_i;         // [2][parts][q] partial indices
     unsigned long long *keys;  // [2][q] packed keys (batched plans, n_chunks > 1)
+    // queries visited in this order: position p takes query (uint32)qorder[p]
+    // (sorted (Morton code << 32 | index) keys), or in index order if NULL;
+    // partials are kept by position, outputs written by query index
+    const unsigned long long *qorder;
 };
 
 // One work item of a batched plan: one wave's queries of one set against
@@ -81,6 +85,7 @@ struct CombineArgs {
     int32_t pad0;
     float *g, *h_up, *h_lo;
     int32_t *arg_up, *arg_lo;
+    const unsigned long long *qorder;  // partial position -> query index, or NULL
 };
 
 // Coordinate origin (stage.hip): the area holds origin[kMaxDim] (permuted
@@ -100,6 +105,10 @@ hipError_t launch_fill_i32(int *p, int64_t n, int v, hipStream_t s);
 // >= max(n, 1024); the caller pads with ~0) (sort.hip).
 int64_t sort_len(int64_t n);
 hipError_t launch_sort_u64(unsigned long long *keys, int64_t P, hipStream_t s);
+// Morton order of q queries [q][d] into P = sort_len(q) sorted keys; bb is
+// 2 kMaxDim words of scratch (stage.hip).
+hipError_t launch_query_order(const float *xq, int64_t q, int d, unsigned int *bb,
+                              unsigned long long *keys, int64_t P, hipStream_t s);
 
 FwdLaunchers fwd_launchers_l1(int d, int dm);
 FwdLaunchers fwd_launchers_l2(int d, int dm);

@@ -122,8 +122,12 @@ lip_tile_cfg default_tile_cfg(int d, int dm, int norm, int64_t n, int64_t q)
         split *= 2;
     c.split = split;
     // the root-free l2 filter paid on the d = 4 workload (two monotone
-    // coordinates) and was neutral to slower on loose bounds at d >= 8
-    c.flags = (norm == LIP_L2 && dm > 0 && d <= 4) ? LIP_TILE_L2_FILTER : 0;
+    // coordinates) and was neutral to slower on loose bounds at d >= 8; with
+    // it, queries in Morton order make a wave's filter decisions coherent
+    // (l2 forward 30.1 -> 26.8 ms at d = 4, Q = 1e6, sorting included; the
+    // sort is not worth it for few queries)
+    if (norm == LIP_L2 && dm > 0 && d <= 4)
+        c.flags = LIP_TILE_L2_FILTER | (q >= (int64_t(1) << 16) ? LIP_TILE_QUERY_ORDER : 0);
     return c;
 }
 
@@ -179,7 +183,8 @@ lip_status run_bounds(const MetricInfo &mi, const float *x, const float *y, int6
     const FwdPlan p = make_fwd_plan(mi, n, q, cfg);
     const size_t sb = staged_bytes(n, mi.d);
     const size_t pbytes = fwd_partial_bytes(p, q) / 2;
-    const size_t need = kOriginBytes + sb + 2 * pbytes;
+    const bool qord = (cfg.flags & LIP_TILE_QUERY_ORDER) != 0;
+    const size_t need = kOriginBytes + sb + 2 * pbytes + (qord ? query_order_bytes(q) : 0);
     if (ws_bytes < need) return LIP_E_WORKSPACE;
     FwdLauncher launch = fwd_launchers(mi.norm, mi.d, mi.dm).plain;
     if (!launch) return LIP_E_UNSUPPORTED;
@@ -222,6 +227,14 @@ lip_status run_bounds(const MetricInfo &mi, const float *x, const float *y, int6
         a.part_v = (float *)pb;
         a.part_i = (int32_t *)(pb + pbytes);
     }
+    if (qord) {
+        char *qb = (char *)ws + sb + 2 * pbytes;
+        unsigned long long *keys = (unsigned long long *)qb;
+        unsigned int *bb = (unsigned int *)(qb + align_up((size_t)sort_len(q) * 8, 256));
+        if (launch_query_order(xq, q, mi.d, bb, keys, sort_len(q), stream) != hipSuccess)
+            return LIP_E_DEVICE;
+        a.qorder = keys;
+    }
     launch(a, dim3((unsigned)p.grid), dim3(64 * p.waves), stream);
     if (hipGetLastError() != hipSuccess) return LIP_E_DEVICE;
     if (p.part_chunks > 1) {
@@ -235,6 +248,7 @@ lip_status run_bounds(const MetricInfo &mi, const float *x, const float *y, int6
         c.h_lo = h_lo;
         c.arg_up = arg_up;
         c.arg_lo = arg_lo;
+        c.qorder = a.qorder;
         if (launch_combine(c, stream) != hipSuccess) return LIP_E_DEVICE;
     }
     return LIP_OK;
@@ -270,7 +284,8 @@ size_t lip_workspace_size(int64_t n, int64_t q, int32_t d, uint32_t flags)
     if (q < 0) q = 0;
     if (d < 1) d = 1;
     if (d > kMaxDim) d = kMaxDim;
-    size_t fwd = kOriginBytes + staged_bytes(n, d) + partial_bytes(q) + bf16_extra_bytes(n, q, d);
+    size_t fwd = kOriginBytes + staged_bytes(n, d) + partial_bytes(q) + query_order_bytes(q) +
+                 bf16_extra_bytes(n, q, d);
     size_t m = fwd;
     const size_t ds = data_side_ws_bytes(n, d);
     const size_t bwd = backward_ws_bytes(n);

@@ -192,76 +192,6 @@ __global__ void steps_rec_kernel(const float *x, const float *y, const double *d
     }
 }
 
-// Spatial order of the queries: Morton code of the coordinates quantised to
-// 32 / d bits (at least 1, at most 16) inside the queries' bounding box,
-// packed as (code << 32 | index); positions q..P-1 are padding (~0).
-__device__ inline unsigned int f32_key(float v)
-{
-    const unsigned int b = __float_as_uint(v);
-    return (b >> 31) ? ~b : (b | 0x80000000u);
-}
-
-__device__ inline float f32_unkey(unsigned int k)
-{
-    return __uint_as_float((k >> 31) ? (k & 0x7FFFFFFFu) : ~k);
-}
-
-__global__ void qbox_init_kernel(unsigned int *bb, int d)
-{
-    const int j = threadIdx.x;
-    if (j < d) {
-        bb[j] = ~0u;
-        bb[kMaxDim + j] = 0u;
-    }
-}
-
-__global__ void qbox_kernel(const float *xq, int64_t q, int d, unsigned int *bb)
-{
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int j = 0; j < d; ++j) {
-        unsigned int lo = ~0u, hi = 0u;
-        for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < q; k += stride) {
-            const unsigned int key = f32_key(xq[k * d + j]);
-            lo = key < lo ? key : lo;
-            hi = key > hi ? key : hi;
-        }
-        for (int off = 32; off > 0; off >>= 1) {
-            const unsigned int a = __shfl_xor(lo, off), b = __shfl_xor(hi, off);
-            lo = a < lo ? a : lo;
-            hi = b > hi ? b : hi;
-        }
-        if ((threadIdx.x & 63) == 0) {
-            atomicMin(bb + j, lo);
-            atomicMax(bb + kMaxDim + j, hi);
-        }
-    }
-}
-
-__global__ void qmorton_kernel(const float *xq, int64_t q, int d, int64_t P, const unsigned int *bb,
-                               unsigned long long *keys)
-{
-    const int bits = 32 / d > 0 ? (32 / d < 16 ? 32 / d : 16) : 1;
-    const float cells = (float)(1u << bits);
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < P; k += stride) {
-        if (k >= q) {
-            keys[k] = ~0ull;
-            continue;
-        }
-        unsigned long long code = 0;
-        unsigned int c[kMaxDim];
-        for (int j = 0; j < d; ++j) {
-            const float lo = f32_unkey(bb[j]), hi = f32_unkey(bb[kMaxDim + j]);
-            float t = hi > lo ? (xq[k * d + j] - lo) / (hi - lo) * cells : 0.0f;
-            t = t < 0.0f ? 0.0f : (t > cells - 1.0f ? cells - 1.0f : t);  // NaN -> cells - 1
-            c[j] = (unsigned int)t;
-        }
-        for (int b = bits - 1; b >= 0; --b)
-            for (int j = 0; j < d; ++j) code = (code << 1) | ((c[j] >> b) & 1u);
-        keys[k] = (code << 32) | (unsigned int)k;
-    }
-}
-
 StepLaunch get_step_fwd(int norm, int d, int dm)
 {
     switch (norm) {
@@ -530,13 +460,7 @@ extern "C" lip_status lip_fit_eval_steps(const lip_metric *metric, const float *
     hipLaunchKernelGGL(steps_rec_kernel, dim3(grid1d(A.ds.npad)), dim3(256), 0, s, x, y,
                        steps->d1, steps->V, K, mi.d, n, A.ds.npad, A.xf,
                        (const unsigned int *)amax, rec);
-    hipLaunchKernelGGL(qbox_init_kernel, dim3(1), dim3(64), 0, s, qbb, mi.d);
-    int64_t gq = (q + 255) / 256;
-    if (gq > 1024) gq = 1024;
-    hipLaunchKernelGGL(qbox_kernel, dim3((unsigned)gq), dim3(256), 0, s, xq, q, mi.d, qbb);
-    hipLaunchKernelGGL(qmorton_kernel, dim3(grid1d(PQ)), dim3(256), 0, s, xq, q, mi.d, PQ,
-                       (const unsigned int *)qbb, qorder);
-    if (launch_sort_u64(qorder, PQ, s) != hipSuccess) return LIP_E_DEVICE;
+    if (launch_query_order(xq, q, mi.d, qbb, qorder, PQ, s) != hipSuccess) return LIP_E_DEVICE;
     const unsigned grid = (unsigned)(((qwaves + 3) / 4) * A.ds.n_chunks);
     launch(A, dim3(grid), dim3(256), s);
     if (hipGetLastError() != hipSuccess) return LIP_E_DEVICE;

@@ -64,6 +64,7 @@ extern "C" lip_status lip_fit_eval_noalloc(const lip_metric *metric, const float
     if (base > kScratchBytes) return LIP_E_SHAPE;
     if (q == 0) return LIP_OK;
     lip_tile_cfg cfg = tune_lookup(mi.d, mi.dm, mi.norm, n, q);
+    cfg.flags &= ~LIP_TILE_QUERY_ORDER;  // its keys would need scratch of their own
     for (;;) {
         const size_t part = fwd_partial_bytes(make_fwd_plan(mi, n, q, cfg), q);
         if (base + part <= kScratchBytes || cfg.split <= 1) break;

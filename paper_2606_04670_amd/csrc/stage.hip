@@ -132,11 +132,12 @@ __global__ void combine_kernel(CombineArgs a)
                 il = a.part_i[((int64_t)a.n_chunks + c) * a.q + j];
             }
         }
-        if (a.g) a.g[j] = 0.5f * (bu + bl);
-        if (a.h_up) a.h_up[j] = bu;
-        if (a.h_lo) a.h_lo[j] = bl;
-        if (a.arg_up) a.arg_up[j] = iu;
-        if (a.arg_lo) a.arg_lo[j] = il;
+        const int64_t o = a.qorder ? (int64_t)(uint32_t)a.qorder[j] : j;
+        if (a.g) a.g[o] = 0.5f * (bu + bl);
+        if (a.h_up) a.h_up[o] = bu;
+        if (a.h_lo) a.h_lo[o] = bl;
+        if (a.arg_up) a.arg_up[o] = iu;
+        if (a.arg_lo) a.arg_lo[o] = il;
     }
 }
 
@@ -204,6 +205,95 @@ hipError_t launch_combine(const CombineArgs &a, hipStream_t s)
     const int block = 256;
     hipLaunchKernelGGL(combine_kernel, dim3(grid_for(a.q, block)), dim3(block), 0, s, a);
     return hipGetLastError();
+}
+
+// Spatial order of the queries: Morton code of the coordinates quantised to
+// 32 / d bits (at least 1, at most 16) inside the queries' bounding box,
+// packed as (code << 32 | index); positions q..P-1 are padding (~0).  Used
+// by kernels whose waves do better on spatially close queries (the filtered
+// l2 forward, the step-function forward); results do not depend on it.
+__device__ inline unsigned int f32_key(float v)
+{
+    const unsigned int b = __float_as_uint(v);
+    return (b >> 31) ? ~b : (b | 0x80000000u);
+}
+
+__device__ inline float f32_unkey(unsigned int k)
+{
+    return __uint_as_float((k >> 31) ? (k & 0x7FFFFFFFu) : ~k);
+}
+
+__global__ void qbox_init_kernel(unsigned int *bb, int d)
+{
+    const int j = threadIdx.x;
+    if (j < d) {
+        bb[j] = ~0u;
+        bb[kMaxDim + j] = 0u;
+    }
+}
+
+__global__ void qbox_kernel(const float *xq, int64_t q, int d, unsigned int *bb)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int j = 0; j < d; ++j) {
+        unsigned int lo = ~0u, hi = 0u;
+        for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < q; k += stride) {
+            const unsigned int key = f32_key(xq[k * d + j]);
+            lo = key < lo ? key : lo;
+            hi = key > hi ? key : hi;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const unsigned int a = __shfl_xor(lo, off), b = __shfl_xor(hi, off);
+            lo = a < lo ? a : lo;
+            hi = b > hi ? b : hi;
+        }
+        if ((threadIdx.x & 63) == 0) {
+            atomicMin(bb + j, lo);
+            atomicMax(bb + kMaxDim + j, hi);
+        }
+    }
+}
+
+__global__ void qmorton_kernel(const float *xq, int64_t q, int d, int64_t P, const unsigned int *bb,
+                               unsigned long long *keys)
+{
+    const int bits = 32 / d > 0 ? (32 / d < 16 ? 32 / d : 16) : 1;
+    const float cells = (float)(1u << bits);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < P; k += stride) {
+        if (k >= q) {
+            keys[k] = ~0ull;
+            continue;
+        }
+        unsigned long long code = 0;
+        unsigned int c[kMaxDim];
+        for (int j = 0; j < d; ++j) {
+            const float lo = f32_unkey(bb[j]), hi = f32_unkey(bb[kMaxDim + j]);
+            float t = hi > lo ? (xq[k * d + j] - lo) / (hi - lo) * cells : 0.0f;
+            t = t < 0.0f ? 0.0f : (t > cells - 1.0f ? cells - 1.0f : t);  // NaN -> cells - 1
+            c[j] = (unsigned int)t;
+        }
+        for (int b = bits - 1; b >= 0; --b)
+            for (int j = 0; j < d; ++j) code = (code << 1) | ((c[j] >> b) & 1u);
+        keys[k] = (code << 32) | (unsigned int)k;
+    }
+}
+
+hipError_t launch_query_order(const float *xq, int64_t q, int d, unsigned int *bb,
+                              unsigned long long *keys, int64_t P, hipStream_t s)
+{
+    hipLaunchKernelGGL(qbox_init_kernel, dim3(1), dim3(64), 0, s, bb, d);
+    int64_t gq = (q + 255) / 256;
+    if (gq > 1024) gq = 1024;
+    if (gq < 1) gq = 1;
+    hipLaunchKernelGGL(qbox_kernel, dim3((unsigned)gq), dim3(256), 0, s, xq, q, d, bb);
+    int64_t gp = (P + 255) / 256;
+    if (gp > 65535) gp = 65535;
+    hipLaunchKernelGGL(qmorton_kernel, dim3((unsigned)gp), dim3(256), 0, s, xq, q, d, P,
+                       (const unsigned int *)bb, keys);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_sort_u64(keys, P, s);
 }
 
 hipError_t launch_nonfinite(const float *v, int64_t n, int *flag, hipStream_t s)

@@ -1,5 +1,5 @@
 // Tuning table of the bound kernels' runtime parameters (argmin tile, data
-// split, waves per workgroup, the l2 filter flag): lookup, lip_tune_get / lip_tune_set and
+// split, waves per workgroup, the l2 filter and query order flags): lookup, lip_tune_get / lip_tune_set and
 // the JSON cache (lip_tune_save / lip_tune_load, LIPFIT_TUNE_CACHE).
 //
 // Key: (d, number of monotone coordinates, norm, size class of n, size class
@@ -47,7 +47,7 @@ bool cfg_valid(const lip_tile_cfg &c)
 {
     return c.tile >= 8 && c.tile <= kMaxTile && c.tile % 8 == 0 && c.split >= 1 &&
            c.split <= kMaxChunks && c.waves >= 1 && c.waves <= kMaxFwdWaves &&
-           (c.flags & ~LIP_TILE_L2_FILTER) == 0;
+           (c.flags & ~(LIP_TILE_L2_FILTER | LIP_TILE_QUERY_ORDER)) == 0;
 }
 
 // Architecture name of the current device without feature suffixes

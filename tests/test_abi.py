@@ -148,7 +148,7 @@ def test_tuning_table(L):
     assert cfg.tile % 8 == 0 and cfg.split >= 1 and cfg.waves >= 1
     bad = L.LipTileCfg(12, 1, 4, 0)
     assert lib.lip_tune_set(4, 2, 1, 0, 0, ctypes.byref(bad)) == L.LIP_E_VALUE
-    bad_flags = L.LipTileCfg(32, 1, 4, 2)
+    bad_flags = L.LipTileCfg(32, 1, 4, 4)
     assert lib.lip_tune_set(4, 2, 1, 0, 0, ctypes.byref(bad_flags)) == L.LIP_E_VALUE
     bad_waves = L.LipTileCfg(32, 1, 9, 0)
     assert lib.lip_tune_set(4, 2, 1, 0, 0, ctypes.byref(bad_waves)) == L.LIP_E_VALUE
@@ -160,7 +160,8 @@ def test_tuning_table(L):
         lib.lip_tune_get(d, m, norm, 1000, 1000, ctypes.byref(cfg))
         assert cfg.flags == want, (d, m, norm)
     lib.lip_tune_get(4, 2, 2, 100000, 1000000, ctypes.byref(cfg))
-    assert (cfg.split, cfg.waves, cfg.flags) == (8, 4, L.LIP_TILE_L2_FILTER)
+    assert (cfg.split, cfg.waves, cfg.flags) == (8, 4,
+                                                 L.LIP_TILE_L2_FILTER | L.LIP_TILE_QUERY_ORDER)
     assert lib.lip_tune_set(4, 2, 1, 10, 0, ctypes.byref(bad)) == L.LIP_E_SHAPE
     # an entry for every size
     good = L.LipTileCfg(128, 2, 2, 0)

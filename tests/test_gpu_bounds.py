@@ -114,14 +114,16 @@ def test_tiling_and_split_do_not_change_results(lf, norm):
                          local=True)
     ref = None
     try:
-        # flags: 1 = l2 filter.  A workgroup's waves merge consecutive chunks:
+        # flags: 1 = l2 filter, 2 = queries in Morton order.  A workgroup's
+        # waves merge consecutive chunks:
         # with 8 waves and split 5 it runs 5 waves, split 64 with 8 waves
         # leaves 8 partials, 3 waves of split 64 leave 22 (the last group
         # partly empty)
         for tile, split, waves, fl in [(64, 1, 4, 0), (8, 1, 1, 1), (256, 3, 2, 0), (32, 16, 4, 1),
                                        (128, 64, 3, 1), (32, 8, 8, 0), (16, 5, 8, 1),
                                        (8, 64, 8, 0), (32, 3, 2, 1), (128, 1, 8, 0),
-                                       (64, 16, 1, 0)]:
+                                       (64, 16, 1, 0), (32, 8, 4, 3), (16, 1, 4, 2),
+                                       (64, 64, 8, 3)]:
             lf.tune_set(4, 2, norm, tile=tile, split=split, waves=waves, flags=fl)
             out = run(lf, p)
             if ref is None:
@@ -266,8 +268,10 @@ def test_l2_filter_identical(lf, d, mon, local, weighted):
                        p.Mk, (p.xq.astype(np.float64) + shift).astype(np.float32), 2, mon, p.w)
         off = _with_cfg(lf, ps, d, dm, 0)
         on = _with_cfg(lf, ps, d, dm, 1)
+        ordered = _with_cfg(lf, ps, d, dm, 3)
         for k in off:
             np.testing.assert_array_equal(on[k], off[k], err_msg=f"{k} shift={shift}")
+            np.testing.assert_array_equal(ordered[k], off[k], err_msg=f"{k} ordered shift={shift}")
         check_bounds(ps, on, label=f"filtered d={d} shift={shift}")
 
 
