@@ -199,7 +199,6 @@ __device__ __forceinline__ void fwd_scan(const FwdArgs &a, int chunk, int64_t q0
     for (int r = 0; r < R; ++r) {
         int64_t qi = q0 + r * 64 + lane;
         qi = qi < a.q ? qi : a.q - 1;
-        if (a.qorder) qi = (int64_t)(uint32_t)a.qorder[qi];
         const float *src = a.xq + qi * D;
 #pragma unroll
         for (int j = 0; j < D; ++j) qv[r][j] = xf_coord(a.xf, src, j);

@@ -66,10 +66,12 @@ struct FwdPlan {
     int64_t grid = 0;
 };
 
-// Bytes of the query order of the bound path (sorted keys + box scratch).
-inline size_t query_order_bytes(int64_t q)
+// Bytes of the query order of the bound path (sorted keys, box scratch and
+// the queries in that order).
+inline size_t query_order_bytes(int64_t q, int d)
 {
-    return align_up((size_t)sort_len(q > 0 ? q : 1) * 8, 256) + 256;
+    return align_up((size_t)sort_len(q > 0 ? q : 1) * 8, 256) + 256 +
+           align_up((size_t)(q > 0 ? q : 1) * (size_t)d * 4, 256);
 }
 
 // Bytes of the split partials of a plan (values and indices of both bounds).

@@ -35,9 +35,10 @@ struct FwdArgs {
                              // d <= 8, else n_chunks; parts > 1)
     int32_t *part_i;         // [2][parts][q] partial indices
     unsigned long long *keys;  // [2][q] packed keys (batched plans, n_chunks > 1)
-    // queries visited in this order: position p takes query (uint32)qorder[p]
-    // (sorted (Morton code << 32 | index) keys), or in index order if NULL;
-    // partials are kept by position, outputs written by query index
+    // query order: xq holds the queries permuted, position p being query
+    // (uint32)qorder[p] (sorted (Morton code << 32 | index) keys); partials
+    // are kept by position, outputs written by query index.  NULL: xq in
+    // index order.
     const unsigned long long *qorder;
 };
 
@@ -109,6 +110,9 @@ hipError_t launch_sort_u64(unsigned long long *keys, int64_t P, hipStream_t s);
 // 2 kMaxDim words of scratch (stage.hip).
 hipError_t launch_query_order(const float *xq, int64_t q, int d, unsigned int *bb,
                               unsigned long long *keys, int64_t P, hipStream_t s);
+// out[p] = xq[(uint32)keys[p]] for p < q (rows of d floats).
+hipError_t launch_query_gather(const float *xq, int64_t q, int d, const unsigned long long *keys,
+                               float *out, hipStream_t s);
 
 FwdLaunchers fwd_launchers_l1(int d, int dm);
 FwdLaunchers fwd_launchers_l2(int d, int dm);

@@ -184,7 +184,7 @@ lip_status run_bounds(const MetricInfo &mi, const float *x, const float *y, int6
     const size_t sb = staged_bytes(n, mi.d);
     const size_t pbytes = fwd_partial_bytes(p, q) / 2;
     const bool qord = (cfg.flags & LIP_TILE_QUERY_ORDER) != 0;
-    const size_t need = kOriginBytes + sb + 2 * pbytes + (qord ? query_order_bytes(q) : 0);
+    const size_t need = kOriginBytes + sb + 2 * pbytes + (qord ? query_order_bytes(q, mi.d) : 0);
     if (ws_bytes < need) return LIP_E_WORKSPACE;
     FwdLauncher launch = fwd_launchers(mi.norm, mi.d, mi.dm).plain;
     if (!launch) return LIP_E_UNSUPPORTED;
@@ -231,8 +231,11 @@ lip_status run_bounds(const MetricInfo &mi, const float *x, const float *y, int6
         char *qb = (char *)ws + sb + 2 * pbytes;
         unsigned long long *keys = (unsigned long long *)qb;
         unsigned int *bb = (unsigned int *)(qb + align_up((size_t)sort_len(q) * 8, 256));
-        if (launch_query_order(xq, q, mi.d, bb, keys, sort_len(q), stream) != hipSuccess)
+        float *xs = (float *)((char *)bb + 256);
+        if (launch_query_order(xq, q, mi.d, bb, keys, sort_len(q), stream) != hipSuccess ||
+            launch_query_gather(xq, q, mi.d, keys, xs, stream) != hipSuccess)
             return LIP_E_DEVICE;
+        a.xq = xs;
         a.qorder = keys;
     }
     launch(a, dim3((unsigned)p.grid), dim3(64 * p.waves), stream);
@@ -284,7 +287,7 @@ size_t lip_workspace_size(int64_t n, int64_t q, int32_t d, uint32_t flags)
     if (q < 0) q = 0;
     if (d < 1) d = 1;
     if (d > kMaxDim) d = kMaxDim;
-    size_t fwd = kOriginBytes + staged_bytes(n, d) + partial_bytes(q) + query_order_bytes(q) +
+    size_t fwd = kOriginBytes + staged_bytes(n, d) + partial_bytes(q) + query_order_bytes(q, d) +
                  bf16_extra_bytes(n, q, d);
     size_t m = fwd;
     const size_t ds = data_side_ws_bytes(n, d);

@@ -279,6 +279,28 @@ __global__ void qmorton_kernel(const float *xq, int64_t q, int d, int64_t P, con
     }
 }
 
+// Rows of the queries in their visiting order (one thread per float).
+__global__ void query_gather_kernel(const float *xq, int64_t q, int d,
+                                    const unsigned long long *keys, float *out)
+{
+    const int64_t total = q * d;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+        const int64_t p = e / d, j = e - p * d;
+        out[e] = xq[(int64_t)(uint32_t)keys[p] * d + j];
+    }
+}
+
+hipError_t launch_query_gather(const float *xq, int64_t q, int d, const unsigned long long *keys,
+                               float *out, hipStream_t s)
+{
+    int64_t g = (q * d + 255) / 256;
+    if (g > 65535) g = 65535;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(query_gather_kernel, dim3((unsigned)g), dim3(256), 0, s, xq, q, d, keys, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_query_order(const float *xq, int64_t q, int d, unsigned int *bb,
                               unsigned long long *keys, int64_t P, hipStream_t s)
 {
