@@ -937,6 +937,53 @@ template <int D, int NORM, bool HASW, bool MON, int FM>
 __device__ __forceinline__ void c32_dist(const DsArgs &A, const float (&xr)[D], const float *xc,
                                          float &du, float &dl)
 {
+    if constexpr (MON && FM >= 0) {
+        // kinds known: the free coordinates first, into the part shared by
+        // both sums (any order is within the error bound E), then the
+        // monotone ones
+        float f = 0.0f;
+        bool first = true;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            if (!((FM >> j) & 1)) continue;
+            float c = fabsf(xr[j] - xc[j]);
+            if (HASW) c *= (float)A.w[j];
+            if (NORM == 1) f = first ? c : f + c;
+            else if (NORM == 2) f = first ? c * c : fmaf(c, c, f);
+            else f = first ? c : fmaxf(f, c);
+            first = false;
+        }
+        float su = f, sl = f;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            if ((FM >> j) & 1) continue;
+            const float d = xr[j] - xc[j];
+            float cu = fmaxf(d, 0.0f), cl = fmaxf(-d, 0.0f);
+            if (HASW) {
+                const float wj = (float)A.w[j];
+                cu *= wj;
+                cl *= wj;
+            }
+            if (NORM == 1) {
+                su = first ? cu : su + cu;
+                sl = first ? cl : sl + cl;
+            } else if (NORM == 2) {
+                su = first ? cu * cu : fmaf(cu, cu, su);
+                sl = first ? cl * cl : fmaf(cl, cl, sl);
+            } else {
+                su = first ? cu : fmaxf(su, cu);
+                sl = first ? cl : fmaxf(sl, cl);
+            }
+            first = false;
+        }
+        if (NORM == 2) {
+            su = __builtin_amdgcn_sqrtf(su);
+            sl = __builtin_amdgcn_sqrtf(sl);
+        }
+        du = su;
+        dl = sl;
+        return;
+    }
     float su = 0.0f, sl = 0.0f;
 #pragma unroll
     for (int j = 0; j < D; ++j) {
@@ -1015,10 +1062,14 @@ __global__ void __launch_bounds__(256) consistency32_kernel(DsArgs A)
     unsigned int xu = 0, xl = 0;        // violations decided in FP64 (per lane)
     const cfloat_ptr C = as_const(A.c32);
 
+    // Per (column, row) the predicates are lane masks (one vector compare
+    // each, the logic on the scalar unit): certain violations are counted
+    // at once; au / al mark the ambiguous lanes, eu / el the lanes that need
+    // the FP64 evaluation (ambiguous, or within E of the running minimum).
     auto visit = [&](int64_t g, const float (&v)[G * S], auto mask_tag) {
         constexpr bool MASK = decltype(mask_tag)::value;
-        bool any = false;
-        bool eu[G][R], el[G][R], au[G][R], al[G][R];
+        unsigned long long any = 0;
+        unsigned long long eu[G][R], el[G][R], au[G][R], al[G][R];
 #pragma unroll
         for (int c = 0; c < G; ++c) {
             const float yk = v[c * S + D], mk = v[c * S + D + 1];
@@ -1028,32 +1079,34 @@ __global__ void __launch_bounds__(256) consistency32_kernel(DsArgs A)
                 c32_dist<D, NORM, HASW, MON, FM>(A, xr[r], v + c * S, du, dl);
                 const float tu = fmaf(mk, du, yk) - yr[r];
                 const float tl = yr[r] - fmaf(-mk, dl, yk);
-                bool ok = valid[r];
-                if (MASK) ok = ok && (g + c) < A.n && (int)(g + c) != ir[r];
-                const bool su = tu < vlo, sl = tl < vlo;  // violations for certain
-                au[c][r] = ok && !su && !(tu >= vhi);   // ambiguous
-                al[c][r] = ok && !sl && !(tl >= vhi);
-                bool okm = true;
-                if (MASK) okm = (g + c) < A.n && (int)(g + c) != ir[r];
-                eu[c][r] = au[c][r] || (okm && !(tu > umin[r]));
-                el[c][r] = al[c][r] || (okm && !(tl > lmin[r]));
+                // okm: the pair exists (column inside the data, not the
+                // row's own); ok: also the row exists
+                unsigned long long okm = ~0ull, ok = vmask[r];
                 if (MASK) {
-                    cu += __popcll(__ballot(ok && su));
-                    cl += __popcll(__ballot(ok && sl));
-                } else {
-                    // valid rows through the wave-uniform mask (scalar work)
-                    cu += __popcll(__ballot(su) & vmask[r]);
-                    cl += __popcll(__ballot(sl) & vmask[r]);
+                    okm = __builtin_amdgcn_ballot_w64((g + c) < A.n && (int)(g + c) != ir[r]);
+                    ok &= okm;
                 }
-                any = any || eu[c][r] || el[c][r];
+                const unsigned long long su = __builtin_amdgcn_ballot_w64(tu < vlo);
+                const unsigned long long sl = __builtin_amdgcn_ballot_w64(tl < vlo);
+                const unsigned long long nu = __builtin_amdgcn_ballot_w64(tu >= vhi);
+                const unsigned long long nl = __builtin_amdgcn_ballot_w64(tl >= vhi);
+                cu += __popcll(su & ok);  // violations for certain
+                cl += __popcll(sl & ok);
+                au[c][r] = ok & ~su & ~nu;  // ambiguous
+                al[c][r] = ok & ~sl & ~nl;
+                eu[c][r] = au[c][r] | (okm & __builtin_amdgcn_ballot_w64(!(tu > umin[r])));
+                el[c][r] = al[c][r] | (okm & __builtin_amdgcn_ballot_w64(!(tl > lmin[r])));
+                any |= eu[c][r] | el[c][r];
             }
         }
-        if (__builtin_amdgcn_ballot_w64(any) == 0) return;
+        if (any == 0) return;
 #pragma unroll
         for (int c = 0; c < G; ++c)
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                if (!(eu[c][r] || el[c][r])) continue;
+                if ((eu[c][r] | el[c][r]) == 0) continue;  // wave-uniform
+                const unsigned long long bit = 1ull << lane;
+                if (!((eu[c][r] | el[c][r]) & bit)) continue;
                 const int64_t k = g + c;
                 // the FP64 row values are the FP32 inputs widened (exact),
                 // formed here instead of being held for the whole scan
@@ -1062,14 +1115,14 @@ __global__ void __launch_bounds__(256) consistency32_kernel(DsArgs A)
                 for (int j = 0; j < D; ++j) xd[j] = (double)xr[r][j];
                 double tu, tl;
                 cons_pair<D, NORM, HASW, MON>(A, xd, (double)yr[r], k, tu, tl);
-                if (au[c][r] && tu < -A.tol) ++xu;
-                if (al[c][r] && tl < -A.tol) ++xl;
-                if (eu[c][r] && tu < bu[r]) {
+                if ((au[c][r] & bit) && tu < -A.tol) ++xu;
+                if ((al[c][r] & bit) && tl < -A.tol) ++xl;
+                if ((eu[c][r] & bit) && tu < bu[r]) {
                     bu[r] = tu;
                     pu[r] = (int)k;
                     umin[r] = f32_up(tu + E);
                 }
-                if (el[c][r] && tl < bl[r]) {
+                if ((el[c][r] & bit) && tl < bl[r]) {
                     bl[r] = tl;
                     pl[r] = (int)k;
                     lmin[r] = f32_up(tl + E);
@@ -1082,7 +1135,13 @@ __global__ void __launch_bounds__(256) consistency32_kernel(DsArgs A)
     };
     // Groups that overlap the end of the data or this wave's own rows check
     // bounds and the diagonal per pair.
-    auto masked = [&](int64_t g) { return g + G > A.n || (g < w.r1 && g + G > w.r0); };
+    // (column indices fit in 32 bits: n < 2^31; 32-bit compares stay on the
+    // scalar unit)
+    const int32_t n32 = (int32_t)A.n, r0 = (int32_t)w.r0, r1 = (int32_t)w.r1;
+    auto masked = [&](int64_t g) {
+        const int32_t g32 = (int32_t)g;
+        return g32 > n32 - G || (g32 < r1 && g32 > r0 - G);
+    };
     float va[G * S], vb[G * S];
     int64_t g = w.c0;
     if (g < w.c1) load(g, va);
