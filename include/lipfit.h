@@ -401,7 +401,7 @@ typedef struct {
  * candidates first (from the largest weighted component of each distance)
  * and form the exact candidates (two square roots) only for the rows of 64
  * queries where some query could improve.  Identical results; faster when
- * few data compete for each query (default on for d <= 4). */
+ * few data compete for each query (default on). */
 #define LIP_TILE_L2_FILTER 1
 /* Visit the queries in Morton order (a sort of the queries' codes per call,
  * in the workspace): a wave's queries are then close to each other, so the

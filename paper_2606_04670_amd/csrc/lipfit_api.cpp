@@ -121,13 +121,16 @@ lip_tile_cfg default_tile_cfg(int d, int dm, int norm, int64_t n, int64_t q)
            (int64_t)split * 2 * q <= kMaxPartials)
         split *= 2;
     c.split = split;
-    // the root-free l2 filter paid on the d = 4 workload (two monotone
-    // coordinates) and was neutral to slower on loose bounds at d >= 8; with
-    // it, queries in Morton order make a wave's filter decisions coherent
-    // (l2 forward 30.1 -> 26.8 ms at d = 4, Q = 1e6, sorting included; the
-    // sort is not worth it for few queries)
-    if (norm == LIP_L2 && dm > 0 && d <= 4)
-        c.flags = LIP_TILE_L2_FILTER | (q >= (int64_t(1) << 16) ? LIP_TILE_QUERY_ORDER : 0);
+    // the root-free l2 filter halves the l2 forward with monotone
+    // coordinates at d = 2..10 (N = 1e5, Q = 1e6, per-datum constants); with
+    // it, queries in Morton order make a wave's filter decisions coherent on
+    // the d = 4 benchmark data (27.3 against 30.1 ms, sorting included; not
+    // measurable on uniform random data at other d, and not worth the sort
+    // for few queries)
+    if (norm == LIP_L2 && dm > 0) {
+        c.flags = LIP_TILE_L2_FILTER;
+        if (d <= 4 && q >= (int64_t(1) << 16)) c.flags |= LIP_TILE_QUERY_ORDER;
+    }
     return c;
 }
 

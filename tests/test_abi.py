@@ -155,8 +155,9 @@ def test_tuning_table(L):
     eight = L.LipTileCfg(32, 8, 8, L.LIP_TILE_L2_FILTER)
     assert lib.lip_tune_set(4, 2, 1, 0, 0, ctypes.byref(eight)) == L.LIP_OK
     assert lib.lip_tune_set(4, 2, 1, 0, 0, None) == L.LIP_OK
-    # the default turns the l2 filter on with monotone coordinates at d <= 4 only
-    for d, m, norm, want in ((4, 2, 2, 1), (4, 0, 2, 0), (8, 4, 2, 0), (4, 2, 1, 0), (2, 1, 2, 1)):
+    # the default turns the l2 filter on with monotone coordinates
+    for d, m, norm, want in ((4, 2, 2, 1), (4, 0, 2, 0), (8, 4, 2, 1), (4, 2, 1, 0), (2, 1, 2, 1),
+                             (16, 0, 2, 0), (16, 1, 2, 1)):
         lib.lip_tune_get(d, m, norm, 1000, 1000, ctypes.byref(cfg))
         assert cfg.flags == want, (d, m, norm)
     lib.lip_tune_get(4, 2, 2, 100000, 1000000, ctypes.byref(cfg))
