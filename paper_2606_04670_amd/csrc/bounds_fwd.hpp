@@ -91,7 +91,8 @@ __device__ __forceinline__ float uniform_f32(float v)
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
-// l2 with monotone coordinates, filtered: the exact candidates need two
+// l2, filtered (with monotone coordinates, or without them: then both
+// distances are the symmetric one): the exact candidates need one or two
 // square roots per pair (v_sqrt_f32 issues at a quarter of the VALU rate and
 // takes about half of the pair's time), but few records can change a row's
 // running bounds.  Each pair first gets root-free bounds of its candidates
@@ -161,15 +162,15 @@ __device__ __forceinline__ void eval_group_l2f(const float (&v)[group_for_dim(D)
     }
 }
 
-// One group of records for all R rows of a lane: filtered (l2 with monotone
-// coordinates, when the launch asks for it) or plain.
+// One group of records for all R rows of a lane: filtered (l2, when the
+// launch asks for it) or plain.
 template <int D, int DM, int NORM, int R>
 __device__ __forceinline__ void eval_group_rows(const FwdArgs &a,
                                                 const float (&v)[group_for_dim(D) * Rec<D>::S],
                                                 const float (&qv)[R][D], const float (&qm)[R],
                                                 float big, float (&hu)[R], float (&hl)[R])
 {
-    if constexpr (NORM == kNormL2 && DM > 0) {
+    if constexpr (NORM == kNormL2) {
         if (a.l2_filter) {
             eval_group_l2f<D, DM, R>(v, qv, big, hu, hl);
             return;
