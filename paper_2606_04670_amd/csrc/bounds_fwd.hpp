@@ -119,6 +119,38 @@ __device__ __forceinline__ float uniform_f32(float v)
 // The per-record values are a few VALU operations shared by all R rows (read
 // into scalar registers); per pair the filter is 4 differences, 3 maxima,
 // 2 FMA and 2 compares.
+// Per-record constants of the filter (wave-uniform, moved to scalar
+// registers so that the rows share them without holding vector registers).
+struct L2fRec {
+    float ms, ylo, yhi;
+};
+__device__ __forceinline__ L2fRec l2f_record(float yk, float mk)
+{
+    const float t = fmaxf(fmaxf(fabsf(yk) * 0x1p-23f, mk * 0x1p-58f), 0x1p-126f);
+    return L2fRec{uniform_f32(mk * (1.0f - 0x1p-19f)), uniform_f32(yk - t), uniform_f32(yk + t)};
+}
+
+// Root-free bounds ulb <= u and lub >= l of one pair (the first DF = D - DM
+// coordinates free, the rest increasing).
+template <int D, int DM>
+__device__ __forceinline__ void l2f_bounds(const float (&q)[D], const float (&xk)[D],
+                                           const L2fRec &c, float &ulb, float &lub)
+{
+    constexpr int DF = D - DM;
+    float f = 0.0f;
+#pragma unroll
+    for (int i = 0; i < DF; ++i) f = fmaxf(f, fabsf(q[i] - xk[i]));
+    float su = f, sl = f;
+#pragma unroll
+    for (int i = DF; i < D; ++i) {
+        const float dl = q[i] - xk[i];
+        su = fmaxf(su, dl);
+        sl = fmaxf(sl, -dl);
+    }
+    ulb = fmaf(c.ms, su, c.ylo);
+    lub = fmaf(-c.ms, sl, c.yhi);
+}
+
 template <int D, int DM, int R>
 __device__ __forceinline__ void eval_group_l2f(const float (&v)[group_for_dim(D) * Rec<D>::S],
                                                const float (&q)[R][D], float big,
@@ -126,32 +158,17 @@ __device__ __forceinline__ void eval_group_l2f(const float (&v)[group_for_dim(D)
 {
     constexpr int S = Rec<D>::S;
     constexpr int kGroup = group_for_dim(D);
-    constexpr int DF = D - DM;
 #pragma unroll
     for (int g = 0; g < kGroup; ++g) {
         float xk[D];
 #pragma unroll
         for (int j = 0; j < D; ++j) xk[j] = v[g * S + j];
         const float yk = v[g * S + Rec<D>::Y], mk = v[g * S + Rec<D>::M];
-        // wave-uniform values, moved to scalar registers so that the rows
-        // share them without holding vector registers
-        const float ms = uniform_f32(mk * (1.0f - 0x1p-19f));
-        const float t = fmaxf(fmaxf(fabsf(yk) * 0x1p-23f, mk * 0x1p-58f), 0x1p-126f);
-        const float ylo = uniform_f32(yk - t), yhi = uniform_f32(yk + t);
+        const L2fRec c = l2f_record(yk, mk);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            float f = 0.0f;
-#pragma unroll
-            for (int i = 0; i < DF; ++i) f = fmaxf(f, fabsf(q[r][i] - xk[i]));
-            float su = f, sl = f;
-#pragma unroll
-            for (int i = DF; i < D; ++i) {
-                const float dl = q[r][i] - xk[i];
-                su = fmaxf(su, dl);
-                sl = fmaxf(sl, -dl);
-            }
-            const float ulb = fmaf(ms, su, ylo);
-            const float lub = fmaf(-ms, sl, yhi);
+            float ulb, lub;
+            l2f_bounds<D, DM>(q[r], xk, c, ulb, lub);
             if (__builtin_amdgcn_ballot_w64((ulb < hu[r]) | (lub > hl[r]))) {
                 float u, l;
                 pair_bounds<D, DM, kNormL2>(q[r], 0.0f, xk, yk, mk, yk, big, u, l);

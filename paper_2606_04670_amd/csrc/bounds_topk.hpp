@@ -13,7 +13,9 @@
 // some lane of the wave improves one of its two lists (a wave-uniform branch:
 // after the first data, few candidates improve any list; the number of
 // insertions per query grows like KL log(n / KL)).  The k values form a
-// multiset, so no index rule is needed; records past n (the staging's
+// multiset, so no index rule is needed; for l2 with monotone coordinates
+// the forward's root-free bounds skip the records that cannot enter a row's
+// lists (identical results); records past n (the staging's
 // padding repeats the last datum) are masked, so every datum counts once.
 // Split chunks write their sorted lists; a merge kernel takes the KL
 // smallest / largest of all of them.  Longer lists would leave too few
@@ -116,6 +118,29 @@ __global__ void __launch_bounds__(256) bounds_topk_kernel(TopkArgs A)
 #pragma unroll
             for (int j = 0; j < D; ++j) xk[j] = v[c * S + j];
             if (g0 + c >= c1) break;  // wave-uniform
+            if constexpr (NORM == kNormL2 && DM > 0) {
+                // l2 with monotone coordinates: the forward's root-free
+                // bounds first (ulb <= u, lub >= l); a record that cannot
+                // enter any lane's lists is skipped for the row
+                const L2fRec cr = l2f_record(v[c * S + Rec<D>::Y], v[c * S + Rec<D>::M]);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    float ulb, lub;
+                    l2f_bounds<D, DM>(qv[r], xk, cr, ulb, lub);
+                    if (__builtin_amdgcn_ballot_w64(ulb < U[r][KL - 1] || lub > L[r][KL - 1]) ==
+                        0)
+                        continue;
+                    float u, l;
+                    pair_bounds<D, DM, NORM>(qv[r], qm[r], xk, v[c * S + Rec<D>::Y],
+                                             v[c * S + Rec<D>::M], v[c * S + Rec<D>::YU], big, u,
+                                             l);
+                    if (__builtin_amdgcn_ballot_w64(u < U[r][KL - 1] || l > L[r][KL - 1]) != 0) {
+                        topk_insert_up<KL>(U[r], u);
+                        topk_insert_lo<KL>(L[r], l);
+                    }
+                }
+                continue;
+            }
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 float u, l;
