@@ -401,7 +401,8 @@ typedef struct {
  * candidates first (from the largest weighted component of each distance)
  * and form the exact candidates (two square roots) only for the rows of 64
  * queries where some query could improve.  Identical results; faster when
- * few data compete for each query (default on). */
+ * few data compete for each query (default on).  Without monotone
+ * coordinates the flag is accepted and has no effect. */
 #define LIP_TILE_L2_FILTER 1
 /* Visit the queries in Morton order (a sort of the queries' codes per call,
  * in the workspace): a wave's queries are then close to each other, so the

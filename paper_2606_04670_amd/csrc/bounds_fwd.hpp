@@ -91,8 +91,7 @@ __device__ __forceinline__ float uniform_f32(float v)
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
-// l2, filtered (with monotone coordinates, or without them: then both
-// distances are the symmetric one): the exact candidates need one or two
+// l2 with monotone coordinates, filtered: the exact candidates need two
 // square roots per pair (v_sqrt_f32 issues at a quarter of the VALU rate and
 // takes about half of the pair's time), but few records can change a row's
 // running bounds.  Each pair first gets root-free bounds of its candidates
@@ -179,15 +178,17 @@ __device__ __forceinline__ void eval_group_l2f(const float (&v)[group_for_dim(D)
     }
 }
 
-// One group of records for all R rows of a lane: filtered (l2, when the
-// launch asks for it) or plain.
+// One group of records for all R rows of a lane: filtered (l2 with monotone
+// coordinates, when the launch asks for it) or plain.  Without monotone
+// coordinates the filter is not compiled in: there it was slower than the
+// plain loop, and its branch alone cost the plain loop registers.
 template <int D, int DM, int NORM, int R>
 __device__ __forceinline__ void eval_group_rows(const FwdArgs &a,
                                                 const float (&v)[group_for_dim(D) * Rec<D>::S],
                                                 const float (&qv)[R][D], const float (&qm)[R],
                                                 float big, float (&hu)[R], float (&hl)[R])
 {
-    if constexpr (NORM == kNormL2) {
+    if constexpr (NORM == kNormL2 && DM > 0) {
         if (a.l2_filter) {
             eval_group_l2f<D, DM, R>(v, qv, big, hu, hl);
             return;

@@ -239,8 +239,7 @@ FILTER_CASES = [
     (8, [1, 0] * 4, False, False),
     (12, [0, 0, 1] * 4, True, True),
     (16, [1] * 16, False, False),
-    # no monotone coordinate: both distances symmetric (the filter is off by
-    # default there, but a caller may set it)
+    # no monotone coordinate: the flag is accepted and changes nothing
     (2, [0, 0], True, True),
     (8, [0] * 8, False, False),
 ]
