@@ -168,17 +168,18 @@ __device__ __forceinline__ void ds_step(double f, double w, double d, double &su
     }
 }
 
-// One pair, per-lane column k (vector loads): the same operation sequence as
-// the grouped loops below.  Without MON, sl = su.
-template <int D, int NORM, bool HASW, bool MON>
-__device__ __forceinline__ void ds_dist1(const DsArgs &A, const double (&xr)[D], int64_t k,
-                                         double &su, double &sl)
+// One pair, the column's staged values given by col(j) (j < D coordinates):
+// the same operation sequence as the grouped loops below.  Without MON,
+// sl = su.
+template <int D, int NORM, bool HASW, bool MON, class Col>
+__device__ __forceinline__ void ds_dist_col(const DsArgs &A, const double (&xr)[D], Col col,
+                                            double &su, double &sl)
 {
     su = 0.0;
     sl = 0.0;
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-        const double d = xr[i] - A.X[(int64_t)i * A.npad + k];
+        const double d = xr[i] - col(i);
         if (i == 0)
             ds_step<NORM, HASW, MON, true>(A.fsel[i], A.w[i], d, su, sl);
         else
@@ -189,6 +190,15 @@ __device__ __forceinline__ void ds_dist1(const DsArgs &A, const double (&xr)[D],
         if (MON) sl = sqrt(sl);
     }
     if (!MON) sl = su;
+}
+
+// One pair, column k read from the staged data (per-lane vector loads).
+template <int D, int NORM, bool HASW, bool MON>
+__device__ __forceinline__ void ds_dist1(const DsArgs &A, const double (&xr)[D], int64_t k,
+                                         double &su, double &sl)
+{
+    ds_dist_col<D, NORM, HASW, MON>(
+        A, xr, [&](int j) { return A.X[(int64_t)j * A.npad + k]; }, su, sl);
 }
 
 // Component step with the coordinate's kind known at compile time: a free
@@ -380,15 +390,25 @@ __device__ __forceinline__ void cons_group(const DsArgs &A, cdouble_ptr X, int64
         }
 }
 
+// Slacks of one pair (row values xr, yr; column values col(j): coordinates,
+// then y_k at j = D and M_k at j = D + 1).
+template <int D, int NORM, bool HASW, bool MON, class Col>
+__device__ __forceinline__ void cons_pair_col(const DsArgs &A, const double (&xr)[D], double yr,
+                                              Col col, double &tu, double &tl)
+{
+    double du, dl;
+    ds_dist_col<D, NORM, HASW, MON>(A, xr, col, du, dl);
+    const double yk = col(D), mk = col(D + 1);
+    tu = fma(mk, du, yk) - yr;
+    tl = yr - fma(-mk, dl, yk);
+}
+
 template <int D, int NORM, bool HASW, bool MON>
 __device__ __forceinline__ void cons_pair(const DsArgs &A, const double (&xr)[D], double yr,
                                           int64_t k, double &tu, double &tl)
 {
-    double du, dl;
-    ds_dist1<D, NORM, HASW, MON>(A, xr, k, du, dl);
-    const double yk = A.X[(int64_t)D * A.npad + k], mk = A.X[(int64_t)(D + 1) * A.npad + k];
-    tu = fma(mk, du, yk) - yr;
-    tl = yr - fma(-mk, dl, yk);
+    cons_pair_col<D, NORM, HASW, MON>(
+        A, xr, yr, [&](int j) { return A.X[(int64_t)j * A.npad + k]; }, tu, tl);
 }
 
 template <int D, int NORM, bool HASW, bool MON, int FM = -1>
@@ -890,8 +910,8 @@ __global__ void __launch_bounds__(256) knn_select_kernel(DsArgs A)
 //   t32 <= U + E (FP32)   : may lower the running minimum U, evaluated in
 //                            FP64 (strict improvement in column order keeps
 //                            the lowest index, as the partner requires).
-// Pairs that need FP64 are evaluated with cons_pair (the FP64 kernel's own
-// operation sequence).  A NaN t32 or an infinite E sends the pair to FP64.
+// Pairs that need FP64 are evaluated with cons_pair_col (the FP64 kernel's
+// own operation sequence, on the column's FP32 record widened).  A NaN t32 or an infinite E sends the pair to FP64.
 // Rows per lane of the FP32-filtered kernel: one.  The per-pair predicates of
 // every (row, column) of a group are held as lane masks in scalar registers
 // until the wave's FP64 branch; with more rows they overflow the scalar file
@@ -1113,8 +1133,14 @@ __global__ void __launch_bounds__(256) consistency32_kernel(DsArgs A)
                 double xd[D];
 #pragma unroll
                 for (int j = 0; j < D; ++j) xd[j] = (double)xr[r][j];
+                // the column's FP64 values are its FP32 record widened
+                // (both stagings hold the same FP32 numbers: the sign-flipped
+                // coordinates, y_k and M_k), so they come from the scalar
+                // registers of the group instead of a load of the FP64 copy
+                const float *xc = v + c * S;
                 double tu, tl;
-                cons_pair<D, NORM, HASW, MON>(A, xd, (double)yr[r], k, tu, tl);
+                cons_pair_col<D, NORM, HASW, MON>(
+                    A, xd, (double)yr[r], [&](int j) { return (double)xc[j]; }, tu, tl);
                 if ((au[c][r] & bit) && tu < -A.tol) ++xu;
                 if ((al[c][r] & bit) && tl < -A.tol) ++xl;
                 if ((eu[c][r] & bit) && tu < bu[r]) {
