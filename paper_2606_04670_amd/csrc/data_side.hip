@@ -73,24 +73,59 @@ __global__ void bbox_init_kernel(unsigned long long *bb, int d)
     }
 }
 
-__global__ void bbox_kernel(const double *X, int64_t n, int64_t npad, int d, unsigned long long *bb)
+// Workgroups of the small reductions over the rows (bounding boxes, the FP32
+// error bound, the worst pair): one per compute unit.
+constexpr int kReduceBlocks = 256;
+
+// Bounding box of the staged coordinates as order keys: per-thread minima
+// and maxima over a strided part of the rows, reduced in the workgroup
+// (shuffles, then LDS across its waves), one atomic per coordinate and side.
+__global__ void __launch_bounds__(256) bbox_kernel(const double *X, int64_t n, int64_t npad,
+                                                   int d, unsigned long long *bb)
 {
-    for (int j = 0; j < d; ++j) {
-        double lo = __builtin_inf(), hi = -__builtin_inf();
-        const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-        for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
-            const double v = X[(int64_t)j * npad + k];
-            lo = fmin(lo, v);
-            hi = fmax(hi, v);
+    __shared__ double slo[4][kMaxDim], shi[4][kMaxDim];
+    double lo[kMaxDim], hi[kMaxDim];
+#pragma unroll
+    for (int j = 0; j < kMaxDim; ++j) {
+        lo[j] = __builtin_inf();
+        hi[j] = -__builtin_inf();
+    }
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
+#pragma unroll
+        for (int j = 0; j < kMaxDim; ++j) {
+            if (j < d) {
+                const double v = X[(int64_t)j * npad + k];
+                lo[j] = fmin(lo[j], v);
+                hi[j] = fmax(hi[j], v);
+            }
         }
-        for (int off = 32; off > 0; off >>= 1) {
-            lo = fmin(lo, __shfl_xor(lo, off));
-            hi = fmax(hi, __shfl_xor(hi, off));
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < kMaxDim; ++j) {
+        if (j < d) {
+            double a = lo[j], b = hi[j];
+            for (int off = 32; off > 0; off >>= 1) {
+                a = fmin(a, __shfl_xor(a, off));
+                b = fmax(b, __shfl_xor(b, off));
+            }
+            if (lane == 0) {
+                slo[wv][j] = a;
+                shi[wv][j] = b;
+            }
         }
-        if ((threadIdx.x & 63) == 0) {
-            atomicMin(bb + j, f64_key(lo));
-            atomicMax(bb + kMaxDim + j, f64_key(hi));
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < d) {
+        const int j = threadIdx.x;
+        double a = __builtin_inf(), b = -__builtin_inf();
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+            a = fmin(a, slo[w][j]);
+            b = fmax(b, shi[w][j]);
         }
+        atomicMin(bb + j, f64_key(a));
+        atomicMax(bb + kMaxDim + j, f64_key(b));
     }
 }
 
@@ -140,23 +175,39 @@ __global__ void stage32_kernel(const float *x, const float *y, const float *Mk, 
 // bounding-box extent).  Data whose FP32 evaluation could overflow (extent
 // >= 2^60 or bounds >= 2^100), or non-finite values, give +inf, which sends
 // every pair to FP64.
-__global__ void __launch_bounds__(1024) cons_bound_kernel(const float *c32, int64_t n, int d,
-                                                           DsArgs A, double *E)
+//
+// Pass 1 (kReduceBlocks workgroups): max |y|, max M_k and the per-coordinate
+// minima and maxima, reduced in each workgroup and combined with atomics on
+// order keys in kb[2 + 2 kMaxDim] (max |y|, max M_k, minima, maxima; set up
+// by cons_bound_init_kernel).  Pass 2 (one thread) forms E.
+__global__ void cons_bound_init_kernel(unsigned long long *kb)
 {
-    __shared__ double red[3 + 2 * kMaxDim][32];
+    const int t = threadIdx.x;
+    if (t < 2 + 2 * kMaxDim) kb[t] = (t >= 2 && t < 2 + kMaxDim) ? ~0ull : 0ull;
+}
+
+__global__ void __launch_bounds__(256) cons_bound_kernel(const float *c32, int64_t n, int d,
+                                                         unsigned long long *kb)
+{
+    __shared__ double red[2 + 2 * kMaxDim][4];
     const int S = d + 2;
     double ymax = 0.0, mmax = 0.0, lo[kMaxDim], hi[kMaxDim];
+#pragma unroll
     for (int j = 0; j < kMaxDim; ++j) {
         lo[j] = __builtin_inf();
         hi[j] = -__builtin_inf();
     }
-    for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
         ymax = fmax(ymax, fabs((double)c32[k * S + d]));
         mmax = fmax(mmax, (double)c32[k * S + d + 1]);
-        for (int j = 0; j < d; ++j) {
-            const double v = c32[k * S + j];
-            lo[j] = fmin(lo[j], v);
-            hi[j] = fmax(hi[j], v);
+#pragma unroll
+        for (int j = 0; j < kMaxDim; ++j) {
+            if (j < d) {
+                const double v = c32[k * S + j];
+                lo[j] = fmin(lo[j], v);
+                hi[j] = fmax(hi[j], v);
+            }
         }
     }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -166,46 +217,63 @@ __global__ void __launch_bounds__(1024) cons_bound_kernel(const float *c32, int6
     };
     ymax = wmax(ymax);
     mmax = wmax(mmax);
-    for (int j = 0; j < d; ++j) {
-        lo[j] = -wmax(-lo[j]);
-        hi[j] = wmax(hi[j]);
+#pragma unroll
+    for (int j = 0; j < kMaxDim; ++j) {
+        if (j < d) {
+            lo[j] = -wmax(-lo[j]);
+            hi[j] = wmax(hi[j]);
+        }
     }
     if (lane == 0) {
         red[0][wv] = ymax;
         red[1][wv] = mmax;
-        for (int j = 0; j < d; ++j) {
-            red[3 + j][wv] = lo[j];
-            red[3 + kMaxDim + j][wv] = hi[j];
+#pragma unroll
+        for (int j = 0; j < kMaxDim; ++j) {
+            if (j < d) {
+                red[2 + j][wv] = lo[j];
+                red[2 + kMaxDim + j][wv] = hi[j];
+            }
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const int nw = (int)(blockDim.x >> 6);
-        double ym = 0.0, mm = 0.0, dist = 0.0;
+    const int nw = (int)(blockDim.x >> 6);
+    const int t = threadIdx.x;
+    if (t < 2) {
+        double m = 0.0;
+        for (int q = 0; q < nw; ++q) m = fmax(m, red[t][q]);
+        atomicMax(kb + t, f64_key(m));
+    } else if (t < 2 + d) {
+        const int j = t - 2;
+        double l = __builtin_inf(), h = -__builtin_inf();
         for (int q = 0; q < nw; ++q) {
-            ym = fmax(ym, red[0][q]);
-            mm = fmax(mm, red[1][q]);
+            l = fmin(l, red[2 + j][q]);
+            h = fmax(h, red[2 + kMaxDim + j][q]);
         }
-        for (int j = 0; j < d; ++j) {
-            double l = __builtin_inf(), h = -__builtin_inf();
-            for (int q = 0; q < nw; ++q) {
-                l = fmin(l, red[3 + j][q]);
-                h = fmax(h, red[3 + kMaxDim + j][q]);
-            }
-            const double span = A.w[j] * (h - l);
-            // l1: sum; l2: root of the sum of squares; linf: max
-            if (span > 0.0)
-                dist = A.norm == 1 ? dist + span : (A.norm == 2 ? dist + span * span : fmax(dist, span));
-        }
-        if (A.norm == 2) dist = sqrt(dist);
-        // relative part; the absolute part covers FP32 underflow of squared
-        // components (a distance error of at most 2^-72) and of the sums
-        double e = 0x1p-18 * (mm * dist + 2.0 * ym) + mm * 0x1p-60 + 0x1p-126;
-        // FP32 squares and bounds must stay finite: components below 2^60,
-        // bounds below 2^100; otherwise every pair goes to FP64
-        if (!(dist < 0x1p60) || !(mm * dist + ym < 0x1p100) || !(e < 0x1p100)) e = __builtin_inf();
-        E[0] = e;
+        atomicMin(kb + 2 + j, f64_key(l));
+        atomicMax(kb + 2 + kMaxDim + j, f64_key(h));
     }
+}
+
+__global__ void cons_bound_final_kernel(const unsigned long long *kb, int d, DsArgs A, double *E)
+{
+    if (threadIdx.x != 0) return;
+    const double ym = f64_unkey(kb[0]), mm = f64_unkey(kb[1]);
+    double dist = 0.0;
+    for (int j = 0; j < d; ++j) {
+        const double l = f64_unkey(kb[2 + j]), h = f64_unkey(kb[2 + kMaxDim + j]);
+        const double span = A.w[j] * (h - l);
+        // l1: sum; l2: root of the sum of squares; linf: max
+        if (span > 0.0)
+            dist = A.norm == 1 ? dist + span : (A.norm == 2 ? dist + span * span : fmax(dist, span));
+    }
+    if (A.norm == 2) dist = sqrt(dist);
+    // relative part; the absolute part covers FP32 underflow of squared
+    // components (a distance error of at most 2^-72) and of the sums
+    double e = 0x1p-18 * (mm * dist + 2.0 * ym) + mm * 0x1p-60 + 0x1p-126;
+    // FP32 squares and bounds must stay finite: components below 2^60,
+    // bounds below 2^100; otherwise every pair goes to FP64
+    if (!(dist < 0x1p60) || !(mm * dist + ym < 0x1p100) || !(e < 0x1p100)) e = __builtin_inf();
+    E[0] = e;
 }
 
 __global__ void zero_counts_kernel(unsigned long long *c)
@@ -239,55 +307,92 @@ __global__ void consistency_combine_kernel(DsArgs A)
 // Smallest slack over all rows and both bounds, with the pair attaining it:
 // (value, row i, partner k) compared lexicographically, so ties go to the
 // lowest i, then the lowest k.  No pair at all (n == 1): +inf and (-1, -1).
-// One workgroup of 1024 threads.
-__global__ void __launch_bounds__(1024) worst_slack_kernel(const double *su, const double *sl,
-                                                           const int32_t *pu, const int32_t *pl,
-                                                           int64_t n, double *worst,
-                                                           int64_t *pair)
+// Pass 1 (up to kReduceBlocks workgroups) writes one candidate per
+// workgroup, pass 2 (one workgroup) reduces them; the minimum of a total
+// order does not depend on how the rows are split.
+struct WorstRec {
+    double v;
+    long long i, k;
+};
+
+__device__ __forceinline__ bool worst_better(double v, long long i, long long k, double bv,
+                                             long long bi, long long bk)
 {
-    __shared__ double sv[1024];
-    __shared__ long long si[1024], sk[1024];
-    double bv = __builtin_inf();
-    long long bi = -1, bk = -1;
-    auto better = [](double v, long long i, long long k, double bv, long long bi, long long bk) {
-        if (k < 0) return false;
-        if (bk < 0) return true;
-        if (v != bv) return v < bv;
-        if (i != bi) return i < bi;
-        return k < bk;
-    };
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-        if (better(su[i], i, pu[i], bv, bi, bk)) {
-            bv = su[i];
-            bi = i;
-            bk = pu[i];
-        }
-        if (better(sl[i], i, pl[i], bv, bi, bk)) {
-            bv = sl[i];
-            bi = i;
-            bk = pl[i];
-        }
-    }
-    sv[threadIdx.x] = bv;
-    si[threadIdx.x] = bi;
-    sk[threadIdx.x] = bk;
+    if (k < 0) return false;
+    if (bk < 0) return true;
+    if (v != bv) return v < bv;
+    if (i != bi) return i < bi;
+    return k < bk;
+}
+
+// Workgroup reduction of (v, i, k) (256 threads); thread 0 gets the result.
+__device__ __forceinline__ void worst_block_reduce(double &bv, long long &bi, long long &bk)
+{
+    __shared__ double sv[256];
+    __shared__ long long si[256], sk[256];
+    const int t = threadIdx.x;
+    sv[t] = bv;
+    si[t] = bi;
+    sk[t] = bk;
     __syncthreads();
     for (int h = blockDim.x / 2; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) {
-            const int o = threadIdx.x + h;
-            if (better(sv[o], si[o], sk[o], sv[threadIdx.x], si[threadIdx.x], sk[threadIdx.x])) {
-                sv[threadIdx.x] = sv[o];
-                si[threadIdx.x] = si[o];
-                sk[threadIdx.x] = sk[o];
-            }
+        if (t < h && worst_better(sv[t + h], si[t + h], sk[t + h], sv[t], si[t], sk[t])) {
+            sv[t] = sv[t + h];
+            si[t] = si[t + h];
+            sk[t] = sk[t + h];
         }
         __syncthreads();
     }
+    bv = sv[0];
+    bi = si[0];
+    bk = sk[0];
+}
+
+__global__ void __launch_bounds__(256) worst_partial_kernel(const double *su, const double *sl,
+                                                            const int32_t *pu,
+                                                            const int32_t *pl, int64_t n,
+                                                            WorstRec *part)
+{
+    double bv = __builtin_inf();
+    long long bi = -1, bk = -1;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double vu = su[i], vl = sl[i];
+        const long long ku = pu[i], kl = pl[i];
+        if (worst_better(vu, i, ku, bv, bi, bk)) {
+            bv = vu;
+            bi = i;
+            bk = ku;
+        }
+        if (worst_better(vl, i, kl, bv, bi, bk)) {
+            bv = vl;
+            bi = i;
+            bk = kl;
+        }
+    }
+    worst_block_reduce(bv, bi, bk);
+    if (threadIdx.x == 0) part[blockIdx.x] = WorstRec{bv, bi, bk};
+}
+
+__global__ void __launch_bounds__(256) worst_final_kernel(const WorstRec *part, int n_part,
+                                                          double *worst, int64_t *pair)
+{
+    double bv = __builtin_inf();
+    long long bi = -1, bk = -1;
+    for (int b = threadIdx.x; b < n_part; b += blockDim.x) {
+        const WorstRec r = part[b];
+        if (worst_better(r.v, r.i, r.k, bv, bi, bk)) {
+            bv = r.v;
+            bi = r.i;
+            bk = r.k;
+        }
+    }
+    worst_block_reduce(bv, bi, bk);
     if (threadIdx.x == 0) {
-        if (worst) worst[0] = sk[0] >= 0 ? sv[0] : __builtin_inf();
+        if (worst) worst[0] = bk >= 0 ? bv : __builtin_inf();
         if (pair) {
-            pair[0] = sk[0] >= 0 ? si[0] : -1;
-            pair[1] = sk[0] >= 0 ? sk[0] : -1;
+            pair[0] = bk >= 0 ? bi : -1;
+            pair[1] = bk >= 0 ? bk : -1;
         }
     }
 }
@@ -393,6 +498,12 @@ __global__ void slope_reduce_kernel(DsArgs A, int64_t *pair)
 
 int64_t ds_npad(int64_t n) { return (n + kDsTile - 1) / kDsTile * kDsTile; }
 
+// Small fixed area of the consistency workspace: E at 0, the error bound's
+// order keys at 64, the worst-pair partials at 512.
+constexpr size_t kConsAuxKeys = 64, kConsAuxWorst = 512;
+constexpr size_t kConsAuxBytes = kConsAuxWorst + align_up(kReduceBlocks * sizeof(WorstRec), 256);
+static_assert(kConsAuxKeys + (2 + 2 * kMaxDim) * 8 <= kConsAuxWorst, "aux layout");
+
 size_t data_side_ws_bytes(int64_t n, int d)
 {
     const size_t staged = align_up((size_t)ds_npad(n) * (size_t)(d + 2) * 8, 256);
@@ -400,7 +511,7 @@ size_t data_side_ws_bytes(int64_t n, int d)
     if (cons_chunks(n, d, LIP_L2) > cc) cc = cons_chunks(n, d, LIP_L2);
     if (cc < kDsMaxChunks) cc = kDsMaxChunks;  // the slope pass uses up to kDsMaxChunks here
     const size_t cons = align_up((size_t)cc * (size_t)n * 24, 256) +
-                        align_up((size_t)ds_npad(n) * (size_t)(d + 2) * 4, 256) + 256 +
+                        align_up((size_t)ds_npad(n) * (size_t)(d + 2) * 4, 256) + kConsAuxBytes +
                         align_up((size_t)n * 24, 256);
     const size_t knn = align_up((size_t)n * 4, 256) + align_up((size_t)n * kKnnCap * 4, 256) +
                        align_up((size_t)sort_len(n) * 8, 256) + align_up((size_t)n * 8, 256) +
@@ -511,7 +622,9 @@ extern "C" lip_status lip_consistency(const lip_metric *metric, const float *x, 
     float *c32 = (float *)q;
     q += align_up((size_t)A.npad * (size_t)(mi.d + 2) * 4, 256);
     double *cE = (double *)q;
-    q += 256;
+    unsigned long long *cons_keys = (unsigned long long *)(q + kConsAuxKeys);
+    WorstRec *worst_part = (WorstRec *)(q + kConsAuxWorst);
+    q += kConsAuxBytes;
     A.c32 = c32;
     A.cE = cE;
     // the worst pair needs every row's slacks and partners: rows the caller
@@ -532,8 +645,13 @@ extern "C" lip_status lip_consistency(const lip_metric *metric, const float *x, 
         hipLaunchKernelGGL(stage32_kernel, dim3((unsigned)g32), dim3(256), 0, s, x, y, Mk, M, n,
                            A.npad, mi.d, sg, c32);
         A.norm = mi.norm;
-        hipLaunchKernelGGL(cons_bound_kernel, dim3(1), dim3(1024), 0, s, (const float *)c32, n,
-                           mi.d, A, cE);
+        int64_t gb = (n + 255) / 256;
+        if (gb > kReduceBlocks) gb = kReduceBlocks;
+        hipLaunchKernelGGL(cons_bound_init_kernel, dim3(1), dim3(64), 0, s, cons_keys);
+        hipLaunchKernelGGL(cons_bound_kernel, dim3((unsigned)gb), dim3(256), 0, s,
+                           (const float *)c32, n, mi.d, cons_keys);
+        hipLaunchKernelGGL(cons_bound_final_kernel, dim3(1), dim3(64), 0, s,
+                           (const unsigned long long *)cons_keys, mi.d, A, cE);
     }
     hipLaunchKernelGGL(zero_counts_kernel, dim3(1), dim3(64), 0, s, A.counts);
     (mi.dm > 0 ? L.consistency_mon : L.consistency)(A, dim3(grid_for_rows(n, rows, A.n_chunks)),
@@ -541,11 +659,16 @@ extern "C" lip_status lip_consistency(const lip_metric *metric, const float *x, 
     if (A.n_chunks > 1 && (A.slack_up || A.slack_lo || A.partner_up || A.partner_lo))
         hipLaunchKernelGGL(consistency_combine_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256),
                            0, s, A);
-    if (worst)
-        hipLaunchKernelGGL(worst_slack_kernel, dim3(1), dim3(1024), 0, s,
+    if (worst) {
+        int64_t gw = (n + 255) / 256;
+        if (gw > kReduceBlocks) gw = kReduceBlocks;
+        hipLaunchKernelGGL(worst_partial_kernel, dim3((unsigned)gw), dim3(256), 0, s,
                            (const double *)A.slack_up, (const double *)A.slack_lo,
                            (const int32_t *)A.partner_up, (const int32_t *)A.partner_lo, n,
-                           worst_slack, worst_pair);
+                           worst_part);
+        hipLaunchKernelGGL(worst_final_kernel, dim3(1), dim3(256), 0, s,
+                           (const WorstRec *)worst_part, (int)gw, worst_slack, worst_pair);
+    }
     return dev_status(hipGetLastError());
 }
 
@@ -608,7 +731,7 @@ extern "C" lip_status lip_estimate_M(const lip_metric *metric, const float *x, c
         A.x32 = x;
         // spatial order of the rows and the per-row threshold pass
         int64_t gb = (n + 255) / 256;
-        if (gb > 1024) gb = 1024;
+        if (gb > kReduceBlocks) gb = kReduceBlocks;
         hipLaunchKernelGGL(bbox_init_kernel, dim3(1), dim3(64), 0, s, bb, mi.d);
         hipLaunchKernelGGL(bbox_kernel, dim3((unsigned)gb), dim3(256), 0, s, A.X, n, A.npad, mi.d,
                            bb);

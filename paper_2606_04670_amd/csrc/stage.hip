@@ -51,22 +51,37 @@ struct OriginPerm {
     int32_t perm[kMaxDim];
 };
 
-__global__ void origin_final_kernel(const float *part, int n_part, int d, OriginPerm pm,
-                                    float *origin)
+// One workgroup: per coordinate, its threads take the partials in turn and
+// reduce them in LDS (minima and maxima do not depend on the order).
+__global__ void __launch_bounds__(256) origin_final_kernel(const float *part, int n_part, int d,
+                                                           OriginPerm pm, float *origin)
 {
-    const int j = threadIdx.x;
-    if (j >= kMaxDim) return;
-    if (j >= d) {
-        origin[j] = 0.0f;
-        return;
+    __shared__ float smin[256], smax[256];
+    const int t = threadIdx.x;
+    for (int j = 0; j < kMaxDim; ++j) {
+        if (j >= d) {
+            if (t == 0) origin[j] = 0.0f;
+            continue;
+        }
+        const int c = pm.perm[j];
+        float mn = __builtin_inff(), mx = -__builtin_inff();
+        for (int b = t; b < n_part; b += blockDim.x) {
+            mn = fminf(mn, part[((int64_t)b * kMaxDim + c) * 2]);
+            mx = fmaxf(mx, part[((int64_t)b * kMaxDim + c) * 2 + 1]);
+        }
+        smin[t] = mn;
+        smax[t] = mx;
+        __syncthreads();
+        for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+            if (t < h) {
+                smin[t] = fminf(smin[t], smin[t + h]);
+                smax[t] = fmaxf(smax[t], smax[t + h]);
+            }
+            __syncthreads();
+        }
+        if (t == 0) origin[j] = origin_of_range(smin[0], smax[0]);
+        __syncthreads();
     }
-    const int c = pm.perm[j];
-    float mn = __builtin_inff(), mx = -__builtin_inff();
-    for (int b = 0; b < n_part; ++b) {
-        mn = fminf(mn, part[((int64_t)b * kMaxDim + c) * 2]);
-        mx = fmaxf(mx, part[((int64_t)b * kMaxDim + c) * 2 + 1]);
-    }
-    origin[j] = origin_of_range(mn, mx);
 }
 
 // Stage the data set into records [x'_0..x'_{D-1} | y | M | yU] (see
@@ -195,7 +210,7 @@ hipError_t launch_origin(const float *x, int64_t n, int d, const int32_t *perm, 
     if (g > kOriginBlocks) g = kOriginBlocks;
     float *part = area + kMaxDim * 4;
     hipLaunchKernelGGL(origin_partial_kernel, dim3((unsigned)g), dim3(256), 0, s, x, n, d, part);
-    hipLaunchKernelGGL(origin_final_kernel, dim3(1), dim3(64), 0, s, (const float *)part, (int)g,
+    hipLaunchKernelGGL(origin_final_kernel, dim3(1), dim3(256), 0, s, (const float *)part, (int)g,
                        d, pm, area);
     return hipGetLastError();
 }
@@ -212,6 +227,8 @@ hipError_t launch_combine(const CombineArgs &a, hipStream_t s)
 // packed as (code << 32 | index); positions q..P-1 are padding (~0).  Used
 // by kernels whose waves do better on spatially close queries (the filtered
 // l2 forward, the step-function forward); results do not depend on it.
+constexpr int kBoxBlocks = 256;  // workgroups of the query bounding-box reduction
+
 __device__ inline unsigned int f32_key(float v)
 {
     const unsigned int b = __float_as_uint(v);
@@ -232,25 +249,57 @@ __global__ void qbox_init_kernel(unsigned int *bb, int d)
     }
 }
 
-__global__ void qbox_kernel(const float *xq, int64_t q, int d, unsigned int *bb)
+// Bounding box of the queries as order keys: every thread keeps the minimum
+// and maximum key of each coordinate over whole query rows (contiguous
+// loads), the workgroup reduces them (shuffles, then LDS across its waves)
+// and adds one atomic per coordinate and side.
+__global__ void __launch_bounds__(256) qbox_kernel(const float *xq, int64_t q, int d,
+                                                   unsigned int *bb)
 {
+    __shared__ unsigned int slo[4][kMaxDim], shi[4][kMaxDim];
+    unsigned int lo[kMaxDim], hi[kMaxDim];
+#pragma unroll
+    for (int j = 0; j < kMaxDim; ++j) {
+        lo[j] = ~0u;
+        hi[j] = 0u;
+    }
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int j = 0; j < d; ++j) {
-        unsigned int lo = ~0u, hi = 0u;
-        for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < q; k += stride) {
-            const unsigned int key = f32_key(xq[k * d + j]);
-            lo = key < lo ? key : lo;
-            hi = key > hi ? key : hi;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < q; k += stride) {
+#pragma unroll
+        for (int j = 0; j < kMaxDim; ++j) {
+            if (j < d) {
+                const unsigned int key = f32_key(xq[k * d + j]);
+                lo[j] = key < lo[j] ? key : lo[j];
+                hi[j] = key > hi[j] ? key : hi[j];
+            }
         }
-        for (int off = 32; off > 0; off >>= 1) {
-            const unsigned int a = __shfl_xor(lo, off), b = __shfl_xor(hi, off);
-            lo = a < lo ? a : lo;
-            hi = b > hi ? b : hi;
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < kMaxDim; ++j) {
+        if (j < d) {
+            unsigned int a = lo[j], b = hi[j];
+            for (int off = 32; off > 0; off >>= 1) {
+                const unsigned int c = __shfl_xor(a, off), e = __shfl_xor(b, off);
+                a = c < a ? c : a;
+                b = e > b ? e : b;
+            }
+            if (lane == 0) {
+                slo[wv][j] = a;
+                shi[wv][j] = b;
+            }
         }
-        if ((threadIdx.x & 63) == 0) {
-            atomicMin(bb + j, lo);
-            atomicMax(bb + kMaxDim + j, hi);
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < d) {
+        const int j = threadIdx.x;
+        unsigned int a = ~0u, b = 0u;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+            a = slo[w][j] < a ? slo[w][j] : a;
+            b = shi[w][j] > b ? shi[w][j] : b;
         }
+        atomicMin(bb + j, a);
+        atomicMax(bb + kMaxDim + j, b);
     }
 }
 
@@ -306,7 +355,7 @@ hipError_t launch_query_order(const float *xq, int64_t q, int d, unsigned int *b
 {
     hipLaunchKernelGGL(qbox_init_kernel, dim3(1), dim3(64), 0, s, bb, d);
     int64_t gq = (q + 255) / 256;
-    if (gq > 1024) gq = 1024;
+    if (gq > kBoxBlocks) gq = kBoxBlocks;
     if (gq < 1) gq = 1;
     hipLaunchKernelGGL(qbox_kernel, dim3((unsigned)gq), dim3(256), 0, s, xq, q, d, bb);
     int64_t gp = (P + 255) / 256;
