@@ -656,9 +656,17 @@ extern "C" lip_status lip_consistency(const lip_metric *metric, const float *x, 
     hipLaunchKernelGGL(zero_counts_kernel, dim3(1), dim3(64), 0, s, A.counts);
     (mi.dm > 0 ? L.consistency_mon : L.consistency)(A, dim3(grid_for_rows(n, rows, A.n_chunks)),
                                                     dim3(256), s);
-    if (A.n_chunks > 1 && (A.slack_up || A.slack_lo || A.partner_up || A.partner_lo))
+    const bool rows_out = A.slack_up || A.slack_lo || A.partner_up || A.partner_lo;
+    if (mi.norm != LIP_L2) {
+        // the FP64 kernel leaves per-chunk minima and tiles; the finish
+        // kernel combines them and finds the partners
+        if (rows_out)
+            (mi.dm > 0 ? L.cons_finish_mon : L.cons_finish)(A, dim3((unsigned)((n + 255) / 256)),
+                                                            dim3(256), s);
+    } else if (A.n_chunks > 1 && rows_out) {
         hipLaunchKernelGGL(consistency_combine_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256),
                            0, s, A);
+    }
     if (worst) {
         int64_t gw = (n + 255) / 256;
         if (gw > kReduceBlocks) gw = kReduceBlocks;

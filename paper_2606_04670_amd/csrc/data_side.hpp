@@ -30,7 +30,9 @@
 // Partners without per-pair index tracking: the column loop keeps running
 // minima only and notes, per tile of kDsTile columns, whether they strictly
 // improved; the last improving tile is re-scanned with the same arithmetic
-// to find the first attaining column.  Violation counts are wave-uniform:
+// to find the first attaining column (for the FP64 consistency kernel in a
+// separate pass over the rows, and only in the chunk that holds the
+// minimum).  Violation counts are wave-uniform:
 // ballot + popcount into scalar registers.
 #pragma once
 
@@ -471,43 +473,73 @@ __global__ void __launch_bounds__(256) consistency_kernel(DsArgs A)
             tl_t[r] = bl[r] < pl[r] ? t : tl_t[r];
         }
     }
-    // partners: first column of the last improving tile attaining the minimum
+    // per chunk and row: the smallest slacks and the last tile where they
+    // improved; consistency_finish_kernel finds the partners from them
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        int pu_i = -1, pl_i = -1;
-        const int64_t bu0 = w.c0 + (int64_t)(tu_t[r] < 0 ? 0 : tu_t[r]) * kDsTile;
-        const int64_t bl0 = w.c0 + (int64_t)(tl_t[r] < 0 ? 0 : tl_t[r]) * kDsTile;
-        for (int k = kDsTile - 1; k >= 0; --k) {
-            const int64_t ku = bu0 + k, kl = bl0 + k;
-            if (tu_t[r] >= 0 && ku < w.c1 && ku != ir[r]) {
-                double tu, tl;
-                cons_pair<D, NORM, HASW, MON>(A, xr[r], yr[r], ku, tu, tl);
-                if (tu == bu[r]) pu_i = (int)ku;
-            }
-            if (tl_t[r] >= 0 && kl < w.c1 && kl != ir[r]) {
-                double tu, tl;
-                cons_pair<D, NORM, HASW, MON>(A, xr[r], yr[r], kl, tu, tl);
-                if (tl == bl[r]) pl_i = (int)kl;
-            }
-        }
         if (!valid[r]) continue;
-        const int64_t i = ir[r];
-        if (A.n_chunks == 1) {
-            if (A.slack_up) A.slack_up[i] = bu[r];
-            if (A.slack_lo) A.slack_lo[i] = bl[r];
-            if (A.partner_up) A.partner_up[i] = pu_i;
-            if (A.partner_lo) A.partner_lo[i] = pl_i;
-        } else {
-            const int64_t o = (int64_t)w.chunk * A.n + i;
-            A.pv_up[o] = bu[r];
-            A.pv_lo[o] = bl[r];
-            A.pi_up[o] = pu_i;
-            A.pi_lo[o] = pl_i;
-        }
+        const int64_t o = (int64_t)w.chunk * A.n + ir[r];
+        A.pv_up[o] = bu[r];
+        A.pv_lo[o] = bl[r];
+        A.pi_up[o] = tu_t[r];
+        A.pi_lo[o] = tl_t[r];
     }
     if (lane == 0) {
         atomicAdd(A.counts, cu);
         atomicAdd(A.counts + 1, cl);
+    }
+}
+
+// Per row, after consistency_kernel: the smallest slack of each bound over
+// the chunks (the first chunk on ties, i.e. the lower columns) and its
+// partner, the first column of that chunk's last improving tile attaining
+// it, found with the column loop's arithmetic.  Only the winning chunk's
+// tile is re-scanned, in a kernel of its own where many rows keep the loads
+// in flight.  A tile starts below n at a multiple of kDsTile and npad is a
+// multiple of kDsTile, so all its columns are inside the staged
+// (zero-padded) data: they are evaluated unconditionally and the conditions
+// only decide which results count.
+template <int D, int NORM, bool HASW, bool MON>
+__global__ void __launch_bounds__(256) consistency_finish_kernel(DsArgs A)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    double xr[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) xr[j] = A.X[(int64_t)j * A.npad + i];
+    const double yr = A.X[(int64_t)D * A.npad + i];
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+        const double *pv = side ? A.pv_lo : A.pv_up;
+        const int32_t *pt = side ? A.pi_lo : A.pi_up;
+        double best = __builtin_inf();
+        int cb = -1, tb = -1;
+        for (int c = 0; c < A.n_chunks; ++c) {
+            const int64_t o = (int64_t)c * A.n + i;
+            const double v = pv[o];
+            if (v < best) {
+                best = v;
+                cb = c;
+                tb = pt[o];
+            }
+        }
+        int part = -1;
+        if (tb >= 0) {
+            const int64_t base = (int64_t)cb * A.chunk_cols + (int64_t)tb * kDsTile;
+            int64_t c1 = (int64_t)(cb + 1) * A.chunk_cols;
+            c1 = c1 < A.n ? c1 : A.n;
+#pragma unroll 4
+            for (int k = kDsTile - 1; k >= 0; --k) {
+                const int64_t col = base + k;
+                double tu, tl;
+                cons_pair<D, NORM, HASW, MON>(A, xr, yr, col, tu, tl);
+                if (((side ? tl : tu) == best) & (col < c1) & (col != i)) part = (int)col;
+            }
+        }
+        double *sv = side ? A.slack_lo : A.slack_up;
+        int32_t *sp = side ? A.partner_lo : A.partner_up;
+        if (sv) sv[i] = best;
+        if (sp) sp[i] = part;
     }
 }
 
@@ -1220,6 +1252,8 @@ typedef void (*DsLaunch)(const DsArgs &, dim3, dim3, hipStream_t);
 
 struct DsLaunchers {
     DsLaunch consistency, consistency_mon, slope, scan, select16, select32, tau16, tau32;
+    // slacks and partners after the FP64 consistency kernel (l1, linf)
+    DsLaunch cons_finish, cons_finish_mon;
 };
 
 // Dimensions up to which the consistency pass has one kernel per free /
@@ -1265,6 +1299,16 @@ DsLaunchers ds_launchers_for()
         else
             hipLaunchKernelGGL((consistency_kernel<D, NORM, HASW, true>), g, b, 0, s, a);
     };
+    if constexpr (NORM == 2) {
+        L.cons_finish = L.cons_finish_mon = nullptr;
+    } else {
+        L.cons_finish = [](const DsArgs &a, dim3 g, dim3 b, hipStream_t s) {
+            hipLaunchKernelGGL((consistency_finish_kernel<D, NORM, HASW, false>), g, b, 0, s, a);
+        };
+        L.cons_finish_mon = [](const DsArgs &a, dim3 g, dim3 b, hipStream_t s) {
+            hipLaunchKernelGGL((consistency_finish_kernel<D, NORM, HASW, true>), g, b, 0, s, a);
+        };
+    }
     L.slope = [](const DsArgs &a, dim3 g, dim3 b, hipStream_t s) {
         hipLaunchKernelGGL((slope_kernel<D, NORM, HASW>), g, b, 0, s, a);
     };
