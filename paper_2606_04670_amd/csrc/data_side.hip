@@ -661,8 +661,8 @@ extern "C" lip_status lip_consistency(const lip_metric *metric, const float *x, 
         // the FP64 kernel leaves per-chunk minima and tiles; the finish
         // kernel combines them and finds the partners
         if (rows_out)
-            (mi.dm > 0 ? L.cons_finish_mon : L.cons_finish)(A, dim3((unsigned)((n + 255) / 256)),
-                                                            dim3(256), s);
+            (mi.dm > 0 ? L.cons_finish_mon : L.cons_finish)(
+                A, dim3((unsigned)((2 * n + 255) / 256)), dim3(256), s);
     } else if (A.n_chunks > 1 && rows_out) {
         hipLaunchKernelGGL(consistency_combine_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256),
                            0, s, A);

@@ -499,48 +499,54 @@ __global__ void __launch_bounds__(256) consistency_kernel(DsArgs A)
 // multiple of kDsTile, so all its columns are inside the staged
 // (zero-padded) data: they are evaluated unconditionally and the conditions
 // only decide which results count.
+constexpr int kFinishChunks = 32;  // column chunks the finish pass reads (at most)
+
 template <int D, int NORM, bool HASW, bool MON>
 __global__ void __launch_bounds__(256) consistency_finish_kernel(DsArgs A)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // two threads per row, one per bound (more rows' loads in flight)
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = t >> 1;
+    const int side = (int)(t & 1);
     if (i >= A.n) return;
     double xr[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) xr[j] = A.X[(int64_t)j * A.npad + i];
     const double yr = A.X[(int64_t)D * A.npad + i];
+    const double *pv = side ? A.pv_lo : A.pv_up;
+    const int32_t *pt = side ? A.pi_lo : A.pi_up;
+    // all chunks' minima loaded before any is compared (independent loads)
+    double v[kFinishChunks];
 #pragma unroll
-    for (int side = 0; side < 2; ++side) {
-        const double *pv = side ? A.pv_lo : A.pv_up;
-        const int32_t *pt = side ? A.pi_lo : A.pi_up;
-        double best = __builtin_inf();
-        int cb = -1, tb = -1;
-        for (int c = 0; c < A.n_chunks; ++c) {
-            const int64_t o = (int64_t)c * A.n + i;
-            const double v = pv[o];
-            if (v < best) {
-                best = v;
-                cb = c;
-                tb = pt[o];
-            }
+    for (int c = 0; c < kFinishChunks; ++c)
+        v[c] = c < A.n_chunks ? pv[(int64_t)c * A.n + i] : __builtin_inf();
+    double best = __builtin_inf();
+    int cb = -1;
+#pragma unroll
+    for (int c = 0; c < kFinishChunks; ++c) {
+        if (v[c] < best) {
+            best = v[c];
+            cb = c;
         }
-        int part = -1;
-        if (tb >= 0) {
-            const int64_t base = (int64_t)cb * A.chunk_cols + (int64_t)tb * kDsTile;
-            int64_t c1 = (int64_t)(cb + 1) * A.chunk_cols;
-            c1 = c1 < A.n ? c1 : A.n;
-#pragma unroll 4
-            for (int k = kDsTile - 1; k >= 0; --k) {
-                const int64_t col = base + k;
-                double tu, tl;
-                cons_pair<D, NORM, HASW, MON>(A, xr, yr, col, tu, tl);
-                if (((side ? tl : tu) == best) & (col < c1) & (col != i)) part = (int)col;
-            }
-        }
-        double *sv = side ? A.slack_lo : A.slack_up;
-        int32_t *sp = side ? A.partner_lo : A.partner_up;
-        if (sv) sv[i] = best;
-        if (sp) sp[i] = part;
     }
+    const int tb = cb >= 0 ? pt[(int64_t)cb * A.n + i] : -1;
+    int part = -1;
+    if (tb >= 0) {
+        const int64_t base = (int64_t)cb * A.chunk_cols + (int64_t)tb * kDsTile;
+        int64_t c1 = (int64_t)(cb + 1) * A.chunk_cols;
+        c1 = c1 < A.n ? c1 : A.n;
+#pragma unroll 8
+        for (int k = kDsTile - 1; k >= 0; --k) {
+            const int64_t col = base + k;
+            double tu, tl;
+            cons_pair<D, NORM, HASW, MON>(A, xr, yr, col, tu, tl);
+            if (((side ? tl : tu) == best) & (col < c1) & (col != i)) part = (int)col;
+        }
+    }
+    double *sv = side ? A.slack_lo : A.slack_up;
+    int32_t *sp = side ? A.partner_lo : A.partner_up;
+    if (sv) sv[i] = best;
+    if (sp) sp[i] = part;
 }
 
 // ---- global M: max over i < k of |y_i - y_k| / dist ------------------------------
@@ -1361,6 +1367,7 @@ void choose_chunks(int64_t n, int rows_per_wave, int max_chunks, DsArgs *A,
 // Column chunks of the consistency passes: finer than the other passes' so
 // that the grid holds ~6 waves per SIMD slot and the last round is short.
 constexpr int kConsMaxChunks = 32;
+static_assert(kConsMaxChunks <= kFinishChunks, "the finish pass reads every chunk");
 constexpr int64_t kConsTargetWaves = 24576;
 int cons_chunks(int64_t n, int d, int norm);
 unsigned grid_for_rows(int64_t n, int rows_per_wave, int n_chunks);
