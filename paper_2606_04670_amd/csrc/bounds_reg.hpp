@@ -29,6 +29,7 @@
 // partials go through the bound path's combine.
 #pragma once
 
+#include "bounds_fwd.hpp"  // l2f_record: per-record constants of the root-free l2 filter
 #include "host_common.hpp"
 #include "lip_device.hpp"
 
@@ -104,6 +105,32 @@ __device__ __forceinline__ void reg_dist(const float (&q)[2 * D - DF], const flo
     tl = sl;
 }
 
+// l2: root-free bounds of one pair's candidates from the largest component
+// of each distance, as in the bound kernel's filter (the same argument
+// holds: the exact path squares exactly these components, sums
+// non-negative terms with monotone rounding and takes v_sqrt_f32 of the
+// sum, and its candidates are fma(M_k, dist, y_k)).  The components are all
+// non-negative: a and b have the sign of the coordinate difference, so one
+// of a and -b is >= 0.
+template <int D, int DF>
+__device__ __forceinline__ void reg_l2_root_free(const float (&q)[2 * D - DF], const float *xk,
+                                                 const L2fRec &c, float &ulb, float &lub)
+{
+    float f = 0.0f;
+#pragma unroll
+    for (int i = 0; i < DF; ++i) f = fmaxf(f, fabsf(q[i] - xk[i]));
+    float su = f, sl = f;
+#pragma unroll
+    for (int j = 0; j < D - DF; ++j) {
+        const int e = DF + 2 * j;
+        const float a = q[e] - xk[e], b = q[e + 1] - xk[e + 1];
+        su = fmaxf(su, fmaxf(a, -b));
+        sl = fmaxf(sl, fmaxf(b, -a));
+    }
+    ulb = fmaf(c.ms, su, c.ylo);
+    lub = fmaf(-c.ms, sl, c.yhi);
+}
+
 template <int D, int DF, int NORM>
 __global__ void __launch_bounds__(256) bounds_reg_kernel(RegArgs A)
 {
@@ -158,12 +185,29 @@ __global__ void __launch_bounds__(256) bounds_reg_kernel(RegArgs A)
             if (g0 + c >= c1) break;  // wave-uniform
             const float *xk = v + c * S;
             const float yk = xk[E], mk = xk[E + 1];
+            if constexpr (NORM == kNormL2) {
+                // exact distances (two square roots) only for the rows of 64
+                // queries where some lane could improve
+                const L2fRec rc = l2f_record(yk, mk);
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                float du, dl;
-                reg_dist<D, DF, NORM>(qv[r], xk, du, dl);
-                hu[r] = __builtin_amdgcn_fmed3f(hu[r], fmaf(mk, du, yk), nbig);
-                hl[r] = __builtin_amdgcn_fmed3f(hl[r], fmaf(-mk, dl, yk), big);
+                for (int r = 0; r < R; ++r) {
+                    float ulb, lub;
+                    reg_l2_root_free<D, DF>(qv[r], xk, rc, ulb, lub);
+                    if (__builtin_amdgcn_ballot_w64((ulb < hu[r]) | (lub > hl[r]))) {
+                        float du, dl;
+                        reg_dist<D, DF, NORM>(qv[r], xk, du, dl);
+                        hu[r] = __builtin_amdgcn_fmed3f(hu[r], fmaf(mk, du, yk), nbig);
+                        hl[r] = __builtin_amdgcn_fmed3f(hl[r], fmaf(-mk, dl, yk), big);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    float du, dl;
+                    reg_dist<D, DF, NORM>(qv[r], xk, du, dl);
+                    hu[r] = __builtin_amdgcn_fmed3f(hu[r], fmaf(mk, du, yk), nbig);
+                    hl[r] = __builtin_amdgcn_fmed3f(hl[r], fmaf(-mk, dl, yk), big);
+                }
             }
         }
         if (--left == 0 || g0 + G >= c1) {
